@@ -1,0 +1,328 @@
+"""Pins of the FP64 oracle against facts fixed by the mathematics and the paper.
+
+Each test ties one oracle step to something other than the oracle itself: a closed form, a
+dense direct solve, an exact identity of the continuous problem, brute-force symbolic
+differentiation, or an exactness property of the discretisation.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.sparse as sps
+import sympy as sp
+
+import kfbi_inputs as KI
+from oracle.geometry import LevelSet, frames, Grid, build_crossings
+from oracle.mac import MAC
+from oracle.surface import jump_relations, fit_matrix
+from oracle.interp import stencil, weights
+from oracle.kfbi import Oracle
+
+
+# ------------------------------------------------------------------------------------------
+# Sine-transform Poisson solver: discrete eigenvectors (closed form)
+# ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("m", [0, 1, 2])
+def test_poisson_eigenvector(m):
+    N, mu = 8, 1.7
+    mac = MAC(N, -1.0, 1.0, 0, mu)
+    h = mac.h
+    modes = (3, 5, 2)
+    # sin(pi j a / N) on the integer axis (a = 1..N-1), sin(pi j (a+1/2)/N) on half axes
+    vecs, lam = [], 0.0
+    for d in range(3):
+        j = modes[d]
+        if d == m:
+            a = np.arange(N + 1)
+            v = np.sin(np.pi * j * a / N)
+        else:
+            a = np.arange(N)
+            v = np.sin(np.pi * j * (a + 0.5) / N)
+        vecs.append(v)
+        lam += 4.0 / h ** 2 * math.sin(j * math.pi / (2 * N)) ** 2
+    e = vecs[0][:, None, None] * vecs[1][None, :, None] * vecs[2][None, None, :]
+    # e is an eigenvector of -Delta_h with the ghost/Dirichlet rules of the scheme
+    assert np.allclose(-mac.lap(e, m), lam * e, atol=1e-9 * lam)
+    x = mac.poisson(e, m)
+    assert np.allclose(x, e / (mu * lam), atol=1e-14)
+
+
+def test_mac_gradient_is_minus_divergence_transpose():
+    N = 4
+    mac = MAC(N, 0.0, 1.0, 0, 1.0)
+    idx, pidx, n = mac.unknown_index()
+    nu = n - N ** 3
+    Gm = np.zeros((nu, N ** 3))
+    for c in range(N ** 3):
+        p = np.zeros(N ** 3)
+        p[c] = 1
+        g = mac.G(p.reshape((N,) * 3))
+        for m in range(3):
+            Gm[idx[m][idx[m] >= 0], c] = g[m][idx[m] >= 0]
+    Dm = np.zeros((N ** 3, nu))
+    for c in range(nu):
+        u = mac.zeros_u()
+        for m in range(3):
+            sel = idx[m] == c
+            u[m][sel] = 1.0
+        Dm[:, c] = mac.D(u).ravel()
+    assert np.array_equal(Dm, -Gm.T)
+    # D G = 7-point Laplacian with zero-flux box walls at cells
+    h = mac.h
+    L = Dm @ Gm
+    for c in range(N ** 3):
+        i, j, k = np.unravel_index(c, (N,) * 3)
+        nb = sum(1 for (a, b) in [(i, 0), (j, 0), (k, 0)] for s in (-1, 1) if 0 <= a + s < N)
+        assert abs(L[c, c] + nb / h ** 2) < 1e-9
+
+
+@pytest.mark.parametrize("pde", [0, 1])
+@pytest.mark.parametrize("N", [4, 6])
+def test_schur_cg_matches_dense_lu(pde, N):
+    rng = np.random.default_rng(N + 10 * pde)
+    mac = MAC(N, -1.0, 1.0, pde, 1.3, 7.0)
+    Fu = mac.zeros_u()
+    for m in range(3):
+        Fu[m][mac.interior(m)] = rng.standard_normal(Fu[m][mac.interior(m)].shape)
+    Fp = rng.standard_normal((N,) * 3)
+    u, p, _ = mac.solve(Fu, Fp)
+    ud, pd = mac.dense_solve(Fu, Fp)
+    for m in range(3):
+        assert np.abs(u[m] - ud[m]).max() < 1e-11
+    assert np.abs(p - pd).max() < 1e-11
+    # discrete divergence invariant: D u + c p = F_p (- mean for Stokes), momentum exact
+    ru, rp = mac.apply(u, p)
+    target = Fp - Fp.mean() if pde == 0 else Fp
+    assert np.abs(rp - target).max() < 1e-10
+    for m in range(3):
+        assert np.abs((ru[m] - Fu[m])[mac.interior(m)]).max() < 1e-9
+
+
+# ------------------------------------------------------------------------------------------
+# Jump relations: exact for analytic pairs (symbolic differentiation along the true surface)
+# ------------------------------------------------------------------------------------------
+def _rand_poly(rng, X, deg=3):
+    terms = [X[0] ** a * X[1] ** b * X[2] ** c for a in range(deg + 1) for b in range(deg + 1)
+             for c in range(deg + 1) if a + b + c <= deg]
+    return sum(sp.Rational(int(rng.integers(-9, 10)), int(rng.integers(1, 6))) * t for t in terms)
+
+
+@pytest.mark.parametrize("pde", [0, 1])
+def test_jump_relations_exact_on_analytic_pairs(pde):
+    rng = np.random.default_rng(7 + pde)
+    X = sp.symbols("x y z", real=True)
+    mu, lam = 1.4, 3.0
+    R, c = 0.6, np.array([0.1, -0.2, 0.05])
+
+    def field(rng):
+        if pde == 0:
+            A = [_rand_poly(rng, X) for _ in range(3)]
+            u = [sp.diff(A[2], X[1]) - sp.diff(A[1], X[2]), sp.diff(A[0], X[2]) - sp.diff(A[2], X[0]),
+                 sp.diff(A[1], X[0]) - sp.diff(A[0], X[1])]
+            p = _rand_poly(rng, X, 2)
+        else:
+            u = [_rand_poly(rng, X) for _ in range(3)]
+            p = -(lam + mu) * sum(sp.diff(u[i], X[i]) for i in range(3))
+        return u, p
+
+    up, pp = field(rng)
+    um, pm = field(rng)
+    ju = [up[i] - um[i] for i in range(3)]
+    jpres = pp - pm
+
+    def sigma(u, p):
+        gu = sp.Matrix(3, 3, lambda i, k: sp.diff(u[i], X[k]))
+        if pde == 0:
+            return -p * sp.eye(3) + mu * (gu + gu.T)
+        div = sum(sp.diff(u[i], X[i]) for i in range(3))
+        return lam * div * sp.eye(3) + mu * (gu + gu.T)
+
+    def force(u, p):
+        lapu = [sum(sp.diff(u[i], X[k], 2) for k in range(3)) for i in range(3)]
+        if pde == 0:
+            return [-mu * lapu[i] + sp.diff(p, X[i]) for i in range(3)]
+        div = sum(sp.diff(u[i], X[i]) for i in range(3))
+        return [-mu * lapu[i] - (lam + mu) * sp.diff(div, X[i]) for i in range(3)]
+
+    jsig = sigma(up, pp) - sigma(um, pm)
+    jf = [a - b for a, b in zip(force(up, pp), force(um, pm))]
+    ls = LevelSet(KI.sphere(R, tuple(c)))
+    dirs = rng.standard_normal((3, 3))
+    for d in dirs:
+        n0 = d / np.linalg.norm(d)
+        x0 = c + R * n0
+        n, t1, t2, kappa = frames(ls, x0[None])
+        assert np.allclose(kappa[0], -np.eye(2) / R, atol=1e-12)
+        # Monge patch of the sphere over the tangent plane at x0
+        xi = sp.symbols("a b", real=True)
+        nu = -R + sp.sqrt(R ** 2 - xi[0] ** 2 - xi[1] ** 2)
+        P = [x0[k] + xi[0] * t1[0, k] + xi[1] * t2[0, k] + nu * n[0, k] for k in range(3)]
+        sub = dict(zip(X, P))
+        at0 = {xi[0]: 0, xi[1]: 0}
+        Phi_s = [e.subs(sub) for e in ju]
+        Phi = np.array([float(e.subs(at0)) for e in Phi_s])
+        Phi_a = np.array([[float(sp.diff(e, xi[a]).subs(at0)) for e in Phi_s] for a in range(2)])
+        Phi_ab = np.array([[float(sp.diff(e, xi[a], xi[b]).subs(at0)) for e in Phi_s]
+                           for (a, b) in [(0, 0), (0, 1), (1, 1)]])
+        nvec = [(P[k] - c[k]) / R for k in range(3)]
+        Tvec = [sum(jsig[i, k].subs(sub) * nvec[k] for k in range(3)) for i in range(3)]
+        Tr = np.array([float(e.subs(at0)) for e in Tvec])
+        dTr = np.array([[float(sp.diff(e, xi[a]).subs(at0)) for e in Tvec] for a in range(2)])
+        pt = dict(zip(X, x0))
+        F = np.array([float(e.subs(pt)) for e in jf])
+        J0, Gu, H, jp, gp = jump_relations(pde, mu, lam, n, t1, t2, kappa, Phi[None], Phi_a[None],
+                                           Phi_ab[None], F[None], Tr[None], dTr[None])
+        Gu_ex = np.array([[float(sp.diff(ju[i], X[k]).subs(pt)) for k in range(3)] for i in range(3)])
+        H_ex = np.array([[[float(sp.diff(ju[i], X[k], X[l]).subs(pt)) for l in range(3)]
+                          for k in range(3)] for i in range(3)])
+        scale = max(1.0, np.abs(H_ex).max())
+        assert np.allclose(J0[0], [float(e.subs(pt)) for e in ju], atol=1e-12)
+        assert np.abs(Gu[0] - Gu_ex).max() < 1e-10 * scale
+        assert np.abs(H[0] - H_ex).max() < 1e-9 * scale
+        assert abs(jp[0] - float(jpres.subs(pt))) < 1e-10 * scale
+        gp_ex = np.array([float(sp.diff(jpres, X[k]).subs(pt)) for k in range(3)])
+        assert np.abs(gp[0] - gp_ex).max() < 1e-9 * scale
+
+
+# ------------------------------------------------------------------------------------------
+# Interpolation: exact for piecewise quadratics with exact jumps
+# ------------------------------------------------------------------------------------------
+def test_interpolation_exact_for_quadratics():
+    rng = np.random.default_rng(3)
+    N, lo, h = 16, -1.0, 2.0 / 16
+    for trial in range(20):
+        x = rng.uniform(-0.5, 0.5, 3)
+        m = trial % 3
+        nodes = stencil(x, m, N, lo, h)
+        w, z = weights(x, nodes, m, lo, h)
+        # interior quadratic q+, exterior q-; nodes marked "outside" at random
+        Qp, Qm = rng.standard_normal((3, 3)), rng.standard_normal((3, 3))
+        bp, bm = rng.standard_normal(3), rng.standard_normal(3)
+        cp, cm = rng.standard_normal(), rng.standard_normal()
+        qp = lambda y: cp + bp @ (y - x) + 0.5 * (y - x) @ (Qp + Qp.T) @ (y - x)
+        qm = lambda y: cm + bm @ (y - x) + 0.5 * (y - x) @ (Qm + Qm.T) @ (y - x)
+        outside = rng.random(10) < 0.5
+        vals = np.array([qm(zz) if o else qp(zz) for zz, o in zip(z, outside)])
+        # jump function: Taylor expansion of q+ - q- about x (exact for quadratics)
+        J = np.array([(qp(zz) - qm(zz)) for zz in z])
+        est = w @ (vals + np.where(outside, J, 0.0))
+        assert abs(est - cp) < 1e-12
+        assert abs(w.sum() - 1.0) < 1e-13
+
+
+# ------------------------------------------------------------------------------------------
+# Surface fit: value / first / second derivative errors shrink at the expected rates
+# ------------------------------------------------------------------------------------------
+def test_fit_convergence_rates_on_sphere():
+    R = 0.5
+    errs = []
+    for N in (16, 32):
+        cfg = KI.Config(N=N, shape=KI.sphere(R))
+        grid, ls = Grid(N, -1.0, 1.0), LevelSet(cfg.shape)
+        cr = build_crossings(grid, ls)
+        P, _ = fit_matrix(cr, grid.h)
+        g = lambda X: np.sin(2 * X[:, 0]) * np.cos(X[:, 1]) + X[:, 2] ** 2
+        vals = g(cr.xyz[cr.cp_target])
+        fit = (P @ vals).reshape(-1, 6)
+        # exact Monge-patch derivatives at each target by symbolic differentiation is costly;
+        # use a fine central difference of g along the exact sphere patch instead (error ~1e-8)
+        e = 1e-4
+        sel = np.arange(0, len(cr.fam), max(1, len(cr.fam) // 200))
+        d1 = d2 = 0.0
+        for t in sel:
+            x0, n, t1, t2 = cr.xyz[t], cr.normal[t], cr.t1[t], cr.t2[t]
+            c = x0 - R * n
+
+            def pt(a, b):
+                nu = -R + math.sqrt(R * R - a * a - b * b)
+                return (x0 + a * t1 + b * t2 + nu * n)[None]
+
+            f = lambda a, b: g(pt(a, b))[0]
+            ex1 = (f(e, 0) - f(-e, 0)) / (2 * e)
+            ex11 = (f(e, 0) - 2 * f(0, 0) + f(-e, 0)) / e ** 2
+            d1 = max(d1, abs(fit[t, 1] - ex1))
+            d2 = max(d2, abs(fit[t, 3] - ex11))
+        errs.append((d1, d2))
+    r1 = errs[0][0] / errs[1][0]
+    r2 = errs[0][1] / errs[1][1]
+    assert r1 > 2.5, errs      # O(h^2) first derivatives
+    assert r2 > 1.5, errs      # O(h) second derivatives
+
+
+# ------------------------------------------------------------------------------------------
+# The operator: exact identities of the continuous problem that the scheme keeps exactly
+# ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("name,N", [("sphere32", 16), ("ellip128", 24), ("star128", 32)])
+def test_K_of_constant_density_is_identity(name, N):
+    """A constant density c gives the interface solution u = c in Omega, 0 outside, p = 0;
+    every corrected MAC equation holds exactly and the interpolation reproduces constants,
+    so K c = c to rounding.  This pins the sign of every correction term."""
+    O = Oracle(KI.WORKLOADS[name].with_N(N))
+    c = np.array([0.3, -0.7, 1.1])
+    K = O.eval(np.tile(c, (O.n, 1)))
+    assert np.abs(K - c).max() < 1e-12
+
+
+def test_printed_case4_sign_breaks_constant_identity():
+    """Planting the printed '+' sign of the continuity correction (case 4) in the oracle
+    breaks K c = c: the identity is sensitive to that sign."""
+    O = Oracle(KI.WORKLOADS["sphere32"].with_N(16))
+    off = O.rhs_off
+    C = O.Cmat.tocsr(copy=True)
+    rows = np.repeat(np.arange(C.shape[0]), np.diff(C.indptr))
+    cont = rows >= off[3]
+    C.data[cont] *= -1.0
+    O.Cmat = C
+    c = np.array([0.3, -0.7, 1.1])
+    K = O.eval(np.tile(c, (O.n, 1)))
+    assert np.abs(K - c).max() > 1e-3
+
+
+def test_rigid_motion_density():
+    """phi = b + w x x is the trace of a rigid motion, which solves the double-layer
+    interface problem with u = phi inside and 0 outside, so K phi = phi + (fit error)."""
+    errs = []
+    for N in (16, 32):
+        O = Oracle(KI.WORKLOADS["sphere32"].with_N(N))
+        X = O.points
+        phi = np.array([0.2, -0.1, 0.4]) + np.cross(np.array([0.5, -0.3, 0.8]), X)
+        errs.append(np.abs(O.eval(phi) - phi).max())
+    assert errs[1] < errs[0] / 2.5, errs
+
+
+def test_adjoint_dot_product_and_columns():
+    O = Oracle(KI.WORKLOADS["sphere32"].with_N(16))
+    rng = np.random.default_rng(5)
+    x = rng.standard_normal((O.n, 3))
+    y = rng.standard_normal((O.n, 3))
+    lhs = np.vdot(O.eval(x), y)
+    rhs = np.vdot(x, O.eval_adjoint(y))
+    assert abs(lhs - rhs) < 1e-11 * (abs(lhs) + 1)
+    # explicit columns of K against rows of K^T
+    for j in rng.choice(3 * O.n, 4, replace=False):
+        e = np.zeros(3 * O.n)
+        e[j] = 1
+        col = O.eval(e.reshape(-1, 3)).ravel()
+        for i in rng.choice(3 * O.n, 4, replace=False):
+            f = np.zeros(3 * O.n)
+            f[i] = 1
+            row = O.eval_adjoint(f.reshape(-1, 3)).ravel()
+            assert abs(col[i] - row[j]) < 1e-12
+
+
+@pytest.mark.slow
+def test_bvp_second_order_on_sphere():
+    res = []
+    for N in (16, 32):
+        cfg = KI.WORKLOADS["sphere32"].with_N(N)
+        O = Oracle(cfg)
+        X = O.points
+        g = KI.exact_u(cfg.solution, X[:, 0], X[:, 1], X[:, 2])
+        f = lambda x, y, z: KI.body_force(cfg.solution, x, y, z, cfg.mu, cfg.lam)
+        phi, u, p, it, hist = O.solve_bvp(g, f, tol=1e-8)
+        e = O.errors(u, p, lambda x, y, z: KI.exact_u(cfg.solution, x, y, z),
+                     lambda x, y, z: KI.exact_p(cfg.solution, x, y, z))
+        res.append(e)
+        assert hist[-1] < 1e-8
+    for m in range(3):
+        assert res[0][f"u{m}_l2"] / res[1][f"u{m}_l2"] > 3.0, res
