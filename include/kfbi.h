@@ -1,0 +1,161 @@
+/*
+ * kfbi.h -- C ABI of libkfbi, an MI355X (gfx950) implementation of one evaluation of the
+ * kernel-free boundary integral (KFBI) operator for 3D Stokes and Navier (linear elasticity)
+ * Dirichlet problems on irregular domains, after Zhao, Dong and Ying, "Kernel free boundary
+ * integral method for 3D Stokes and Navier equations on irregular domains".
+ *
+ * Plain C: no C++ or torch types cross this boundary.  Every call returns a kfbi_status;
+ * on error the outputs are unspecified and kfbi_last_error() returns a message.  Nothing
+ * aborts or throws.
+ *
+ * Memory: the caller owns every buffer passed in.  Arguments named *_dev are device
+ * pointers (HIP device memory of the current device, float64, C-contiguous); *_host are
+ * host pointers.  The library owns only what its context holds (geometry, sparse maps and
+ * device workspaces), allocated in kfbi_create and released by kfbi_destroy.
+ *
+ * Ordering: work is issued on cfg.stream (a hipStream_t; NULL = the default stream) and
+ * every call returns after its work has completed (the CG and GMRES loops read scalars back
+ * to the host).  One context per thread/stream; contexts are independent.
+ *
+ * Grid layout of exported fields (numpy C order [i][j][k] <-> (x, y, z), box [lo,hi]^3,
+ * h = (hi-lo)/N): u1 has shape (N+1, N, N) with u1[i][j][k] the x-velocity at
+ * (lo + i h, lo + (j+1/2) h, lo + (k+1/2) h) (i = 0 and N are box faces, zero); u2, u3 are
+ * analogous; p has shape (N, N, N) at cell centres.  Packed u = u1 | u2 | u3.
+ */
+#ifndef KFBI_H
+#define KFBI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct kfbi_ctx kfbi_ctx; /* opaque */
+
+typedef enum {
+  KFBI_OK = 0,
+  KFBI_EINVAL = -1,  /* bad argument, non-finite input, unsupported size */
+  KFBI_ENOMEM = -2,  /* host or device allocation failed */
+  KFBI_EGEOM = -3,   /* geometry not resolved by the grid (too few fit neighbours, an
+                        interpolation stencil or a crossed arm touching the box boundary) */
+  KFBI_ENOCONV = -4, /* CG, refinement or GMRES did not reach its tolerance in maxit */
+  KFBI_EDEVICE = -5  /* a HIP runtime call failed */
+} kfbi_status;
+
+/* Problem (Sec. 2 of the paper): Stokes  -mu lap u + grad p = f, div u = 0;
+ * Navier  -mu lap u - (lambda+mu) grad div u = f, written in generalised Stokes form with
+ * p = -(lambda+mu) div u and div u + p/(lambda+mu) = 0 (Remark 3.1). */
+typedef enum { KFBI_STOKES = 0, KFBI_NAVIER = 1 } kfbi_pde;
+
+/* Arithmetic of the MAC solve.  FP64: everything in float64.  MIXED_FP32: transforms and
+ * inner Schur CG in float32 inside float64 residual refinement of the full MAC system;
+ * corrections, jumps, interpolation, residuals and all dot products stay float64. */
+typedef enum { KFBI_FP64 = 0, KFBI_MIXED_FP32 = 1 } kfbi_precision;
+
+typedef enum { KFBI_SPHERE = 0, KFBI_ELLIPSOID = 1, KFBI_STAR = 2, KFBI_TORUS = 3 } kfbi_shape_kind;
+
+/* Omega = {psi <= 0}.  param: sphere R | ellipsoid semi-axes a,b,c (body axes rotated by
+ * rot_z_deg about z) | star r0, eps, k, l with r = r0 + eps sin(k theta) cos(l phi),
+ * theta = arccos(z/|x|), phi = atan2(y,x) | torus tube radius a, centre-line radius c. */
+typedef struct {
+  kfbi_shape_kind kind;
+  double center[3];
+  double param[6];
+  double rot_z_deg;
+} kfbi_shape;
+
+typedef struct {
+  int32_t N;          /* cells per axis; power of two, 16 <= N <= 512 */
+  double lo, hi;      /* box [lo,hi]^3 */
+  kfbi_pde pde;
+  double mu, lambda;  /* lambda ignored for Stokes */
+  kfbi_shape shape;
+  kfbi_precision precision;
+  double cg_rtol;     /* relative tolerance of the MAC solve (Schur CG residual for FP64,
+                         full-system refinement residual for MIXED_FP32); <= 0: 1e-12 */
+  int32_t cg_maxit;   /* <= 0: 2000 */
+  double inner_rtol;  /* MIXED_FP32: tolerance of each float32 inner solve; <= 0: 1e-5 */
+  double gmres_rtol;  /* <= 0: 1e-8 */
+  int32_t gmres_maxit;/* <= 0: 200 */
+  void* stream;       /* hipStream_t; NULL = default stream */
+} kfbi_config;
+
+typedef struct {
+  int32_t cg_iters;        /* total Schur CG iterations of the last call */
+  int32_t refine_rounds;   /* MIXED_FP32 refinement rounds of the last MAC solve */
+  int32_t gmres_iters;
+  double final_rel_residual;
+  double ms_total;
+  double ms_stage[4];      /* jumps+corrections, MAC solve, interpolation, other */
+} kfbi_info;
+
+/* Host callback for body forces: fill out[i][3] with f at xyz[i][3], i < m. */
+typedef void (*kfbi_vec_fn)(const double* xyz, int64_t m, double* out, void* user);
+
+/* Builds the geometry and every sparse map (Algorithm 1 step 1): node classification,
+ * crossings of the surface with the nine grid-line families, control points, local frames,
+ * least-squares surface-fit weights, jump maps, correction arms and interpolation weights,
+ * and uploads them.  *out receives a new context (NULL on error). */
+kfbi_status kfbi_create(const kfbi_config* cfg, kfbi_ctx** out);
+void kfbi_destroy(kfbi_ctx* ctx);
+const char* kfbi_last_error(const kfbi_ctx* ctx);
+/* Message of the last kfbi_create failure in this thread (kfbi_create has no context). */
+const char* kfbi_create_error(void);
+
+/* Number n of control points; the density and K phi are n x 3. */
+kfbi_status kfbi_num_points(const kfbi_ctx* ctx, int64_t* n);
+/* Control points and outward unit normals, host arrays [n][3] (normal may be NULL). */
+kfbi_status kfbi_get_points(const kfbi_ctx* ctx, double* xyz_host, double* normal_host);
+/* Number of crossings (surface points where jumps are evaluated) and MAC unknowns. */
+kfbi_status kfbi_sizes(const kfbi_ctx* ctx, int64_t* n_crossings, int64_t* n_irregular);
+
+/* K phi = 1/2 phi - M phi (Prop. 4.2 / 4.4): the interior trace u+ at the control points of
+ * the double-layer interface problem  -mu lap u + grad p = 0, div u + c p = 0 off the
+ * surface, [[u]] = phi, [[sigma n]] = 0, u = 0 on the box.  phi_dev, out_dev: [n][3]
+ * float64 device arrays (may not alias).  info may be NULL. */
+kfbi_status kfbi_eval(kfbi_ctx* ctx, const double* phi_dev, double* out_dev, kfbi_info* info);
+
+/* Transpose of kfbi_eval: out = K^T w (same shapes). */
+kfbi_status kfbi_eval_adjoint(kfbi_ctx* ctx, const double* w_dev, double* out_dev, kfbi_info* info);
+
+/* Dirichlet BVP (Sec. 3, Algorithm 1 step 3): u = g at the control points, body force f
+ * (f == NULL: zero).  Volume trace b, GMRES (zero initial guess, unrestarted) on
+ * K phi = g - b to gmres_rtol, then the unified interface solve.  g_dev, phi_dev: [n][3]
+ * device; u_dev (packed u1|u2|u3 in the exported layout) and p_dev ([N][N][N]) are optional
+ * (NULL = not returned). */
+kfbi_status kfbi_solve_bvp(kfbi_ctx* ctx, const double* g_dev, kfbi_vec_fn f, void* f_user,
+                           double* phi_dev, double* u_dev, double* p_dev, kfbi_info* info);
+
+/* Grid velocity of the unified interface solve for density phi (and the body force of the
+ * last kfbi_solve_bvp with f != NULL if use_force != 0), exported layout. */
+kfbi_status kfbi_interface_solve(kfbi_ctx* ctx, const double* phi_dev, int32_t use_force,
+                                 double* u_dev, double* p_dev, kfbi_info* info);
+
+/* Measurement helper: launches the sine/cosine transform pass kernel of the context's MAC
+ * solver (kind 0 DCT-II, 1 DST-II, 2 DCT-III, 3 DST-III, 4 DST-I; axis 0..2; precision of
+ * the context's inner solver) reps times back to back on the context stream between two HIP
+ * events, on the solver's own work fields (contents are overwritten).  Returns the mean
+ * duration of one launch and the algorithmic HBM bytes of one launch (one read and one write
+ * of an N^3 field). */
+kfbi_status kfbi_time_pass(kfbi_ctx* ctx, int32_t kind, int32_t axis, int32_t reps, double* avg_ms,
+                           double* bytes_per_launch);
+
+/* Host-only setup (no device is touched): the same geometry and maps as kfbi_create, for
+ * inspection and testing on machines without a GPU. */
+typedef struct kfbi_plan kfbi_plan;
+kfbi_status kfbi_plan_create(const kfbi_config* cfg, kfbi_plan** out);
+void kfbi_plan_destroy(kfbi_plan* plan);
+/* Copies the named host array into out (if non-NULL) and returns its element count, or -1
+ * for an unknown name.  Names: xyz normal t1 t2 kappa (float64, per crossing), fam line1
+ * line2 (int32), cp_target (int64), nb_ptr (int64) nb_idx (int32) fitw (float64, 6 per
+ * neighbour entry), jmap (5x18 per crossing) jfmap (5x3) emap (3x18 per control point, then
+ * 3x3), irr_node irr_ptr (int64) arm_t (int32) arm_o (int8) arm_a (3 per arm), itp_idx
+ * (int64) itp_w (10 per control point and component), side0 side1 side2 sidep (uint8 N^3,
+ * face index 0..N-1 along the face normal). */
+int64_t kfbi_plan_get(const kfbi_plan* plan, const char* name, void* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* KFBI_H */

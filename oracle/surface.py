@@ -50,7 +50,9 @@ def fit_matrix(cr, h):
     tree = cKDTree(X)
     T = len(cr.fam)
     rows, cols, vals = [], [], []
-    radius = np.full(T, 2.5 * h)
+    # 2.5h plus a relative 1e-9 so that neighbours at exactly 2.5h (symmetric grids) are
+    # included whatever the rounding of the distance
+    radius = np.full(T, 2.5 * h + 1e-9 * h)
     nb = [None] * T
     pending = np.arange(T)
     while len(pending):

@@ -1,0 +1,906 @@
+// C ABI of libkfbi: context, device data, the operator evaluation pipeline, its transpose,
+// mixed-precision refinement and the GMRES boundary-value solve.
+//
+// One evaluation (Algorithm 1 step 2 of the paper):
+//   fit + jumps (per crossing)  ->  correction scatter into the MAC right-hand side
+//   ->  MAC solve (spectral Schur-complement CG, velocity back-substitution)
+//   ->  ten-node interpolation with the jump term  =  K phi.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <memory>
+#include <string>
+#include <type_traits>
+#include <vector>
+
+#include "../../include/kfbi.h"
+#include "kernels.h"
+#include "setup.h"
+#include "trig.h"
+
+using namespace kfbi;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct DevErr {
+  std::string msg;
+};
+
+#define HIPCHK(expr)                                                                                  \
+  do {                                                                                                \
+    hipError_t _e = (expr);                                                                           \
+    if (_e != hipSuccess)                                                                             \
+      throw DevErr{std::string(#expr) + ": " + hipGetErrorString(_e) + " (" + std::to_string(__LINE__) + ")"}; \
+  } while (0)
+
+template <typename T>
+T* dalloc(size_t n, std::vector<void*>& owned) {
+  void* p = nullptr;
+  if (n == 0) n = 1;
+  hipError_t e = hipMalloc(&p, n * sizeof(T));
+  if (e != hipSuccess) throw DevErr{"hipMalloc of " + std::to_string(n * sizeof(T)) + " bytes failed"};
+  owned.push_back(p);
+  return static_cast<T*>(p);
+}
+
+template <typename T>
+T* dupload(const std::vector<T>& v, std::vector<void*>& owned, hipStream_t s) {
+  T* p = dalloc<T>(v.size(), owned);
+  if (!v.empty()) HIPCHK(hipMemcpyAsync(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice, s));
+  return p;
+}
+
+// ---------------------------------------------------------------------------------------
+// spectral MAC solver in precision T
+// ---------------------------------------------------------------------------------------
+template <typename T>
+struct MacSolver {
+  int N = 0;
+  int64_t M = 0;
+  int pde = 0;
+  double mu = 1, c = 0;
+  hipStream_t s = nullptr;
+  DevTables<T> tb;
+  T *Fh[3] = {nullptr, nullptr, nullptr}, *b = nullptr, *x = nullptr, *r = nullptr, *d = nullptr, *q = nullptr;
+  T *A = nullptr, *B = nullptr, *A1 = nullptr, *B2 = nullptr, *B3 = nullptr, *tmp = nullptr;
+  double* partials = nullptr;
+  double* scal = nullptr;
+  double* host_rr = nullptr;  // pinned, 2 slots
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  int nparts_x = 0, nparts_u = 1024;
+
+  void init(int N_, double h, int pde_, double mu_, double c_, hipStream_t s_, std::vector<void*>& owned) {
+    N = N_;
+    M = (int64_t)N * N * N;
+    pde = pde_;
+    mu = mu_;
+    c = c_;
+    s = s_;
+    // tables (computed in float64, stored in T)
+    std::vector<T> tw(2 * N), tw2(4 * N), mk(2 * N), sc(N), isc(N);
+    for (int k = 0; k < N; ++k) {
+      tw[2 * k] = T(std::cos(2 * M_PI * k / N));
+      tw[2 * k + 1] = T(-std::sin(2 * M_PI * k / N));
+      mk[2 * k] = T(std::cos(M_PI * k / (2.0 * N)));
+      mk[2 * k + 1] = T(-std::sin(M_PI * k / (2.0 * N)));
+      double sk = (k == 0) ? std::sqrt(1.0 / N) : std::sqrt(2.0 / N);
+      sc[k] = T(sk);
+      isc[k] = T(1.0 / sk);
+    }
+    for (int k = 0; k < 2 * N; ++k) {
+      tw2[2 * k] = T(std::cos(2 * M_PI * k / (2.0 * N)));
+      tw2[2 * k + 1] = T(-std::sin(2 * M_PI * k / (2.0 * N)));
+    }
+    std::vector<double> sig(N), sig2s(N);
+    for (int k = 0; k < N; ++k) {
+      sig[k] = 2.0 / h * std::sin(M_PI * k / (2.0 * N));
+      double s1 = 2.0 / h * std::sin(M_PI * (k + 1) / (2.0 * N));
+      sig2s[k] = s1 * s1;
+    }
+    tb.tw = dupload(tw, owned, s);
+    tb.tw2 = dupload(tw2, owned, s);
+    tb.mk = dupload(mk, owned, s);
+    tb.sc = dupload(sc, owned, s);
+    tb.isc = dupload(isc, owned, s);
+    tb.sig = dupload(sig, owned, s);
+    tb.sig2s = dupload(sig2s, owned, s);
+    for (int m = 0; m < 3; ++m) Fh[m] = dalloc<T>(M, owned);
+    b = dalloc<T>(M, owned);
+    x = dalloc<T>(M, owned);
+    r = dalloc<T>(M, owned);
+    d = dalloc<T>(M, owned);
+    q = dalloc<T>(M, owned);
+    A = dalloc<T>(M, owned);
+    B = dalloc<T>(M, owned);
+    A1 = dalloc<T>(M, owned);
+    B2 = dalloc<T>(M, owned);
+    B3 = dalloc<T>(M, owned);
+    tmp = dalloc<T>(M, owned);
+    nparts_x = xinv_blocks(N, sizeof(T));
+    partials = dalloc<double>(std::max(3 * nparts_x, nparts_u), owned);
+    scal = dalloc<double>(16, owned);
+    HIPCHK(hipHostMalloc((void**)&host_rr, 2 * sizeof(double), hipHostMallocDefault));
+    HIPCHK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
+  }
+  void release() {
+    if (host_rr) (void)hipHostFree(host_rr);
+    host_rr = nullptr;
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+    ev[0] = ev[1] = nullptr;
+  }
+
+  void pass(int kind, int axis, const T* in, T* out, bool acc = false) {
+    HIPCHK(launch_pass<T>(N, kind, axis, in, out, acc, tb, s));
+  }
+  void project_mean(T* v) {
+    if (pde != KFBI_STOKES) return;
+    HIPCHK(launch_sum_partials<T>(M, v, partials, nparts_u, s));
+    HIPCHK(launch_reduce(partials, nparts_u, 1, scal, R_SUM, 1, M, s));
+    HIPCHK(launch_add_scalar<T>(M, v, scal, 5, -1.0 / (double)M, s));
+  }
+
+  // S p for the CG direction d (q = S d); d = r + beta d_old is formed in the first pass
+  void cg_iteration() {
+    HIPCHK(launch_xfwd_cg<T>(N, r, d, A, scal, tb, s));
+    pass(DST2, 0, d, B);
+    pass(DST2, 1, A, A1);
+    pass(DCT2, 1, B, B2);
+    pass(DST2, 1, B, B3);
+    HIPCHK(launch_zmid<T>(N, A1, B2, B3, mu, tb, s));
+    pass(DST3, 1, A1, A1);
+    pass(DCT3, 1, B2, B);
+    pass(DST3, 1, B3, B, true);
+    pass(DCT3, 0, A1, q);
+    HIPCHK(launch_xinv_cg<T>(N, B, q, d, c, partials, tb, s));
+    HIPCHK(launch_reduce(partials, nparts_x, 3, scal, R_ALPHA, pde == KFBI_STOKES, M, s));
+    HIPCHK(launch_cg_update<T>(M, x, r, d, q, scal, partials, nparts_u, s));
+    HIPCHK(launch_reduce(partials, nparts_u, 1, scal, R_BETA, 0, M, s));
+  }
+
+  // Solve A_u u + G p = F_u, D u + c p = F_p (Stokes: D u = F_p - mean F_p, mean p = 0).
+  // Fu: 3 fields (internal layout, face 0 ignored), Fp: 1 field.  Returns CG iterations or
+  // -1 if maxit was reached.
+  int solve(const T* Fu, const T* Fp, T* u, T* p, double rtol, int maxit) {
+    // 1. spectral right-hand sides T_m F_m
+    for (int m = 0; m < 3; ++m) {
+      pass(m == 0 ? DST1 : DST2, 0, Fu + m * M, Fh[m]);
+      pass(m == 1 ? DST1 : DST2, 1, Fh[m], Fh[m]);
+      pass(m == 2 ? DST1 : DST2, 2, Fh[m], Fh[m]);
+    }
+    // 2. b = P(F_p - sum_m C_m^T [sigma/Lambda_m] T_m F_m)
+    HIPCHK(launch_fill<T>(M, b, T(0), s));
+    for (int m = 0; m < 3; ++m) {
+      HIPCHK(launch_zscale_inv<T>(N, m, W_RHS, Fh[m], tmp, mu, tb, s));
+      pass(m == 1 ? DCT3 : DST3, 1, tmp, tmp);
+      pass(m == 0 ? DCT3 : DST3, 0, tmp, b, true);
+    }
+    HIPCHK(launch_rhs_minus_t<T>(M, b, Fp, s));
+    project_mean(b);
+    // 3. CG on S x = b
+    HIPCHK(launch_fill<T>(M, x, T(0), s));
+    HIPCHK(launch_fill<T>(M, d, T(0), s));
+    HIPCHK(hipMemcpyAsync(r, b, M * sizeof(T), hipMemcpyDeviceToDevice, s));
+    HIPCHK(launch_dot_partials<T>(M, r, r, partials, nparts_u, s));
+    HIPCHK(launch_reduce(partials, nparts_u, 1, scal, R_INIT_RR, 0, M, s));
+    double rr0 = 0;
+    HIPCHK(hipMemcpyAsync(&host_rr[0], scal, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    rr0 = host_rr[0];
+    int it = 0;
+    bool conv = (rr0 == 0.0);
+    const double thr = rtol * rtol * rr0;
+    // one iteration of look-ahead: iteration k+1 is queued before the residual of k is read
+    while (!conv && it < maxit) {
+      cg_iteration();
+      HIPCHK(hipMemcpyAsync(&host_rr[it & 1], scal, sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipEventRecord(ev[it & 1], s));
+      ++it;
+      if (it >= 2) {
+        HIPCHK(hipEventSynchronize(ev[(it - 2) & 1]));
+        if (!(host_rr[(it - 2) & 1] > thr)) conv = true;
+        if (std::isnan(host_rr[(it - 2) & 1])) throw DevErr{"NaN in the Schur CG residual"};
+      }
+    }
+    HIPCHK(hipStreamSynchronize(s));
+    if (!conv && it > 0) {
+      double last = host_rr[(it - 1) & 1];
+      if (!(last > thr)) conv = true;
+    }
+    project_mean(x);
+    // 4. velocity back-substitution u_m = T_m^T [(T_m F_m + sigma C_m p) / Lambda_m]
+    for (int m = 0; m < 3; ++m) {
+      pass(m == 0 ? DCT2 : DST2, 0, x, tmp);
+      pass(m == 1 ? DCT2 : DST2, 1, tmp, tmp);
+      pass(m == 2 ? DCT2 : DST2, 2, tmp, tmp);
+      HIPCHK(launch_backsub_combine<T>(N, m, Fh[m], tmp, A, mu, tb, s));
+      pass(m == 2 ? DST1 : DST3, 2, A, A);
+      pass(m == 1 ? DST1 : DST3, 1, A, A);
+      pass(m == 0 ? DST1 : DST3, 0, A, u + m * M);
+    }
+    if (p) HIPCHK(hipMemcpyAsync(p, x, M * sizeof(T), hipMemcpyDeviceToDevice, s));
+    return conv ? it : -1;
+  }
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------
+// context
+// ---------------------------------------------------------------------------------------
+struct kfbi_plan {
+  kfbi_config cfg;
+  Setup S;
+};
+
+struct kfbi_ctx {
+  kfbi_config cfg;
+  Setup S;
+  std::string err;
+  hipStream_t s = nullptr;
+  std::vector<void*> owned;
+  int64_t M = 0;
+  // surface maps
+  int64_t *nb_ptr, *irr_node, *irr_ptr, *itp_idx, *cp_target, *cp_of, *uT_ptr, *uT_node, *cT_ptr, *cT_node;
+  int64_t *fT_ptr, *fT_entry;
+  int32_t *nb_idx, *arm_t, *uT_row, *fT_target;
+  int8_t *arm_o, *cT_slot;
+  double *fitw, *jmap, *jfmap, *emap, *efmap, *arm_a, *itp_w, *uT_w, *cT_a;
+  // work
+  double *jumps, *fitvals, *ejump, *F, *u, *p, *jbar, *fitbar;
+  int* flag;
+  // volume force of the last BVP
+  double* Fj = nullptr;
+  double* vol_val = nullptr;
+  int64_t* vol_idx = nullptr;
+  int64_t nvol = 0;
+  // solvers
+  MacSolver<double> s64;
+  MacSolver<float> s32;
+  bool mixed = false;
+  // mixed refinement fields (float64 and float32)
+  double *ru = nullptr, *Feff = nullptr;
+  float *r32 = nullptr, *x32 = nullptr;
+  double* rscal = nullptr;
+  double* rpart = nullptr;
+  // GMRES
+  double *V = nullptr, *H = nullptr, *gtmp = nullptr;
+  int gm_max = 0;
+  kfbi_info last;
+  ~kfbi_ctx() {
+    s64.release();
+    s32.release();
+    for (void* q : owned) (void)hipFree(q);
+    if (s && !cfg.stream) (void)hipStreamDestroy(s);
+  }
+};
+
+static kfbi_config normalized(const kfbi_config* c) {
+  kfbi_config r = *c;
+  if (r.cg_rtol <= 0) r.cg_rtol = 1e-12;
+  if (r.cg_maxit <= 0) r.cg_maxit = 2000;
+  if (r.inner_rtol <= 0) r.inner_rtol = 1e-5;
+  if (r.gmres_rtol <= 0) r.gmres_rtol = 1e-8;
+  if (r.gmres_maxit <= 0) r.gmres_maxit = 200;
+  return r;
+}
+
+static const char* validate(const kfbi_config* c) {
+  if (!c) return "null config";
+  int N = c->N;
+  if (N < 16 || N > 512 || (N & (N - 1))) return "N must be a power of two in [16, 512]";
+  if (!(c->hi > c->lo)) return "box must satisfy hi > lo";
+  if (!(c->mu > 0) || !std::isfinite(c->mu)) return "mu must be positive";
+  if (c->pde == KFBI_NAVIER && !(c->lambda + c->mu > 0)) return "lambda + mu must be positive";
+  if (c->pde != KFBI_STOKES && c->pde != KFBI_NAVIER) return "unknown pde";
+  if (c->precision != KFBI_FP64 && c->precision != KFBI_MIXED_FP32) return "unknown precision";
+  if (c->shape.kind < KFBI_SPHERE || c->shape.kind > KFBI_TORUS) return "unknown shape";
+  return nullptr;
+}
+
+static kfbi_status status_of_setup(const std::string& e) {
+  return e.rfind("GEOM:", 0) == 0 ? KFBI_EGEOM : KFBI_EINVAL;
+}
+
+extern "C" {
+
+kfbi_status kfbi_plan_create(const kfbi_config* cfg, kfbi_plan** out);
+void kfbi_plan_destroy(kfbi_plan* p);
+
+kfbi_status kfbi_create(const kfbi_config* cfg_in, kfbi_ctx** out) {
+  if (!out) return KFBI_EINVAL;
+  *out = nullptr;
+  if (const char* v = validate(cfg_in)) {
+    g_create_error = v;
+    return KFBI_EINVAL;
+  }
+  std::unique_ptr<kfbi_ctx> C(new kfbi_ctx());
+  C->cfg = normalized(cfg_in);
+  std::string e;
+  try {
+    e = build_setup(C->cfg, C->S);
+  } catch (const std::exception& ex) {
+    e = std::string("setup failed: ") + ex.what();
+  }
+  if (!e.empty()) {
+    g_create_error = e;
+    return status_of_setup(e);
+  }
+  try {
+    Setup& S = C->S;
+    if (C->cfg.stream)
+      C->s = (hipStream_t)C->cfg.stream;
+    else
+      HIPCHK(hipStreamCreate(&C->s));
+    hipStream_t s = C->s;
+    auto& o = C->owned;
+    C->M = S.M;
+    C->nb_ptr = dupload(S.nb_ptr, o, s);
+    C->nb_idx = dupload(S.nb_idx, o, s);
+    C->fitw = dupload(S.fitw, o, s);
+    C->jmap = dupload(S.jmap, o, s);
+    C->jfmap = dupload(S.jfmap, o, s);
+    std::vector<double> em(S.emap.begin(), S.emap.begin() + S.n * 54);
+    std::vector<double> efm(S.emap.begin() + S.n * 54, S.emap.end());
+    C->emap = dupload(em, o, s);
+    C->efmap = dupload(efm, o, s);
+    C->irr_node = dupload(S.irr_node, o, s);
+    C->irr_ptr = dupload(S.irr_ptr, o, s);
+    C->arm_t = dupload(S.arm_t, o, s);
+    C->arm_o = dupload(S.arm_o, o, s);
+    C->arm_a = dupload(S.arm_a, o, s);
+    C->itp_idx = dupload(S.itp_idx, o, s);
+    C->itp_w = dupload(S.itp_w, o, s);
+    C->cp_target = dupload(S.cp_target, o, s);
+    C->cp_of = dupload(S.cp_of, o, s);
+    C->uT_ptr = dupload(S.uT_ptr, o, s);
+    C->uT_node = dupload(S.uT_node, o, s);
+    C->uT_row = dupload(S.uT_row, o, s);
+    C->uT_w = dupload(S.uT_w, o, s);
+    C->cT_ptr = dupload(S.cT_ptr, o, s);
+    C->cT_node = dupload(S.cT_node, o, s);
+    C->cT_slot = dupload(S.cT_slot, o, s);
+    C->cT_a = dupload(S.cT_a, o, s);
+    C->fT_ptr = dupload(S.fT_ptr, o, s);
+    C->fT_entry = dupload(S.fT_entry, o, s);
+    C->fT_target = dupload(S.fT_target, o, s);
+    C->jumps = dalloc<double>(5 * S.T, o);
+    C->fitvals = dalloc<double>(18 * S.T, o);
+    C->ejump = dalloc<double>(3 * S.n, o);
+    C->jbar = dalloc<double>(5 * S.T, o);
+    C->fitbar = dalloc<double>(18 * S.T, o);
+    C->F = dalloc<double>(4 * S.M, o);
+    C->u = dalloc<double>(3 * S.M, o);
+    C->p = dalloc<double>(S.M, o);
+    C->flag = dalloc<int>(1, o);
+    const double c = (S.pde == KFBI_STOKES) ? 0.0 : 1.0 / (S.lam + S.mu);
+    C->mixed = (C->cfg.precision == KFBI_MIXED_FP32);
+    if (C->mixed) {
+      C->s32.init(S.N, S.h, S.pde, S.mu, c, s, o);
+      C->ru = dalloc<double>(4 * S.M, o);
+      C->Feff = dalloc<double>(4 * S.M, o);
+      C->r32 = dalloc<float>(4 * S.M, o);
+      C->x32 = dalloc<float>(4 * S.M, o);
+      C->rscal = dalloc<double>(16, o);
+      C->rpart = dalloc<double>(1024, o);
+    } else {
+      C->s64.init(S.N, S.h, S.pde, S.mu, c, s, o);
+    }
+    HIPCHK(hipStreamSynchronize(s));
+  } catch (const DevErr& de) {
+    g_create_error = de.msg;
+    return KFBI_EDEVICE;
+  }
+  *out = C.release();
+  return KFBI_OK;
+}
+
+void kfbi_destroy(kfbi_ctx* ctx) { delete ctx; }
+
+const char* kfbi_last_error(const kfbi_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+const char* kfbi_create_error(void) { return g_create_error.c_str(); }
+
+kfbi_status kfbi_num_points(const kfbi_ctx* ctx, int64_t* n) {
+  if (!ctx || !n) return KFBI_EINVAL;
+  *n = ctx->S.n;
+  return KFBI_OK;
+}
+
+kfbi_status kfbi_get_points(const kfbi_ctx* ctx, double* xyz, double* normal) {
+  if (!ctx || !xyz) return KFBI_EINVAL;
+  const Setup& S = ctx->S;
+  for (int64_t c = 0; c < S.n; ++c)
+    for (int d = 0; d < 3; ++d) {
+      xyz[3 * c + d] = S.xyz[3 * S.cp_target[c] + d];
+      if (normal) normal[3 * c + d] = S.nrm[3 * S.cp_target[c] + d];
+    }
+  return KFBI_OK;
+}
+
+kfbi_status kfbi_sizes(const kfbi_ctx* ctx, int64_t* n_crossings, int64_t* n_irregular) {
+  if (!ctx) return KFBI_EINVAL;
+  if (n_crossings) *n_crossings = ctx->S.T;
+  if (n_irregular) *n_irregular = (int64_t)ctx->S.irr_node.size();
+  return KFBI_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------------
+// pipeline
+// ---------------------------------------------------------------------------------------
+namespace {
+
+double now_ms() {
+  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
+}
+
+void check_finite(kfbi_ctx* C, const double* v, int64_t n) {
+  HIPCHK(hipMemsetAsync(C->flag, 0, sizeof(int), C->s));
+  HIPCHK(launch_check_finite(n, v, C->flag, C->s));
+  int f = 0;
+  HIPCHK(hipMemcpyAsync(&f, C->flag, sizeof(int), hipMemcpyDeviceToHost, C->s));
+  HIPCHK(hipStreamSynchronize(C->s));
+  if (f) throw std::invalid_argument("non-finite input");
+}
+
+// right-hand side F (4 fields) from the density (and the stored volume force)
+void assemble_rhs(kfbi_ctx* C, const double* phi, bool vol) {
+  const Setup& S = C->S;
+  hipStream_t s = C->s;
+  const double* Fj = (vol && C->Fj) ? C->Fj : nullptr;
+  HIPCHK(launch_fit_jump(S.T, C->nb_ptr, C->nb_idx, C->fitw, C->jmap, C->jfmap, Fj, phi, C->jumps, C->fitvals, s));
+  HIPCHK(launch_interp_jump(S.n, C->cp_target, C->fitvals, C->emap, C->efmap, Fj, C->ejump, s));
+  HIPCHK(launch_fill<double>(4 * S.M, C->F, 0.0, s));
+  HIPCHK(launch_correct((int64_t)S.irr_node.size(), C->irr_node, C->irr_ptr, C->arm_t, C->arm_o, C->arm_a, C->jumps,
+                        C->F, s));
+  if (vol && C->nvol) HIPCHK(launch_scatter_add(C->nvol, C->vol_idx, C->vol_val, C->F, s));
+}
+
+// float64 MAC solve of C->F into C->u, C->p (either directly or by mixed refinement)
+int mac_solve(kfbi_ctx* C, const double* F, double* u, double* p, kfbi_info* info) {
+  const Setup& S = C->S;
+  const int64_t M = S.M;
+  hipStream_t s = C->s;
+  if (!C->mixed) {
+    int it = C->s64.solve(F, F + 3 * M, u, p, C->cfg.cg_rtol, C->cfg.cg_maxit);
+    if (it < 0) throw std::runtime_error("ENOCONV: Schur CG reached cg_maxit");
+    if (info) {
+      info->cg_iters += it;
+      info->refine_rounds = 0;
+    }
+    return it;
+  }
+  // mixed: float32 inner solves inside float64 residual refinement of the full system
+  double* Fe = C->Feff;
+  HIPCHK(hipMemcpyAsync(Fe, F, 4 * M * sizeof(double), hipMemcpyDeviceToDevice, s));
+  const bool stokes = S.pde == KFBI_STOKES;
+  auto project = [&](double* v) {
+    if (!stokes) return;
+    HIPCHK(launch_sum_partials<double>(M, v, C->rpart, 1024, s));
+    HIPCHK(launch_reduce(C->rpart, 1024, 1, C->rscal, R_SUM, 1, M, s));
+    HIPCHK(launch_add_scalar<double>(M, v, C->rscal, 5, -1.0 / (double)M, s));
+  };
+  auto norm2 = [&](const double* v, int64_t n) {
+    HIPCHK(launch_dot_partials<double>(n, v, v, C->rpart, 1024, s));
+    HIPCHK(launch_reduce(C->rpart, 1024, 1, C->rscal, R_SUM, 0, n, s));
+    double h = 0;
+    HIPCHK(hipMemcpyAsync(&h, C->rscal + 5, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return std::sqrt(h);
+  };
+  project(Fe + 3 * M);
+  const double f0 = norm2(Fe, 4 * M);
+  HIPCHK(launch_fill<double>(3 * M, u, 0.0, s));
+  HIPCHK(launch_fill<double>(M, p, 0.0, s));
+  HIPCHK(hipMemcpyAsync(C->ru, Fe, 4 * M * sizeof(double), hipMemcpyDeviceToDevice, s));
+  const double c = stokes ? 0.0 : 1.0 / (S.lam + S.mu);
+  int total = 0, rounds = 0;
+  double rn = f0;
+  while (f0 > 0 && rn > C->cfg.cg_rtol * f0) {
+    if (rounds >= 30) throw std::runtime_error("ENOCONV: mixed refinement did not converge");
+    HIPCHK((launch_convert<float, double>(4 * M, C->r32, C->ru, s)));
+    int it = C->s32.solve(C->r32, C->r32 + 3 * M, C->x32, C->x32 + 3 * M, C->cfg.inner_rtol, C->cfg.cg_maxit);
+    if (it < 0) throw std::runtime_error("ENOCONV: inner float32 CG reached cg_maxit");
+    total += it;
+    HIPCHK(launch_add_into_f64<float>(3 * M, u, C->x32, s));
+    HIPCHK(launch_add_into_f64<float>(M, p, C->x32 + 3 * M, s));
+    HIPCHK(launch_mac_residual(S.N, S.h, S.mu, c, u, p, Fe, Fe + 3 * M, C->ru, C->ru + 3 * M, s));
+    project(C->ru + 3 * M);
+    rn = norm2(C->ru, 4 * M);
+    ++rounds;
+  }
+  if (stokes) project(p);
+  if (info) {
+    info->cg_iters += total;
+    info->refine_rounds = rounds;
+  }
+  return total;
+}
+
+void eval_impl(kfbi_ctx* C, const double* phi, double* out, bool vol, kfbi_info* info) {
+  const Setup& S = C->S;
+  hipStream_t s = C->s;
+  double t0 = now_ms();
+  assemble_rhs(C, phi, vol);
+  HIPCHK(hipStreamSynchronize(s));
+  double t1 = now_ms();
+  mac_solve(C, C->F, C->u, C->p, info);
+  HIPCHK(hipStreamSynchronize(s));
+  double t2 = now_ms();
+  HIPCHK(launch_interp(S.n, C->itp_idx, C->itp_w, C->u, C->ejump, out, s));
+  HIPCHK(hipStreamSynchronize(s));
+  double t3 = now_ms();
+  if (info) {
+    info->ms_stage[0] += t1 - t0;
+    info->ms_stage[1] += t2 - t1;
+    info->ms_stage[2] += t3 - t2;
+    info->ms_total += t3 - t0;
+  }
+}
+
+void adjoint_impl(kfbi_ctx* C, const double* w, double* out, kfbi_info* info) {
+  const Setup& S = C->S;
+  const int64_t M = S.M;
+  hipStream_t s = C->s;
+  double t0 = now_ms();
+  // u-bar = W^T w (F holds the solve's right-hand side (u-bar, 0))
+  HIPCHK(launch_fill<double>(4 * M, C->F, 0.0, s));
+  HIPCHK(launch_interp_T((int64_t)S.uT_node.size(), C->uT_ptr, C->uT_node, C->uT_row, C->uT_w, w, C->F, s));
+  // transpose of the MAC solve: (F_u-bar, F_p-bar) = (u', -p') with (u', p') = solve(u-bar, 0)
+  mac_solve(C, C->F, C->u, C->p, info);
+  HIPCHK(hipMemcpyAsync(C->F, C->u, 3 * M * sizeof(double), hipMemcpyDeviceToDevice, s));
+  HIPCHK(launch_axpby<double>(M, C->F + 3 * M, -1.0, C->p, 0.0, s));
+  // corrections^T, jump maps^T (plus the interpolation jump term), fit^T
+  HIPCHK(launch_correct_T(S.T, C->cT_ptr, C->cT_node, C->cT_slot, C->cT_a, C->F, C->jbar, s));
+  HIPCHK(launch_jump_T(S.T, C->cp_of, C->jmap, C->emap, C->jbar, w, C->fitbar, s));
+  HIPCHK(launch_fit_T(S.n, C->fT_ptr, C->fT_entry, C->fT_target, C->fitw, C->fitbar, out, s));
+  HIPCHK(hipStreamSynchronize(s));
+  if (info) info->ms_total += now_ms() - t0;
+}
+
+template <typename F>
+kfbi_status guarded(kfbi_ctx* C, F&& f) {
+  if (!C) return KFBI_EINVAL;
+  try {
+    f();
+    return KFBI_OK;
+  } catch (const DevErr& e) {
+    C->err = e.msg;
+    return KFBI_EDEVICE;
+  } catch (const std::invalid_argument& e) {
+    C->err = e.what();
+    return KFBI_EINVAL;
+  } catch (const std::runtime_error& e) {
+    C->err = e.what();
+    return std::string(e.what()).rfind("ENOCONV", 0) == 0 ? KFBI_ENOCONV : KFBI_EDEVICE;
+  } catch (const std::bad_alloc&) {
+    C->err = "host allocation failed";
+    return KFBI_ENOMEM;
+  }
+}
+
+// GMRES dot product into a device slot (float64, deterministic)
+void dev_dot(kfbi_ctx* C, const double* a, const double* b, int64_t n, double* slot) {
+  HIPCHK(launch_dot_partials<double>(n, a, b, C->rpart, 64, C->s));
+  HIPCHK(launch_reduce(C->rpart, 64, 1, C->rscal, R_SUM, 0, n, C->s, slot));
+}
+
+}  // namespace
+
+// GMRES device helpers (small kernels)
+__global__ void k_axpy_dev(int64_t n, double* y, const double* x, const double* a, double sign) {
+  const double av = sign * (*a);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] += av * x[i];
+}
+__global__ void k_scale_inv_norm(int64_t n, double* y, const double* nsq, double* hout) {
+  const double nv = sqrt(*nsq);
+  if (blockIdx.x == 0 && threadIdx.x == 0) *hout = nv;
+  const double f = (nv > 0) ? 1.0 / nv : 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] *= f;
+}
+
+namespace {
+
+// unrestarted GMRES (modified Gram-Schmidt, Givens rotations) on K phi = rhs, zero guess
+int gmres(kfbi_ctx* C, const double* rhs, double* phi, double tol, int maxit, double* relres, kfbi_info* info) {
+  const Setup& S = C->S;
+  const int64_t n3 = 3 * S.n;
+  hipStream_t s = C->s;
+  if (C->gm_max < maxit) {
+    C->V = dalloc<double>((size_t)(maxit + 1) * n3, C->owned);
+    C->H = dalloc<double>((size_t)(maxit + 2) * (maxit + 1) + 16, C->owned);
+    C->gm_max = maxit;
+  }
+  if (!C->rpart) C->rpart = dalloc<double>(1024, C->owned);
+  if (!C->rscal) C->rscal = dalloc<double>(16, C->owned);
+  const int LD = maxit + 2;  // column stride of H
+  double* scratch = C->rscal;  // scratch[5] = norm^2
+  HIPCHK(hipMemcpyAsync(C->V, rhs, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
+  dev_dot(C, C->V, C->V, n3, scratch + 5);
+  double beta2 = 0;
+  HIPCHK(hipMemcpyAsync(&beta2, scratch + 5, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const double beta = std::sqrt(beta2);
+  HIPCHK(launch_fill<double>(n3, phi, 0.0, s));
+  if (beta == 0) {
+    *relres = 0;
+    return 0;
+  }
+  hipLaunchKernelGGL(k_scale_inv_norm, dim3(64), dim3(256), 0, s, n3, C->V, scratch + 5, scratch + 6);
+  std::vector<double> Hh((size_t)LD * (maxit + 1), 0.0), cs(maxit + 1), sn(maxit + 1), g(maxit + 2, 0.0);
+  g[0] = beta;
+  int k = 0;
+  double res = 1.0;
+  for (k = 0; k < maxit; ++k) {
+    double* vk = C->V + (size_t)k * n3;
+    double* w = C->V + (size_t)(k + 1) * n3;
+    eval_impl(C, vk, w, false, info);
+    double* Hc = C->H + (size_t)k * LD;
+    for (int i = 0; i <= k; ++i) {
+      dev_dot(C, C->V + (size_t)i * n3, w, n3, Hc + i);
+      hipLaunchKernelGGL(k_axpy_dev, dim3(64), dim3(256), 0, s, n3, w, C->V + (size_t)i * n3, Hc + i, -1.0);
+    }
+    dev_dot(C, w, w, n3, scratch + 5);
+    hipLaunchKernelGGL(k_scale_inv_norm, dim3(64), dim3(256), 0, s, n3, w, scratch + 5, Hc + k + 1);
+    HIPCHK(hipGetLastError());
+    std::vector<double> col(k + 2);
+    HIPCHK(hipMemcpyAsync(col.data(), Hc, (k + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int i = 0; i < k; ++i) {
+      double a = col[i], b = col[i + 1];
+      col[i] = cs[i] * a + sn[i] * b;
+      col[i + 1] = -sn[i] * a + cs[i] * b;
+    }
+    double r = std::hypot(col[k], col[k + 1]);
+    cs[k] = col[k] / r;
+    sn[k] = col[k + 1] / r;
+    col[k] = r;
+    col[k + 1] = 0;
+    for (int i = 0; i <= k; ++i) Hh[(size_t)k * LD + i] = col[i];
+    g[k + 1] = -sn[k] * g[k];
+    g[k] = cs[k] * g[k];
+    res = std::fabs(g[k + 1]) / beta;
+    if (res < tol) {
+      ++k;
+      break;
+    }
+  }
+  const int m = std::min(k, maxit);
+  std::vector<double> y(m);
+  for (int i = m - 1; i >= 0; --i) {
+    double acc = g[i];
+    for (int j = i + 1; j < m; ++j) acc -= Hh[(size_t)j * LD + i] * y[j];
+    y[i] = acc / Hh[(size_t)i * LD + i];
+  }
+  for (int i = 0; i < m; ++i)
+    HIPCHK(launch_axpby<double>(n3, phi, y[i], C->V + (size_t)i * n3, 1.0, s));
+  HIPCHK(hipStreamSynchronize(s));
+  *relres = res;
+  if (info) {
+    info->gmres_iters = m;
+    info->final_rel_residual = res;
+  }
+  if (res >= tol) throw std::runtime_error("ENOCONV: GMRES reached gmres_maxit");
+  return m;
+}
+
+void set_volume_force(kfbi_ctx* C, kfbi_vec_fn f, void* user) {
+  Setup& S = C->S;
+  const int N = S.N;
+  hipStream_t s = C->s;
+  // nodes of T^1..T^3 inside Omega (interior faces only)
+  std::vector<double> xyz;
+  std::vector<int64_t> idx;
+  for (int m = 0; m < 3; ++m)
+    for (int i = 0; i < N; ++i)
+      for (int j = 0; j < N; ++j)
+        for (int k = 0; k < N; ++k) {
+          const int id[3] = {i, j, k};
+          if (id[m] == 0) continue;
+          const int64_t l = ((int64_t)i * N + j) * N + k;
+          if (!S.side[m][l]) continue;
+          for (int d = 0; d < 3; ++d) xyz.push_back(d == m ? S.lo + id[d] * S.h : S.lo + (id[d] + 0.5) * S.h);
+          idx.push_back((int64_t)m * S.M + l);
+        }
+  const int64_t nv = (int64_t)idx.size();
+  std::vector<double> fv(3 * nv), val(nv);
+  if (nv) f(xyz.data(), nv, fv.data(), user);
+  for (int64_t r = 0; r < nv; ++r) {
+    const int m = (int)(idx[r] / S.M);
+    val[r] = fv[3 * r + m];
+    if (!std::isfinite(val[r])) throw std::invalid_argument("non-finite body force");
+  }
+  std::vector<double> Fj(3 * S.T);
+  f(S.xyz.data(), S.T, Fj.data(), user);
+  if (!C->Fj) C->Fj = dalloc<double>(3 * S.T, C->owned);
+  HIPCHK(hipMemcpyAsync(C->Fj, Fj.data(), Fj.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  if (C->nvol < nv || !C->vol_idx) {
+    C->vol_idx = dalloc<int64_t>(std::max<int64_t>(nv, 1), C->owned);
+    C->vol_val = dalloc<double>(std::max<int64_t>(nv, 1), C->owned);
+  }
+  C->nvol = nv;
+  if (nv) {
+    HIPCHK(hipMemcpyAsync(C->vol_idx, idx.data(), nv * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(C->vol_val, val.data(), nv * sizeof(double), hipMemcpyHostToDevice, s));
+  }
+  HIPCHK(hipStreamSynchronize(s));
+}
+
+}  // namespace
+
+extern "C" {
+
+kfbi_status kfbi_eval(kfbi_ctx* C, const double* phi, double* out, kfbi_info* info) {
+  if (!C || !phi || !out) return KFBI_EINVAL;
+  if (info) std::memset(info, 0, sizeof(*info));
+  return guarded(C, [&] {
+    check_finite(C, phi, 3 * C->S.n);
+    eval_impl(C, phi, out, false, info);
+  });
+}
+
+kfbi_status kfbi_eval_adjoint(kfbi_ctx* C, const double* w, double* out, kfbi_info* info) {
+  if (!C || !w || !out) return KFBI_EINVAL;
+  if (info) std::memset(info, 0, sizeof(*info));
+  return guarded(C, [&] {
+    check_finite(C, w, 3 * C->S.n);
+    adjoint_impl(C, w, out, info);
+  });
+}
+
+kfbi_status kfbi_solve_bvp(kfbi_ctx* C, const double* g, kfbi_vec_fn f, void* user, double* phi, double* u_ext,
+                           double* p_ext, kfbi_info* info) {
+  if (!C || !g || !phi) return KFBI_EINVAL;
+  if (info) std::memset(info, 0, sizeof(*info));
+  return guarded(C, [&] {
+    const Setup& S = C->S;
+    const int64_t n3 = 3 * S.n;
+    check_finite(C, g, n3);
+    if (!C->gtmp) C->gtmp = dalloc<double>(n3, C->owned);
+    if (f) {
+      set_volume_force(C, f, user);
+      // b = trace of the volume problem (phi = 0)
+      HIPCHK(launch_fill<double>(n3, phi, 0.0, C->s));
+      eval_impl(C, phi, C->gtmp, true, info);
+      HIPCHK(launch_axpby<double>(n3, C->gtmp, 1.0, g, -1.0, C->s));  // g - b
+    } else {
+      C->nvol = 0;
+      HIPCHK(hipMemcpyAsync(C->gtmp, g, n3 * sizeof(double), hipMemcpyDeviceToDevice, C->s));
+    }
+    double rr = 0;
+    gmres(C, C->gtmp, phi, C->cfg.gmres_rtol, C->cfg.gmres_maxit, &rr, info);
+    if (u_ext || p_ext) {
+      assemble_rhs(C, phi, f != nullptr);
+      mac_solve(C, C->F, C->u, C->p, info);
+      if (u_ext) HIPCHK(launch_export_u(S.N, C->u, u_ext, C->s));
+      if (p_ext) HIPCHK(hipMemcpyAsync(p_ext, C->p, S.M * sizeof(double), hipMemcpyDeviceToDevice, C->s));
+      HIPCHK(hipStreamSynchronize(C->s));
+    }
+  });
+}
+
+kfbi_status kfbi_interface_solve(kfbi_ctx* C, const double* phi, int32_t use_force, double* u_ext, double* p_ext,
+                                 kfbi_info* info) {
+  if (!C || !phi) return KFBI_EINVAL;
+  if (info) std::memset(info, 0, sizeof(*info));
+  return guarded(C, [&] {
+    const Setup& S = C->S;
+    check_finite(C, phi, 3 * S.n);
+    assemble_rhs(C, phi, use_force != 0);
+    mac_solve(C, C->F, C->u, C->p, info);
+    if (u_ext) HIPCHK(launch_export_u(S.N, C->u, u_ext, C->s));
+    if (p_ext) HIPCHK(hipMemcpyAsync(p_ext, C->p, S.M * sizeof(double), hipMemcpyDeviceToDevice, C->s));
+    HIPCHK(hipStreamSynchronize(C->s));
+  });
+}
+
+kfbi_status kfbi_time_pass(kfbi_ctx* C, int32_t kind, int32_t axis, int32_t reps, double* avg_ms, double* bytes) {
+  if (!C || !avg_ms || kind < 0 || kind > 4 || axis < 0 || axis > 2 || reps <= 0) return KFBI_EINVAL;
+  return guarded(C, [&] {
+    hipEvent_t e0, e1;
+    HIPCHK(hipEventCreate(&e0));
+    HIPCHK(hipEventCreate(&e1));
+    auto run = [&](auto& sv) {
+      using T = std::remove_reference_t<decltype(*sv.A)>;
+      HIPCHK(launch_fill<T>(sv.M, sv.A, T(1), C->s));
+      sv.pass(kind, axis, sv.A, sv.B);  // warm-up
+      HIPCHK(hipEventRecord(e0, C->s));
+      for (int r = 0; r < reps; ++r) sv.pass(kind, axis, sv.A, sv.B);
+      HIPCHK(hipEventRecord(e1, C->s));
+      HIPCHK(hipEventSynchronize(e1));
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+      *avg_ms = ms / reps;
+      if (bytes) *bytes = 2.0 * (double)sv.M * sizeof(T);
+    };
+    if (C->mixed)
+      run(C->s32);
+    else
+      run(C->s64);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+  });
+}
+
+}  // extern "C"
+
+template <typename V>
+static int64_t copy_out(const V& v, void* out) {
+  if (out) std::memcpy(out, v.data(), v.size() * sizeof(v[0]));
+  return (int64_t)v.size();
+}
+
+extern "C" {
+
+// ---------------------------------------------------------------------------------------
+// host-only plan (setup without a device), used to inspect the geometry and maps
+// ---------------------------------------------------------------------------------------
+kfbi_status kfbi_plan_create(const kfbi_config* cfg, kfbi_plan** out) {
+  if (!out) return KFBI_EINVAL;
+  *out = nullptr;
+  if (const char* v = validate(cfg)) {
+    g_create_error = v;
+    return KFBI_EINVAL;
+  }
+  std::unique_ptr<kfbi_plan> P(new kfbi_plan());
+  P->cfg = normalized(cfg);
+  std::string e;
+  try {
+    e = build_setup(P->cfg, P->S);
+  } catch (const std::exception& ex) {
+    e = std::string("setup failed: ") + ex.what();
+  }
+  if (!e.empty()) {
+    g_create_error = e;
+    return status_of_setup(e);
+  }
+  *out = P.release();
+  return KFBI_OK;
+}
+
+void kfbi_plan_destroy(kfbi_plan* p) { delete p; }
+
+int64_t kfbi_plan_get(const kfbi_plan* p, const char* name, void* out) {
+  if (!p || !name) return -1;
+  const Setup& S = p->S;
+  std::string n(name);
+  if (n == "xyz") return copy_out(S.xyz, out);
+  if (n == "normal") return copy_out(S.nrm, out);
+  if (n == "t1") return copy_out(S.t1, out);
+  if (n == "t2") return copy_out(S.t2, out);
+  if (n == "kappa") return copy_out(S.kap, out);
+  if (n == "fam") return copy_out(S.fam, out);
+  if (n == "line1") return copy_out(S.l1, out);
+  if (n == "line2") return copy_out(S.l2, out);
+  if (n == "cp_target") return copy_out(S.cp_target, out);
+  if (n == "nb_ptr") return copy_out(S.nb_ptr, out);
+  if (n == "nb_idx") return copy_out(S.nb_idx, out);
+  if (n == "fitw") return copy_out(S.fitw, out);
+  if (n == "jmap") return copy_out(S.jmap, out);
+  if (n == "jfmap") return copy_out(S.jfmap, out);
+  if (n == "emap") return copy_out(S.emap, out);
+  if (n == "irr_node") return copy_out(S.irr_node, out);
+  if (n == "irr_ptr") return copy_out(S.irr_ptr, out);
+  if (n == "arm_t") return copy_out(S.arm_t, out);
+  if (n == "arm_o") return copy_out(S.arm_o, out);
+  if (n == "arm_a") return copy_out(S.arm_a, out);
+  if (n == "itp_idx") return copy_out(S.itp_idx, out);
+  if (n == "itp_w") return copy_out(S.itp_w, out);
+  if (n == "side0") return copy_out(S.side[0], out);
+  if (n == "side1") return copy_out(S.side[1], out);
+  if (n == "side2") return copy_out(S.side[2], out);
+  if (n == "sidep") return copy_out(S.side[3], out);
+  return -1;
+}
+
+}  // extern "C"

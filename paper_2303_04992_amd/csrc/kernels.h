@@ -1,0 +1,111 @@
+// Device kernels of the KFBI operator evaluation (launch wrappers).  All wrappers enqueue
+// on the given stream and return hipSuccess or the launch error.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace kfbi {
+
+template <typename T>
+struct SpecTab;  // device tables of one precision (defined in kernels.hip)
+
+// device tables for one precision and grid size
+template <typename T>
+struct DevTables {
+  void* tw = nullptr;   // C2<T>[N]
+  void* tw2 = nullptr;  // C2<T>[2N]
+  void* mk = nullptr;   // C2<T>[N]
+  T* sc = nullptr;      // [N]
+  T* isc = nullptr;     // [N]
+  double* sig = nullptr;   // sigma_k = (2/h) sin(pi k / 2N), k < N
+  double* sig2s = nullptr; // sigma_{k+1}^2, k < N
+};
+
+enum WeightKind { W_SCHUR = 0, W_RHS = 1 };
+
+// ---- transforms
+template <typename T>
+hipError_t launch_pass(int N, int kind, int axis, const T* in, T* out, bool accumulate, const DevTables<T>& tb,
+                       hipStream_t s);
+// z-pass: scale the (x, y, z)-spectral field by the weight of component m, then inverse z
+template <typename T>
+hipError_t launch_zscale_inv(int N, int m, int wkind, const T* in, T* out, double mu, const DevTables<T>& tb,
+                             hipStream_t s);
+// fused z-pass of the Schur operator for the three components (fwd z, weight, inverse z)
+template <typename T>
+hipError_t launch_zmid(int N, T* A1, T* B2, T* B3, double mu, const DevTables<T>& tb, hipStream_t s);
+// d = r + beta d_old (beta from scal[2]) and A = DCT-II_x(d)
+template <typename T>
+hipError_t launch_xfwd_cg(int N, const T* r, T* d, T* A, const double* scal, const DevTables<T>& tb,
+                          hipStream_t s);
+// q += DST-III_x(B) + c d; per-block partial sums of d.q, q, d
+template <typename T>
+hipError_t launch_xinv_cg(int N, const T* B, T* q, const T* d, double c, double* partials, const DevTables<T>& tb,
+                          hipStream_t s);
+int xinv_blocks(int N, int elem_size);
+// x += alpha d; r -= alpha (q - mq); partial sums of r.r
+template <typename T>
+hipError_t launch_cg_update(int64_t M, T* x, T* r, const T* d, const T* q, const double* scal, double* partials,
+                            int nblocks, hipStream_t s);
+// back-substitution combine in spectral space: G = (F + sigma_{i_m} P) / Lambda_m
+template <typename T>
+hipError_t launch_backsub_combine(int N, int m, const T* F, const T* P, T* G, double mu, const DevTables<T>& tb,
+                                  hipStream_t s);
+
+// ---- reductions (float64, deterministic)
+// scal layout: [0] rr, [1] alpha, [2] beta, [3] mean q, [4] rr0, [5] scratch sum, [6] aux
+enum ReduceOp { R_ALPHA = 0, R_BETA = 1, R_SUM = 2, R_INIT_RR = 3 };
+hipError_t launch_reduce(const double* partials, int nparts, int nper, double* scal, int op, int stokes,
+                         int64_t M, hipStream_t s, double* out = nullptr);  // R_SUM: *out (or scal[5])
+template <typename T>
+hipError_t launch_dot_partials(int64_t M, const T* a, const T* b, double* partials, int nblocks, hipStream_t s);
+template <typename T>
+hipError_t launch_sum_partials(int64_t M, const T* a, double* partials, int nblocks, hipStream_t s);
+template <typename T>
+hipError_t launch_add_scalar(int64_t M, T* a, const double* scal, int idx, double factor, hipStream_t s);
+
+// ---- elementwise
+template <typename T>
+hipError_t launch_fill(int64_t n, T* a, T v, hipStream_t s);
+template <typename T>
+hipError_t launch_axpby(int64_t n, T* y, double a, const T* x, double b, hipStream_t s);  // y = a x + b y
+template <typename TO, typename TI>
+hipError_t launch_convert(int64_t n, TO* out, const TI* in, hipStream_t s);
+template <typename TI>
+hipError_t launch_add_into_f64(int64_t n, double* out, const TI* in, hipStream_t s);  // out += in
+hipError_t launch_rhs_minus(int64_t M, double* b, const double* Fp, hipStream_t s);   // b = Fp - b
+template <typename T>
+hipError_t launch_rhs_minus_t(int64_t M, T* b, const T* Fp, hipStream_t s);
+
+// ---- full-system residual of the MAC scheme (float64)
+// r_u = F_u - (-mu lap u + G p), r_p = F_p - (D u + c p), internal layout
+hipError_t launch_mac_residual(int N, double h, double mu, double c, const double* u, const double* p,
+                               const double* Fu, const double* Fp, double* ru, double* rp, hipStream_t s);
+
+// ---- surface stages (float64)
+hipError_t launch_fit_jump(int64_t T, const int64_t* nb_ptr, const int32_t* nb_idx, const double* fitw,
+                           const double* jmap, const double* jfmap, const double* Fj, const double* phi,
+                           double* jumps, double* fitvals, hipStream_t s);
+hipError_t launch_interp_jump(int64_t n, const int64_t* cp_target, const double* fitvals, const double* emap,
+                              const double* efmap, const double* Fj, double* ejump, hipStream_t s);
+hipError_t launch_correct(int64_t nirr, const int64_t* irr_node, const int64_t* irr_ptr, const int32_t* arm_t,
+                          const int8_t* arm_o, const double* arm_a, const double* jumps, double* F, hipStream_t s);
+hipError_t launch_interp(int64_t n, const int64_t* idx, const double* w, const double* u, const double* ejump,
+                         double* out, hipStream_t s);
+// adjoint
+hipError_t launch_interp_T(int64_t nnode, const int64_t* ptr, const int64_t* node, const int32_t* row,
+                           const double* w, const double* wbar, double* ubar, hipStream_t s);
+hipError_t launch_correct_T(int64_t T, const int64_t* ptr, const int64_t* node, const int8_t* slot, const double* a,
+                            const double* Fbar, double* jbar, hipStream_t s);
+hipError_t launch_jump_T(int64_t T, const int64_t* cp_of, const double* jmap, const double* emap,
+                         const double* jbar, const double* wbar, double* fitbar, hipStream_t s);
+hipError_t launch_fit_T(int64_t n, const int64_t* ptr, const int64_t* entry, const int32_t* target,
+                        const double* fitw, const double* fitbar, double* phibar, hipStream_t s);
+// layout conversion between the exported (N+1)-face layout and the internal one
+hipError_t launch_export_u(int N, const double* u_int, double* u_ext, hipStream_t s);
+hipError_t launch_import_u(int N, const double* u_ext, double* u_int, hipStream_t s);
+hipError_t launch_scatter_add(int64_t n, const int64_t* idx, const double* v, double* F, hipStream_t s);
+hipError_t launch_check_finite(int64_t n, const double* a, int* flag, hipStream_t s);
+
+}  // namespace kfbi

@@ -1,0 +1,860 @@
+// Device kernels of the KFBI operator evaluation on gfx950.
+//
+// MAC solve (Sec. 4.2 items i-iii of the paper).  With A_u = -mu Delta_h on the face grid
+// T^m diagonalised by T_m = (DST-I along m) x (DST-II along the two other axes), and the
+// MAC gradient satisfying T_m G_m = -sigma_m C_m with C_m = (DCT-II along m) x (DST-II
+// elsewhere) and sigma_k = (2/h) sin(pi k / 2N), the Schur complement is
+//     S = G^T A_u^{-1} G + c I = sum_m C_m^T [sigma_{k_m}^2 / Lambda_m] C_m + c I,
+// so every CG iteration is three mixed sine/cosine transforms of the pressure, a diagonal
+// scaling and three inverse transforms (no separate gradient/divergence stencil passes).
+// The right-hand side is P(F_p - sum_m C_m^T [sigma/Lambda_m] T_m F_m) and the velocity
+// back-substitution u_m = T_m^T [(T_m F_m + sigma C_m p) / Lambda_m].
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "kernels.h"
+#include "trig.h"
+
+namespace kfbi {
+
+// ---------------------------------------------------------------------------------------
+// helpers
+// ---------------------------------------------------------------------------------------
+template <typename T>
+static Tab<T> tab_of(const DevTables<T>& d) {
+  Tab<T> t;
+  t.tw = reinterpret_cast<const C2<T>*>(d.tw);
+  t.tw2 = reinterpret_cast<const C2<T>*>(d.tw2);
+  t.mk = reinterpret_cast<const C2<T>*>(d.mk);
+  t.sc = d.sc;
+  t.isc = d.isc;
+  return t;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  return v;
+}
+
+// deterministic block sum of NT threads (4 wavefronts); result valid in thread 0
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  __syncthreads();
+  if (lane == 0) sh[wid] = v;
+  __syncthreads();
+  double r = 0;
+  if (threadIdx.x == 0)
+    for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r += sh[w];
+  return r;
+}
+
+template <typename T, int N>
+__device__ __forceinline__ void load_tile(T* lds, const T* __restrict__ g, int axis, const TileAddr& a) {
+  constexpr int W = TileShape<T, N>::W, RS = N + 1;
+  for (int e = threadIdx.x; e < W * N; e += NT) {
+    int p, n;
+    tile_elem<T, N>(axis, e, p, n);
+    lds[p * RS + n] = g[a.base + p * a.pstride + n * a.nstride];
+  }
+  __syncthreads();
+}
+
+// spectral weight of component m at spectral index (i, j, k) (internal index mapping: along
+// axis m index i is mode i of DCT-II/DST-I; along the other axes index i is mode i+1 of
+// DST-II); returns Lambda_m / mu and sigma_{i_m}
+__device__ __forceinline__ void lambda_of(int m, int i, int j, int k, const double* sig, const double* sig2s,
+                                          double& lam, double& sg) {
+  const int id[3] = {i, j, k};
+  lam = 0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) lam += (d == m) ? sig[id[d]] * sig[id[d]] : sig2s[id[d]];
+  sg = sig[id[m]];
+}
+
+// ---------------------------------------------------------------------------------------
+// generic transform pass: out (+)= transform_KIND(in) along axis
+// ---------------------------------------------------------------------------------------
+template <typename T, int N, int KIND, bool ACC>
+__global__ __launch_bounds__(NT) void k_pass(const T* __restrict__ in, T* __restrict__ out, int axis, Tab<T> tb) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* lds = reinterpret_cast<T*>(smem);
+  constexpr int W = TileShape<T, N>::W, RS = N + 1;
+  const TileAddr a = tile_addr<T, N>(axis, blockIdx.x);
+  load_tile<T, N>(lds, in, axis, a);
+  transform_tile<T, N, KIND>(lds, tb);
+  for (int e = threadIdx.x; e < W * N; e += NT) {
+    int p, n;
+    tile_elem<T, N>(axis, e, p, n);
+    const long gi = a.base + p * a.pstride + n * a.nstride;
+    if (ACC)
+      out[gi] += lds[p * RS + n];
+    else
+      out[gi] = lds[p * RS + n];
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// fused Schur z-pass: forward z, multiply by sigma_m^2 / Lambda_m, inverse z (per component)
+// ---------------------------------------------------------------------------------------
+template <typename T, int N, int KF, int KI>
+__device__ void zmid_body(T* lds, T* field, int m, double mu, const double* sig, const double* sig2s,
+                          const Tab<T>& tb) {
+  constexpr int W = TileShape<T, N>::W, RS = N + 1;
+  const TileAddr a = tile_addr<T, N>(2, blockIdx.x);
+  load_tile<T, N>(lds, field, 2, a);
+  transform_tile<T, N, KF>(lds, tb);
+  for (int e = threadIdx.x; e < W * N; e += NT) {
+    const int p = e / N, k = e - p * N;
+    const int q = blockIdx.x * W + p;
+    const int xi = q / N, yi = q - xi * N;
+    double lam, sg;
+    lambda_of(m, xi, yi, k, sig, sig2s, lam, sg);
+    lds[p * RS + k] *= T(sg * sg / (mu * lam));
+  }
+  __syncthreads();
+  transform_tile<T, N, KI>(lds, tb);
+  for (int e = threadIdx.x; e < W * N; e += NT) {
+    const int p = e / N, n = e - p * N;
+    field[a.base + p * N + n] = lds[p * RS + n];
+  }
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(NT) void k_zmid(T* A1, T* B2, T* B3, double mu, const double* sig,
+                                             const double* sig2s, Tab<T> tb) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* lds = reinterpret_cast<T*>(smem);
+  const int m = blockIdx.y;
+  if (m == 0)
+    zmid_body<T, N, DST2, DST3>(lds, A1, 0, mu, sig, sig2s, tb);
+  else if (m == 1)
+    zmid_body<T, N, DST2, DST3>(lds, B2, 1, mu, sig, sig2s, tb);
+  else
+    zmid_body<T, N, DCT2, DCT3>(lds, B3, 2, mu, sig, sig2s, tb);
+}
+
+// z-pass of the right-hand side: scale by sigma_m / Lambda_m, inverse z (KI)
+template <typename T, int N, int KI>
+__global__ __launch_bounds__(NT) void k_zscale_inv(const T* __restrict__ in, T* __restrict__ out, int m, double mu,
+                                                   const double* sig, const double* sig2s, Tab<T> tb) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* lds = reinterpret_cast<T*>(smem);
+  constexpr int W = TileShape<T, N>::W, RS = N + 1;
+  const TileAddr a = tile_addr<T, N>(2, blockIdx.x);
+  load_tile<T, N>(lds, in, 2, a);
+  for (int e = threadIdx.x; e < W * N; e += NT) {
+    const int p = e / N, k = e - p * N;
+    const int q = blockIdx.x * W + p;
+    const int xi = q / N, yi = q - xi * N;
+    double lam, sg;
+    lambda_of(m, xi, yi, k, sig, sig2s, lam, sg);
+    lds[p * RS + k] *= T(sg / (mu * lam));
+  }
+  __syncthreads();
+  transform_tile<T, N, KI>(lds, tb);
+  for (int e = threadIdx.x; e < W * N; e += NT) {
+    const int p = e / N, n = e - p * N;
+    out[a.base + p * N + n] = lds[p * RS + n];
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// CG x-passes with fused vector updates
+// ---------------------------------------------------------------------------------------
+template <typename T, int N>
+__global__ __launch_bounds__(NT) void k_xfwd_cg(const T* __restrict__ r, T* __restrict__ d, T* __restrict__ A,
+                                                const double* __restrict__ scal, Tab<T> tb) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* lds = reinterpret_cast<T*>(smem);
+  constexpr int W = TileShape<T, N>::W, RS = N + 1;
+  const T beta = T(scal[2]);
+  const TileAddr a = tile_addr<T, N>(0, blockIdx.x);
+  for (int e = threadIdx.x; e < W * N; e += NT) {
+    int p, n;
+    tile_elem<T, N>(0, e, p, n);
+    const long gi = a.base + p * a.pstride + n * a.nstride;
+    const T v = r[gi] + beta * d[gi];
+    d[gi] = v;
+    lds[p * RS + n] = v;
+  }
+  __syncthreads();
+  transform_tile<T, N, DCT2>(lds, tb);
+  for (int e = threadIdx.x; e < W * N; e += NT) {
+    int p, n;
+    tile_elem<T, N>(0, e, p, n);
+    A[a.base + p * a.pstride + n * a.nstride] = lds[p * RS + n];
+  }
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(NT) void k_xinv_cg(const T* __restrict__ B, T* __restrict__ q, const T* __restrict__ d,
+                                                double c, double* __restrict__ partials, Tab<T> tb) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double red[NT / 64];
+  T* lds = reinterpret_cast<T*>(smem);
+  constexpr int W = TileShape<T, N>::W, RS = N + 1;
+  const TileAddr a = tile_addr<T, N>(0, blockIdx.x);
+  load_tile<T, N>(lds, B, 0, a);
+  transform_tile<T, N, DST3>(lds, tb);
+  double sdq = 0, sq = 0, sd = 0;
+  for (int e = threadIdx.x; e < W * N; e += NT) {
+    int p, n;
+    tile_elem<T, N>(0, e, p, n);
+    const long gi = a.base + p * a.pstride + n * a.nstride;
+    const T dv = d[gi];
+    const T qv = q[gi] + lds[p * RS + n] + T(c) * dv;
+    q[gi] = qv;
+    sdq += (double)dv * (double)qv;
+    sq += (double)qv;
+    sd += (double)dv;
+  }
+  double t0 = block_sum(sdq, red);
+  double t1 = block_sum(sq, red);
+  double t2 = block_sum(sd, red);
+  if (threadIdx.x == 0) {
+    partials[3 * blockIdx.x + 0] = t0;
+    partials[3 * blockIdx.x + 1] = t1;
+    partials[3 * blockIdx.x + 2] = t2;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_cg_update(int64_t M, T* __restrict__ x, T* __restrict__ r,
+                                                  const T* __restrict__ d, const T* __restrict__ q,
+                                                  const double* __restrict__ scal, double* __restrict__ partials) {
+  __shared__ double red[NT / 64];
+  const T alpha = T(scal[1]), mq = T(scal[3]);
+  double s = 0;
+  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < M; i += (int64_t)gridDim.x * NT) {
+    x[i] += alpha * d[i];
+    const T rv = r[i] - alpha * (q[i] - mq);
+    r[i] = rv;
+    s += (double)rv * (double)rv;
+  }
+  double t = block_sum(s, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_dot_partials(int64_t M, const T* __restrict__ a, const T* __restrict__ b,
+                                                     double* __restrict__ partials) {
+  __shared__ double red[NT / 64];
+  double s = 0;
+  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < M; i += (int64_t)gridDim.x * NT)
+    s += (double)a[i] * (double)b[i];
+  double t = block_sum(s, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+template <typename T>
+__global__ __launch_bounds__(NT) void k_sum_partials(int64_t M, const T* __restrict__ a, double* __restrict__ partials) {
+  __shared__ double red[NT / 64];
+  double s = 0;
+  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < M; i += (int64_t)gridDim.x * NT) s += (double)a[i];
+  double t = block_sum(s, red);
+  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+__global__ __launch_bounds__(NT) void k_reduce(const double* __restrict__ partials, int nparts, int nper,
+                                               double* __restrict__ scal, int op, int stokes, int64_t M,
+                                               double* __restrict__ out) {
+  __shared__ double red[NT / 64];
+  double acc[3] = {0, 0, 0};
+  for (int i = threadIdx.x; i < nparts; i += NT)
+    for (int c = 0; c < nper; ++c) acc[c] += partials[(int64_t)i * nper + c];
+  double tot[3];
+  for (int c = 0; c < 3; ++c) tot[c] = block_sum(c < nper ? acc[c] : 0.0, red);
+  if (threadIdx.x == 0) {
+    if (op == R_ALPHA) {
+      const double mq = stokes ? tot[1] / (double)M : 0.0;
+      const double dq = tot[0] - mq * tot[2];
+      scal[1] = (dq != 0.0) ? scal[0] / dq : 0.0;
+      scal[3] = mq;
+    } else if (op == R_BETA) {
+      scal[2] = (scal[0] > 0.0) ? tot[0] / scal[0] : 0.0;
+      scal[0] = tot[0];
+    } else if (op == R_INIT_RR) {
+      scal[0] = tot[0];
+      scal[4] = tot[0];
+      scal[2] = 0.0;
+    } else {
+      if (out)
+        *out = tot[0];
+      else
+        scal[5] = tot[0];
+    }
+  }
+}
+
+template <typename T>
+__global__ void k_add_scalar(int64_t M, T* a, const double* scal, int idx, double factor) {
+  const T v = T(scal[idx] * factor);
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (int64_t)gridDim.x * blockDim.x)
+    a[i] += v;
+}
+
+template <typename T, int N>
+__global__ void k_backsub_combine(int m, const T* __restrict__ F, const T* __restrict__ P, T* __restrict__ G,
+                                  double mu, const double* sig, const double* sig2s) {
+  const int64_t M = (int64_t)N * N * N;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (int64_t)gridDim.x * blockDim.x) {
+    const int k = (int)(i % N), j = (int)((i / N) % N), xi = (int)(i / ((int64_t)N * N));
+    double lam, sg;
+    lambda_of(m, xi, j, k, sig, sig2s, lam, sg);
+    G[i] = T(((double)F[i] + sg * (double)P[i]) / (mu * lam));
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// elementwise
+// ---------------------------------------------------------------------------------------
+template <typename T>
+__global__ void k_fill(int64_t n, T* a, T v) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    a[i] = v;
+}
+template <typename T>
+__global__ void k_axpby(int64_t n, T* y, double a, const T* x, double b) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    y[i] = T(a * (double)x[i] + b * (double)y[i]);
+}
+template <typename TO, typename TI>
+__global__ void k_convert(int64_t n, TO* out, const TI* in) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = TO(in[i]);
+}
+template <typename TI>
+__global__ void k_add_into_f64(int64_t n, double* out, const TI* in) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] += (double)in[i];
+}
+template <typename T>
+__global__ void k_rhs_minus(int64_t n, T* b, const T* Fp) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    b[i] = Fp[i] - b[i];
+}
+
+// ---------------------------------------------------------------------------------------
+// full-system MAC residual (float64, internal layout)
+// ---------------------------------------------------------------------------------------
+__global__ void k_res_u(int N, int m, double h, double mu, const double* __restrict__ u, const double* __restrict__ p,
+                        const double* __restrict__ F, double* __restrict__ r) {
+  const int64_t M = (int64_t)N * N * N;
+  const double ih2 = 1.0 / (h * h), ih = 1.0 / h;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (int64_t)gridDim.x * blockDim.x) {
+    const int id[3] = {(int)(i / ((int64_t)N * N)), (int)((i / N) % N), (int)(i % N)};
+    const int64_t st[3] = {(int64_t)N * N, N, 1};
+    if (id[m] == 0) {
+      r[i] = 0.0;
+      continue;
+    }
+    const double c = u[i];
+    double lap = 0;
+    for (int d = 0; d < 3; ++d) {
+      double lo, hi;
+      if (d == m) {
+        lo = u[i - st[d]];                               // face a-1 (face 0 holds zero)
+        hi = (id[d] + 1 < N) ? u[i + st[d]] : 0.0;       // face N is the box face
+      } else {
+        lo = (id[d] > 0) ? u[i - st[d]] : -c;            // ghost reflection
+        hi = (id[d] + 1 < N) ? u[i + st[d]] : -c;
+      }
+      lap += (lo - 2.0 * c + hi) * ih2;
+    }
+    const double gp = (p[i] - p[i - st[m]]) * ih;        // cells a-1, a
+    r[i] = F[i] - (-mu * lap + gp);
+  }
+}
+
+__global__ void k_res_p(int N, double h, double cc, const double* __restrict__ u, const double* __restrict__ p,
+                        const double* __restrict__ F, double* __restrict__ r) {
+  const int64_t M = (int64_t)N * N * N;
+  const double ih = 1.0 / h;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (int64_t)gridDim.x * blockDim.x) {
+    const int id[3] = {(int)(i / ((int64_t)N * N)), (int)((i / N) % N), (int)(i % N)};
+    const int64_t st[3] = {(int64_t)N * N, N, 1};
+    double div = 0;
+    for (int m = 0; m < 3; ++m) {
+      const double* um = u + (int64_t)m * M;
+      const double hi = (id[m] + 1 < N) ? um[i + st[m]] : 0.0;
+      div += (hi - um[i]) * ih;
+    }
+    r[i] = F[i] - (div + cc * p[i]);
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// surface stages (float64)
+// ---------------------------------------------------------------------------------------
+__global__ void k_fit_jump(int64_t T, const int64_t* __restrict__ nb_ptr, const int32_t* __restrict__ nb_idx,
+                           const double* __restrict__ fitw, const double* __restrict__ jmap,
+                           const double* __restrict__ jfmap, const double* __restrict__ Fj,
+                           const double* __restrict__ phi, double* __restrict__ jumps, double* __restrict__ fitvals) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= T) return;
+  double fv[18];
+#pragma unroll
+  for (int c = 0; c < 18; ++c) fv[c] = 0.0;
+  for (int64_t e = nb_ptr[t]; e < nb_ptr[t + 1]; ++e) {
+    const int64_t cp = nb_idx[e];
+    const double p0 = phi[3 * cp], p1 = phi[3 * cp + 1], p2 = phi[3 * cp + 2];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) {
+      const double w = fitw[6 * e + q];
+      fv[3 * q] += w * p0;
+      fv[3 * q + 1] += w * p1;
+      fv[3 * q + 2] += w * p2;
+    }
+  }
+#pragma unroll
+  for (int c = 0; c < 18; ++c) fitvals[18 * t + c] = fv[c];
+  for (int r = 0; r < 5; ++r) {
+    const double* Jr = jmap + (t * 5 + r) * 18;
+    double s = 0;
+#pragma unroll
+    for (int c = 0; c < 18; ++c) s += Jr[c] * fv[c];
+    if (Fj) {
+      const double* Fr = jfmap + (t * 5 + r) * 3;
+      s += Fr[0] * Fj[3 * t] + Fr[1] * Fj[3 * t + 1] + Fr[2] * Fj[3 * t + 2];
+    }
+    jumps[5 * t + r] = s;
+  }
+}
+
+__global__ void k_interp_jump(int64_t n, const int64_t* __restrict__ cp_target, const double* __restrict__ fitvals,
+                              const double* __restrict__ emap, const double* __restrict__ efmap,
+                              const double* __restrict__ Fj, double* __restrict__ ejump) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= 3 * n) return;
+  const int64_t c = r / 3;
+  const int64_t t = cp_target[c];
+  double s = 0;
+  for (int q = 0; q < 18; ++q) s += emap[18 * r + q] * fitvals[18 * t + q];
+  if (Fj)
+    for (int i = 0; i < 3; ++i) s += efmap[3 * r + i] * Fj[3 * t + i];
+  ejump[r] = s;
+}
+
+__global__ void k_correct(int64_t nirr, const int64_t* __restrict__ irr_node, const int64_t* __restrict__ irr_ptr,
+                          const int32_t* __restrict__ arm_t, const int8_t* __restrict__ arm_o,
+                          const double* __restrict__ arm_a, const double* __restrict__ jumps, double* __restrict__ F) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= nirr) return;
+  double v = 0;
+  for (int64_t q = irr_ptr[r]; q < irr_ptr[r + 1]; ++q) {
+    const double* J = jumps + 5 * (int64_t)arm_t[q] + arm_o[q];
+    const double* a = arm_a + 3 * q;
+    v += a[0] * J[0] + a[1] * J[1];
+    if (arm_o[q] == 0) v += a[2] * J[2];
+  }
+  F[irr_node[r]] += v;
+}
+
+__global__ void k_interp(int64_t n, const int64_t* __restrict__ idx, const double* __restrict__ w,
+                         const double* __restrict__ u, const double* __restrict__ ejump, double* __restrict__ out) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= 3 * n) return;
+  double s = ejump[r];
+#pragma unroll
+  for (int q = 0; q < 10; ++q) s += w[10 * r + q] * u[idx[10 * r + q]];
+  out[r] = s;
+}
+
+__global__ void k_interp_T(int64_t nnode, const int64_t* __restrict__ ptr, const int64_t* __restrict__ node,
+                           const int32_t* __restrict__ row, const double* __restrict__ w,
+                           const double* __restrict__ wbar, double* __restrict__ ubar) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= nnode) return;
+  double s = 0;
+  for (int64_t e = ptr[k]; e < ptr[k + 1]; ++e) s += w[e] * wbar[row[e]];
+  ubar[node[k]] = s;
+}
+
+__global__ void k_correct_T(int64_t T, const int64_t* __restrict__ ptr, const int64_t* __restrict__ node,
+                            const int8_t* __restrict__ slot, const double* __restrict__ a,
+                            const double* __restrict__ Fbar, double* __restrict__ jbar) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= T) return;
+  double s[5] = {0, 0, 0, 0, 0};
+  for (int64_t e = ptr[t]; e < ptr[t + 1]; ++e) s[slot[e]] += a[e] * Fbar[node[e]];
+  for (int q = 0; q < 5; ++q) jbar[5 * t + q] = s[q];
+}
+
+__global__ void k_jump_T(int64_t T, const int64_t* __restrict__ cp_of, const double* __restrict__ jmap,
+                         const double* __restrict__ emap, const double* __restrict__ jbar,
+                         const double* __restrict__ wbar, double* __restrict__ fitbar) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= T) return;
+  const int64_t cp = cp_of[t];
+  for (int c = 0; c < 18; ++c) {
+    double s = 0;
+    for (int r = 0; r < 5; ++r) s += jmap[(t * 5 + r) * 18 + c] * jbar[5 * t + r];
+    if (cp >= 0)
+      for (int m = 0; m < 3; ++m) s += emap[(cp * 3 + m) * 18 + c] * wbar[3 * cp + m];
+    fitbar[18 * t + c] = s;
+  }
+}
+
+__global__ void k_fit_T(int64_t n, const int64_t* __restrict__ ptr, const int64_t* __restrict__ entry,
+                        const int32_t* __restrict__ target, const double* __restrict__ fitw,
+                        const double* __restrict__ fitbar, double* __restrict__ phibar) {
+  const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  double s[3] = {0, 0, 0};
+  for (int64_t q = ptr[c]; q < ptr[c + 1]; ++q) {
+    const int64_t e = entry[q];
+    const double* fb = fitbar + 18 * (int64_t)target[q];
+    for (int k = 0; k < 6; ++k) {
+      const double w = fitw[6 * e + k];
+      s[0] += w * fb[3 * k];
+      s[1] += w * fb[3 * k + 1];
+      s[2] += w * fb[3 * k + 2];
+    }
+  }
+  phibar[3 * c] = s[0];
+  phibar[3 * c + 1] = s[1];
+  phibar[3 * c + 2] = s[2];
+}
+
+__global__ void k_export_u(int N, const double* __restrict__ ui, double* __restrict__ ue) {
+  const int64_t M = (int64_t)N * N * N;
+  const int64_t Me = (int64_t)(N + 1) * N * N;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < 3 * Me; g += (int64_t)gridDim.x * blockDim.x) {
+    const int m = (int)(g / Me);
+    const int64_t l = g - m * Me;
+    int sh[3] = {N, N, N};
+    sh[m] = N + 1;
+    const int k = (int)(l % sh[2]), j = (int)((l / sh[2]) % sh[1]), i = (int)(l / ((int64_t)sh[2] * sh[1]));
+    const int id[3] = {i, j, k};
+    double v = 0.0;
+    if (id[m] < N) v = ui[m * M + ((int64_t)i * N + j) * N + k];
+    ue[g] = v;
+  }
+}
+
+__global__ void k_import_u(int N, const double* __restrict__ ue, double* __restrict__ ui) {
+  const int64_t M = (int64_t)N * N * N;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < 3 * M; g += (int64_t)gridDim.x * blockDim.x) {
+    const int m = (int)(g / M);
+    const int64_t l = g - m * M;
+    const int k = (int)(l % N), j = (int)((l / N) % N), i = (int)(l / ((int64_t)N * N));
+    int sh[3] = {N, N, N};
+    sh[m] = N + 1;
+    const int64_t Me = (int64_t)(N + 1) * N * N;
+    const int id[3] = {i, j, k};
+    ui[g] = (id[m] == 0) ? 0.0 : ue[m * Me + ((int64_t)i * sh[1] + j) * sh[2] + k];
+  }
+}
+
+__global__ void k_scatter_add(int64_t n, const int64_t* __restrict__ idx, const double* __restrict__ v,
+                              double* __restrict__ F) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n) F[idx[r]] += v[r];
+}
+
+__global__ void k_check_finite(int64_t n, const double* __restrict__ a, int* __restrict__ flag) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    if (!isfinite(a[i])) *flag = 1;  // benign race: every writer stores 1
+}
+
+// ---------------------------------------------------------------------------------------
+// launch wrappers
+// ---------------------------------------------------------------------------------------
+static inline int ew_blocks(int64_t n) {
+  int64_t b = (n + 255) / 256;
+  return (int)(b < 4096 ? (b > 0 ? b : 1) : 4096);
+}
+
+// kernels whose tile needs more than the default 64 KiB of LDS opt in to the larger limit
+template <typename K>
+static void ensure_lds(K kernel, size_t bytes) {
+  if (bytes > 65536) (void)hipFuncSetAttribute((const void*)kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+#define KFBI_DISPATCH_N(N, MACRO) \
+  switch (N) {                    \
+    case 16: MACRO(16); break;    \
+    case 32: MACRO(32); break;    \
+    case 64: MACRO(64); break;    \
+    case 128: MACRO(128); break;  \
+    case 256: MACRO(256); break;  \
+    case 512: MACRO(512); break;  \
+    default: return hipErrorInvalidValue; \
+  }
+
+template <typename T, int N, int KIND, bool ACC>
+static hipError_t pass_n(int axis, const T* in, T* out, const Tab<T>& tb, hipStream_t s) {
+  const size_t lds = TileLDS<T, N, KIND>::BYTES;
+  const int blocks = N * N / TileShape<T, N>::W;
+  ensure_lds(k_pass<T, N, KIND, ACC>, lds);
+  hipLaunchKernelGGL((k_pass<T, N, KIND, ACC>), dim3(blocks), dim3(NT), lds, s, in, out, axis, tb);
+  return hipGetLastError();
+}
+
+template <typename T, int N>
+static hipError_t pass_kind(int kind, int axis, const T* in, T* out, bool acc, const Tab<T>& tb, hipStream_t s) {
+#define KFBI_K(KD)                                                                            \
+  case KD:                                                                                    \
+    return acc ? pass_n<T, N, KD, true>(axis, in, out, tb, s) : pass_n<T, N, KD, false>(axis, in, out, tb, s);
+  switch (kind) {
+    KFBI_K(DCT2)
+    KFBI_K(DST2)
+    KFBI_K(DCT3)
+    KFBI_K(DST3)
+    KFBI_K(DST1)
+  }
+#undef KFBI_K
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_pass(int N, int kind, int axis, const T* in, T* out, bool accumulate, const DevTables<T>& tb,
+                       hipStream_t s) {
+  const Tab<T> t = tab_of(tb);
+#define KFBI_M(NN) return pass_kind<T, NN>(kind, axis, in, out, accumulate, t, s)
+  KFBI_DISPATCH_N(N, KFBI_M)
+#undef KFBI_M
+  return hipErrorInvalidValue;
+}
+
+template <typename T>
+hipError_t launch_zscale_inv(int N, int m, int wkind, const T* in, T* out, double mu, const DevTables<T>& tb,
+                             hipStream_t s) {
+  (void)wkind;
+  const Tab<T> t = tab_of(tb);
+#define KFBI_M(NN)                                                                                          \
+  {                                                                                                         \
+    const int blocks = NN * NN / TileShape<T, NN>::W;                                                           \
+    const size_t lds = TileLDS<T, NN, DCT3>::BYTES;                                                         \
+    ensure_lds(k_zscale_inv<T, NN, DCT3>, lds);                                                             \
+    ensure_lds(k_zscale_inv<T, NN, DST3>, lds);                                                             \
+    if (m == 2)                                                                                             \
+      hipLaunchKernelGGL((k_zscale_inv<T, NN, DCT3>), dim3(blocks), dim3(NT), lds, s, in, out, m, mu, tb.sig, \
+                         tb.sig2s, t);                                                                      \
+    else                                                                                                    \
+      hipLaunchKernelGGL((k_zscale_inv<T, NN, DST3>), dim3(blocks), dim3(NT), lds, s, in, out, m, mu, tb.sig, \
+                         tb.sig2s, t);                                                                      \
+  }
+  KFBI_DISPATCH_N(N, KFBI_M)
+#undef KFBI_M
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_zmid(int N, T* A1, T* B2, T* B3, double mu, const DevTables<T>& tb, hipStream_t s) {
+  const Tab<T> t = tab_of(tb);
+#define KFBI_M(NN)                                                                                              \
+  {                                                                                                             \
+    const int blocks = NN * NN / TileShape<T, NN>::W;                                                               \
+    const size_t lds = TileLDS<T, NN, DCT2>::BYTES;                                                             \
+    ensure_lds(k_zmid<T, NN>, lds);                                                                             \
+    hipLaunchKernelGGL((k_zmid<T, NN>), dim3(blocks, 3), dim3(NT), lds, s, A1, B2, B3, mu, tb.sig, tb.sig2s, t); \
+  }
+  KFBI_DISPATCH_N(N, KFBI_M)
+#undef KFBI_M
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_xfwd_cg(int N, const T* r, T* d, T* A, const double* scal, const DevTables<T>& tb, hipStream_t s) {
+  const Tab<T> t = tab_of(tb);
+#define KFBI_M(NN)                                                                                  \
+  {                                                                                                 \
+    const int blocks = NN * NN / TileShape<T, NN>::W;                                                   \
+    const size_t lds = TileLDS<T, NN, DCT2>::BYTES;                                                 \
+    ensure_lds(k_xfwd_cg<T, NN>, lds);                                                              \
+    hipLaunchKernelGGL((k_xfwd_cg<T, NN>), dim3(blocks), dim3(NT), lds, s, r, d, A, scal, t);       \
+  }
+  KFBI_DISPATCH_N(N, KFBI_M)
+#undef KFBI_M
+  return hipGetLastError();
+}
+
+int xinv_blocks(int N, int elem_size) { return N * N / std::min(128 / elem_size, N); }
+
+template <typename T>
+hipError_t launch_xinv_cg(int N, const T* B, T* q, const T* d, double c, double* partials, const DevTables<T>& tb,
+                          hipStream_t s) {
+  const Tab<T> t = tab_of(tb);
+#define KFBI_M(NN)                                                                                   \
+  {                                                                                                  \
+    const int blocks = NN * NN / TileShape<T, NN>::W;                                                    \
+    const size_t lds = TileLDS<T, NN, DST3>::BYTES;                                                  \
+    ensure_lds(k_xinv_cg<T, NN>, lds);                                                               \
+    hipLaunchKernelGGL((k_xinv_cg<T, NN>), dim3(blocks), dim3(NT), lds, s, B, q, d, c, partials, t); \
+  }
+  KFBI_DISPATCH_N(N, KFBI_M)
+#undef KFBI_M
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_cg_update(int64_t M, T* x, T* r, const T* d, const T* q, const double* scal, double* partials,
+                            int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL((k_cg_update<T>), dim3(nblocks), dim3(NT), 0, s, M, x, r, d, q, scal, partials);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_backsub_combine(int N, int m, const T* F, const T* P, T* G, double mu, const DevTables<T>& tb,
+                                  hipStream_t s) {
+#define KFBI_M(NN)                                                                                           \
+  hipLaunchKernelGGL((k_backsub_combine<T, NN>), dim3(ew_blocks((int64_t)NN * NN * NN)), dim3(256), 0, s, m, F, P, \
+                     G, mu, tb.sig, tb.sig2s);
+  KFBI_DISPATCH_N(N, KFBI_M)
+#undef KFBI_M
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce(const double* partials, int nparts, int nper, double* scal, int op, int stokes, int64_t M,
+                         hipStream_t s, double* out) {
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(NT), 0, s, partials, nparts, nper, scal, op, stokes, M, out);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_dot_partials(int64_t M, const T* a, const T* b, double* partials, int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL((k_dot_partials<T>), dim3(nblocks), dim3(NT), 0, s, M, a, b, partials);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_sum_partials(int64_t M, const T* a, double* partials, int nblocks, hipStream_t s) {
+  hipLaunchKernelGGL((k_sum_partials<T>), dim3(nblocks), dim3(NT), 0, s, M, a, partials);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_add_scalar(int64_t M, T* a, const double* scal, int idx, double factor, hipStream_t s) {
+  hipLaunchKernelGGL((k_add_scalar<T>), dim3(ew_blocks(M)), dim3(256), 0, s, M, a, scal, idx, factor);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_fill(int64_t n, T* a, T v, hipStream_t s) {
+  hipLaunchKernelGGL((k_fill<T>), dim3(ew_blocks(n)), dim3(256), 0, s, n, a, v);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_axpby(int64_t n, T* y, double a, const T* x, double b, hipStream_t s) {
+  hipLaunchKernelGGL((k_axpby<T>), dim3(ew_blocks(n)), dim3(256), 0, s, n, y, a, x, b);
+  return hipGetLastError();
+}
+template <typename TO, typename TI>
+hipError_t launch_convert(int64_t n, TO* out, const TI* in, hipStream_t s) {
+  hipLaunchKernelGGL((k_convert<TO, TI>), dim3(ew_blocks(n)), dim3(256), 0, s, n, out, in);
+  return hipGetLastError();
+}
+template <typename TI>
+hipError_t launch_add_into_f64(int64_t n, double* out, const TI* in, hipStream_t s) {
+  hipLaunchKernelGGL((k_add_into_f64<TI>), dim3(ew_blocks(n)), dim3(256), 0, s, n, out, in);
+  return hipGetLastError();
+}
+hipError_t launch_rhs_minus(int64_t M, double* b, const double* Fp, hipStream_t s) {
+  hipLaunchKernelGGL((k_rhs_minus<double>), dim3(ew_blocks(M)), dim3(256), 0, s, M, b, Fp);
+  return hipGetLastError();
+}
+template <typename T>
+hipError_t launch_rhs_minus_t(int64_t M, T* b, const T* Fp, hipStream_t s) {
+  hipLaunchKernelGGL((k_rhs_minus<T>), dim3(ew_blocks(M)), dim3(256), 0, s, M, b, Fp);
+  return hipGetLastError();
+}
+
+hipError_t launch_mac_residual(int N, double h, double mu, double c, const double* u, const double* p,
+                               const double* Fu, const double* Fp, double* ru, double* rp, hipStream_t s) {
+  const int64_t M = (int64_t)N * N * N;
+  for (int m = 0; m < 3; ++m)
+    hipLaunchKernelGGL(k_res_u, dim3(ew_blocks(M)), dim3(256), 0, s, N, m, h, mu, u + m * M, p, Fu + m * M,
+                       ru + m * M);
+  hipLaunchKernelGGL(k_res_p, dim3(ew_blocks(M)), dim3(256), 0, s, N, h, c, u, p, Fp, rp);
+  return hipGetLastError();
+}
+
+static inline int gb(int64_t n) { return (int)((n + 255) / 256 > 0 ? (n + 255) / 256 : 1); }
+
+hipError_t launch_fit_jump(int64_t T, const int64_t* nb_ptr, const int32_t* nb_idx, const double* fitw,
+                           const double* jmap, const double* jfmap, const double* Fj, const double* phi,
+                           double* jumps, double* fitvals, hipStream_t s) {
+  hipLaunchKernelGGL(k_fit_jump, dim3(gb(T)), dim3(256), 0, s, T, nb_ptr, nb_idx, fitw, jmap, jfmap, Fj, phi, jumps,
+                     fitvals);
+  return hipGetLastError();
+}
+hipError_t launch_interp_jump(int64_t n, const int64_t* cp_target, const double* fitvals, const double* emap,
+                              const double* efmap, const double* Fj, double* ejump, hipStream_t s) {
+  hipLaunchKernelGGL(k_interp_jump, dim3(gb(3 * n)), dim3(256), 0, s, n, cp_target, fitvals, emap, efmap, Fj, ejump);
+  return hipGetLastError();
+}
+hipError_t launch_correct(int64_t nirr, const int64_t* irr_node, const int64_t* irr_ptr, const int32_t* arm_t,
+                          const int8_t* arm_o, const double* arm_a, const double* jumps, double* F, hipStream_t s) {
+  hipLaunchKernelGGL(k_correct, dim3(gb(nirr)), dim3(256), 0, s, nirr, irr_node, irr_ptr, arm_t, arm_o, arm_a, jumps,
+                     F);
+  return hipGetLastError();
+}
+hipError_t launch_interp(int64_t n, const int64_t* idx, const double* w, const double* u, const double* ejump,
+                         double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_interp, dim3(gb(3 * n)), dim3(256), 0, s, n, idx, w, u, ejump, out);
+  return hipGetLastError();
+}
+hipError_t launch_interp_T(int64_t nnode, const int64_t* ptr, const int64_t* node, const int32_t* row,
+                           const double* w, const double* wbar, double* ubar, hipStream_t s) {
+  hipLaunchKernelGGL(k_interp_T, dim3(gb(nnode)), dim3(256), 0, s, nnode, ptr, node, row, w, wbar, ubar);
+  return hipGetLastError();
+}
+hipError_t launch_correct_T(int64_t T, const int64_t* ptr, const int64_t* node, const int8_t* slot, const double* a,
+                            const double* Fbar, double* jbar, hipStream_t s) {
+  hipLaunchKernelGGL(k_correct_T, dim3(gb(T)), dim3(256), 0, s, T, ptr, node, slot, a, Fbar, jbar);
+  return hipGetLastError();
+}
+hipError_t launch_jump_T(int64_t T, const int64_t* cp_of, const double* jmap, const double* emap,
+                         const double* jbar, const double* wbar, double* fitbar, hipStream_t s) {
+  hipLaunchKernelGGL(k_jump_T, dim3(gb(T)), dim3(256), 0, s, T, cp_of, jmap, emap, jbar, wbar, fitbar);
+  return hipGetLastError();
+}
+hipError_t launch_fit_T(int64_t n, const int64_t* ptr, const int64_t* entry, const int32_t* target,
+                        const double* fitw, const double* fitbar, double* phibar, hipStream_t s) {
+  hipLaunchKernelGGL(k_fit_T, dim3(gb(n)), dim3(256), 0, s, n, ptr, entry, target, fitw, fitbar, phibar);
+  return hipGetLastError();
+}
+hipError_t launch_export_u(int N, const double* u_int, double* u_ext, hipStream_t s) {
+  hipLaunchKernelGGL(k_export_u, dim3(ew_blocks(3LL * (N + 1) * N * N)), dim3(256), 0, s, N, u_int, u_ext);
+  return hipGetLastError();
+}
+hipError_t launch_import_u(int N, const double* u_ext, double* u_int, hipStream_t s) {
+  hipLaunchKernelGGL(k_import_u, dim3(ew_blocks(3LL * N * N * N)), dim3(256), 0, s, N, u_ext, u_int);
+  return hipGetLastError();
+}
+hipError_t launch_scatter_add(int64_t n, const int64_t* idx, const double* v, double* F, hipStream_t s) {
+  hipLaunchKernelGGL(k_scatter_add, dim3(gb(n)), dim3(256), 0, s, n, idx, v, F);
+  return hipGetLastError();
+}
+hipError_t launch_check_finite(int64_t n, const double* a, int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_check_finite, dim3(ew_blocks(n)), dim3(256), 0, s, n, a, flag);
+  return hipGetLastError();
+}
+
+// explicit instantiations
+#define KFBI_INST(T)                                                                                                 \
+  template hipError_t launch_pass<T>(int, int, int, const T*, T*, bool, const DevTables<T>&, hipStream_t);           \
+  template hipError_t launch_zscale_inv<T>(int, int, int, const T*, T*, double, const DevTables<T>&, hipStream_t);   \
+  template hipError_t launch_zmid<T>(int, T*, T*, T*, double, const DevTables<T>&, hipStream_t);                     \
+  template hipError_t launch_xfwd_cg<T>(int, const T*, T*, T*, const double*, const DevTables<T>&, hipStream_t);     \
+  template hipError_t launch_xinv_cg<T>(int, const T*, T*, const T*, double, double*, const DevTables<T>&,           \
+                                        hipStream_t);                                                                \
+  template hipError_t launch_cg_update<T>(int64_t, T*, T*, const T*, const T*, const double*, double*, int,          \
+                                          hipStream_t);                                                              \
+  template hipError_t launch_backsub_combine<T>(int, int, const T*, const T*, T*, double, const DevTables<T>&,       \
+                                                hipStream_t);                                                        \
+  template hipError_t launch_dot_partials<T>(int64_t, const T*, const T*, double*, int, hipStream_t);                \
+  template hipError_t launch_sum_partials<T>(int64_t, const T*, double*, int, hipStream_t);                          \
+  template hipError_t launch_add_scalar<T>(int64_t, T*, const double*, int, double, hipStream_t);                    \
+  template hipError_t launch_fill<T>(int64_t, T*, T, hipStream_t);                                                   \
+  template hipError_t launch_axpby<T>(int64_t, T*, double, const T*, double, hipStream_t);                           \
+  template hipError_t launch_rhs_minus_t<T>(int64_t, T*, const T*, hipStream_t);                                     \
+  template hipError_t launch_add_into_f64<T>(int64_t, double*, const T*, hipStream_t);
+KFBI_INST(float)
+KFBI_INST(double)
+template hipError_t launch_convert<float, double>(int64_t, float*, const double*, hipStream_t);
+template hipError_t launch_convert<double, float>(int64_t, double*, const float*, hipStream_t);
+template hipError_t launch_convert<double, double>(int64_t, double*, const double*, hipStream_t);
+
+}  // namespace kfbi

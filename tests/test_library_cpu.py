@@ -1,0 +1,128 @@
+"""Host-side checks of the HIP library that need no GPU: the shared library loads and exports
+every entry point of include/kfbi.h, and its host setup (geometry, fit weights, jump maps,
+correction arms, interpolation weights) reproduces the oracle's on the same inputs."""
+import os
+import re
+
+import numpy as np
+import pytest
+import scipy.sparse as sps
+
+import kfbi_inputs as KI
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _lib():
+    import paper_2303_04992_amd as K
+    return K
+
+
+def test_library_exports_every_declared_symbol():
+    import ctypes
+    K = _lib()
+    hdr = open(os.path.join(ROOT, "include", "kfbi.h")).read()
+    names = sorted(set(re.findall(r"\b(kfbi_[a-z_]+)\s*\(", hdr)))
+    assert len(names) >= 14
+    lib = ctypes.CDLL(K.LIB_PATH)
+    missing = [n for n in names if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_bad_config_is_rejected():
+    K = _lib()
+    cfg = KI.WORKLOADS["sphere32"].with_N(24)          # not a power of two
+    with pytest.raises(K.KfbiError) as e:
+        K.Plan(cfg)
+    assert e.value.status == K.EINVAL
+
+
+def test_underresolved_geometry_is_reported():
+    K = _lib()
+    cfg = KI.WORKLOADS["star512n"].with_N(32)          # 5-lobed star at h = 1/16
+    with pytest.raises(K.KfbiError) as e:
+        K.Plan(cfg)
+    assert e.value.status == K.EGEOM
+
+
+def _compare(name, N):
+    from oracle.kfbi import Oracle
+    from oracle.geometry import FAMILIES
+    from oracle.surface import jidx_u, jidx_du, jidx_ddu, jidx_p, jidx_dp
+    K = _lib()
+    cfg = KI.WORKLOADS[name].with_N(N)
+    P = K.Plan(cfg)
+    O = Oracle(cfg)
+    xyz = P.get("xyz").reshape(-1, 3)
+    fam = P.get("fam")
+    cp = P.get("cp_target")
+    # crossings and control points: identical sets, same order
+    assert len(fam) == O.T and len(cp) == O.n
+    assert np.array_equal(fam, O.cr.fam)
+    assert np.array_equal(cp, O.cr.cp_target)
+    assert np.abs(xyz - O.cr.xyz).max() < 1e-13
+    assert np.abs(P.get("normal").reshape(-1, 3) - O.cr.normal).max() < 1e-12
+    # composite fit + jump map on a random density
+    nb_ptr, nb_idx = P.get("nb_ptr"), P.get("nb_idx")
+    fitw = P.get("fitw").reshape(-1, 6)
+    rows = np.repeat(np.arange(len(fam)), np.diff(nb_ptr))
+    phi = KI.random_density(len(cp))
+    fv = np.zeros((len(fam), 6, 3))
+    np.add.at(fv, rows, fitw[:, :, None] * phi[nb_idx][:, None, :])
+    jm = P.get("jmap").reshape(-1, 5, 18)
+    jl = np.einsum("trc,tc->tr", jm, fv.reshape(len(fam), 18))
+    jo = (O.Jmat @ (O.Fit @ phi.ravel())).reshape(-1, 34)
+    scale = np.abs(jo).max()
+    for t in range(len(fam)):
+        k, g = FAMILIES[fam[t]]
+        v = k if g == -1 else g
+        sel = [jidx_u(v), jidx_du(v, k), jidx_ddu(v, k, k)] + ([jidx_p(), jidx_dp(k)] if g == -1 else [])
+        assert np.abs(jl[t, :len(sel)] - jo[t, sel]).max() < 1e-12 * scale
+    # correction arms: same sparse map (in the oracle's right-hand-side layout)
+    M = N ** 3
+    off = O.rhs_off
+    irr, ip = P.get("irr_node"), P.get("irr_ptr")
+    at, ao, aa = P.get("arm_t"), P.get("arm_o"), P.get("arm_a").reshape(-1, 3)
+
+    def to_oracle(gi):
+        g, l = divmod(int(gi), M)
+        i, j, k = np.unravel_index(l, (N, N, N))
+        if g == 3:
+            return off[3] + np.ravel_multi_index((i, j, k), (N, N, N))
+        sh = tuple(N + 1 if d == g else N for d in range(3))
+        return off[g] + np.ravel_multi_index((i, j, k), sh)
+
+    r_, c_, v_ = [], [], []
+    for r in range(len(irr)):
+        R = to_oracle(irr[r])
+        for q in range(ip[r], ip[r + 1]):
+            t = at[q]
+            k, g = FAMILIES[fam[t]]
+            v = k if g == -1 else g
+            if ao[q] == 0:
+                js, ws = [jidx_u(v), jidx_du(v, k), jidx_ddu(v, k, k)], aa[q]
+            else:
+                js, ws = [jidx_p(), jidx_dp(k)], aa[q, :2]
+            for jj, w in zip(js, ws):
+                r_.append(R)
+                c_.append(t * 34 + jj)
+                v_.append(w)
+    Cl = sps.csr_matrix((v_, (r_, c_)), shape=O.Cmat.shape)
+    assert Cl.nnz == O.Cmat.nnz
+    d = Cl - O.Cmat
+    assert (abs(d).max() if d.nnz else 0.0) < 1e-12 * abs(O.Cmat).max()
+    # interpolation weights and the composite interpolation jump term
+    iw, ii = P.get("itp_w").reshape(-1, 10), P.get("itp_idx").reshape(-1, 10)
+    Wl = sps.csr_matrix((iw.ravel(), (np.repeat(np.arange(3 * len(cp)), 10),
+                                       np.array([to_oracle(g) for g in ii.ravel()]))), shape=O.W.shape)
+    d = Wl - O.W
+    assert (abs(d).max() if d.nnz else 0.0) < 1e-12
+    em = P.get("emap")[:len(cp) * 54].reshape(-1, 3, 18)
+    el = np.einsum("cmq,cq->cm", em, fv.reshape(len(fam), 18)[cp]).ravel()
+    eo = O.E @ jo.ravel()
+    assert np.abs(el - eo).max() < 1e-11 * max(1.0, np.abs(eo).max())
+
+
+@pytest.mark.parametrize("name,N", [("sphere32", 32), ("ellip128", 32), ("star128", 32)])
+def test_host_setup_matches_oracle(name, N):
+    _compare(name, N)
