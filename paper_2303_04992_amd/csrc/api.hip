@@ -110,6 +110,13 @@ struct MacSolver {
     tb.isc = dupload(isc, owned, s);
     tb.sig = dupload(sig, owned, s);
     tb.sig2s = dupload(sig2s, owned, s);
+    std::vector<T> sg2t(N), sg2st(N);
+    for (int k = 0; k < N; ++k) {
+      sg2t[k] = T(sig[k] * sig[k]);
+      sg2st[k] = T(sig2s[k]);
+    }
+    tb.sg2 = dupload(sg2t, owned, s);
+    tb.sg2s = dupload(sg2st, owned, s);
     for (int m = 0; m < 3; ++m) Fh[m] = dalloc<T>(M, owned);
     b = dalloc<T>(M, owned);
     x = dalloc<T>(M, owned);
@@ -122,7 +129,7 @@ struct MacSolver {
     B2 = dalloc<T>(M, owned);
     B3 = dalloc<T>(M, owned);
     tmp = dalloc<T>(M, owned);
-    nparts_x = xinv_blocks(N, sizeof(T));
+    nparts_x = zinv_blocks(N, sizeof(T));
     partials = dalloc<double>(std::max(3 * nparts_x, nparts_u), owned);
     scal = dalloc<double>(16, owned);
     HIPCHK(hipHostMalloc((void**)&host_rr, 2 * sizeof(double), hipHostMallocDefault));
@@ -148,18 +155,20 @@ struct MacSolver {
   }
 
   // S p for the CG direction d (q = S d); d = r + beta d_old is formed in the first pass
+  // C_0 = DCT_x DST_y DST_z, C_1 = DST_x DCT_y DST_z, C_2 = DST_x DST_y DCT_z (orthonormal);
+  // order z, y, [x fused with the weights], y, z
   void cg_iteration() {
-    HIPCHK(launch_xfwd_cg<T>(N, r, d, A, scal, tb, s));
-    pass(DST2, 0, d, B);
-    pass(DST2, 1, A, A1);
-    pass(DCT2, 1, B, B2);
-    pass(DST2, 1, B, B3);
-    HIPCHK(launch_zmid<T>(N, A1, B2, B3, mu, tb, s));
-    pass(DST3, 1, A1, A1);
-    pass(DCT3, 1, B2, B);
-    pass(DST3, 1, B3, B, true);
-    pass(DCT3, 0, A1, q);
-    HIPCHK(launch_xinv_cg<T>(N, B, q, d, c, partials, tb, s));
+    HIPCHK(launch_zfwd_cg<T>(N, r, d, A, scal, tb, s));  // d = r + beta d; A = DST_z d
+    pass(DCT2, 2, d, B);                                  // B = DCT_z d
+    pass(DST2, 1, A, A1);                                 // component 0
+    pass(DCT2, 1, A, B2);                                 // component 1
+    pass(DST2, 1, B, B3);                                 // component 2
+    HIPCHK(launch_xmid<T>(N, A1, B2, B3, mu, tb, s));
+    pass(DST3, 1, A1, A);                                 // components 0 and 1 share DST_z
+    pass(DCT3, 1, B2, A, true);
+    pass(DST3, 1, B3, B);
+    pass(DST3, 2, A, q);
+    HIPCHK(launch_zinv_cg<T>(N, B, q, d, c, partials, tb, s));
     HIPCHK(launch_reduce(partials, nparts_x, 3, scal, R_ALPHA, pde == KFBI_STOKES, M, s));
     HIPCHK(launch_cg_update<T>(M, x, r, d, q, scal, partials, nparts_u, s));
     HIPCHK(launch_reduce(partials, nparts_u, 1, scal, R_BETA, 0, M, s));

@@ -20,6 +20,8 @@ struct DevTables {
   T* isc = nullptr;     // [N]
   double* sig = nullptr;   // sigma_k = (2/h) sin(pi k / 2N), k < N
   double* sig2s = nullptr; // sigma_{k+1}^2, k < N
+  T* sg2 = nullptr;        // sigma_k^2 in T
+  T* sg2s = nullptr;       // sigma_{k+1}^2 in T
 };
 
 enum WeightKind { W_SCHUR = 0, W_RHS = 1 };
@@ -32,18 +34,18 @@ hipError_t launch_pass(int N, int kind, int axis, const T* in, T* out, bool accu
 template <typename T>
 hipError_t launch_zscale_inv(int N, int m, int wkind, const T* in, T* out, double mu, const DevTables<T>& tb,
                              hipStream_t s);
-// fused z-pass of the Schur operator for the three components (fwd z, weight, inverse z)
+// fused x-pass of the Schur operator for the three components (fwd x, weight, inverse x)
 template <typename T>
-hipError_t launch_zmid(int N, T* A1, T* B2, T* B3, double mu, const DevTables<T>& tb, hipStream_t s);
-// d = r + beta d_old (beta from scal[2]) and A = DCT-II_x(d)
+hipError_t launch_xmid(int N, T* A0, T* A1, T* A2, double mu, const DevTables<T>& tb, hipStream_t s);
+// d = r + beta d_old (beta from scal[2]) and T1 = DST-II_z(d)
 template <typename T>
-hipError_t launch_xfwd_cg(int N, const T* r, T* d, T* A, const double* scal, const DevTables<T>& tb,
+hipError_t launch_zfwd_cg(int N, const T* r, T* d, T* T1, const double* scal, const DevTables<T>& tb,
                           hipStream_t s);
-// q += DST-III_x(B) + c d; per-block partial sums of d.q, q, d
+// q += DCT-III_z(B) + c d; per-block partial sums of d.q, q, d
 template <typename T>
-hipError_t launch_xinv_cg(int N, const T* B, T* q, const T* d, double c, double* partials, const DevTables<T>& tb,
+hipError_t launch_zinv_cg(int N, const T* B, T* q, const T* d, double c, double* partials, const DevTables<T>& tb,
                           hipStream_t s);
-int xinv_blocks(int N, int elem_size);
+int zinv_blocks(int N, int elem_size);
 // x += alpha d; r -= alpha (q - mq); partial sums of r.r
 template <typename T>
 hipError_t launch_cg_update(int64_t M, T* x, T* r, const T* d, const T* q, const double* scal, double* partials,

@@ -29,6 +29,8 @@ static Tab<T> tab_of(const DevTables<T>& d) {
   t.mk = reinterpret_cast<const C2<T>*>(d.mk);
   t.sc = d.sc;
   t.isc = d.isc;
+  t.sg2 = d.sg2;
+  t.sg2s = d.sg2s;
   return t;
 }
 
@@ -51,12 +53,14 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   return r;
 }
 
-template <typename T, int N>
+constexpr int EW_NT = 256;  // threads per block of the elementwise and reduction kernels
+
+template <typename T, int N, int NT>
 __device__ __forceinline__ void load_tile(T* lds, const T* __restrict__ g, int axis, const TileAddr& a) {
-  constexpr int W = TileShape<T, N>::W, RS = N + 1;
+  constexpr int W = TileCfg<T, N, DCT2>::W, RS = N + 1;
   for (int e = threadIdx.x; e < W * N; e += NT) {
     int p, n;
-    tile_elem<T, N>(axis, e, p, n);
+    tile_elem<W, N>(axis, e, p, n);
     lds[p * RS + n] = g[a.base + p * a.pstride + n * a.nstride];
   }
   __syncthreads();
@@ -77,74 +81,120 @@ __device__ __forceinline__ void lambda_of(int m, int i, int j, int k, const doub
 // ---------------------------------------------------------------------------------------
 // generic transform pass: out (+)= transform_KIND(in) along axis
 // ---------------------------------------------------------------------------------------
+// (in may equal out: a block reads its whole tile before it writes any output)
 template <typename T, int N, int KIND, bool ACC>
-__global__ __launch_bounds__(NT) void k_pass(const T* __restrict__ in, T* __restrict__ out, int axis, Tab<T> tb) {
+__global__ __launch_bounds__(256) void k_pass(const T* in, T* out, int axis, Tab<T> tb) {
   extern __shared__ __align__(16) unsigned char smem[];
   T* lds = reinterpret_cast<T*>(smem);
-  constexpr int W = TileShape<T, N>::W, RS = N + 1;
-  const TileAddr a = tile_addr<T, N>(axis, blockIdx.x);
-  load_tile<T, N>(lds, in, axis, a);
-  transform_tile<T, N, KIND>(lds, tb);
-  for (int e = threadIdx.x; e < W * N; e += NT) {
-    int p, n;
-    tile_elem<T, N>(axis, e, p, n);
+  using S = TileCfg<T, N, KIND>;
+  constexpr int W = S::W, NT = S::NT;
+  const TileAddr a = tile_addr<W, N>(axis, blockIdx.x);
+  auto st = [&](int p, int n, T v) {
     const long gi = a.base + p * a.pstride + n * a.nstride;
     if (ACC)
-      out[gi] += lds[p * RS + n];
+      out[gi] += v;
     else
-      out[gi] = lds[p * RS + n];
+      out[gi] = v;
+  };
+  if (axis == 2) {
+    load_tile<T, N, NT>(lds, in, axis, a);
+    transform_store<T, N, KIND>(lds, LdsSrc<T, N>{lds}, tb, 2, st);
+  } else {
+    transform_store<T, N, KIND>(lds, GlobSrc<T>{in, a.base, a.nstride}, tb, axis, st);
   }
 }
 
 // ---------------------------------------------------------------------------------------
-// fused Schur z-pass: forward z, multiply by sigma_m^2 / Lambda_m, inverse z (per component)
+// fused Schur x-pass of component mc: forward x (KF), spectral weight sigma^2/Lambda,
+// inverse x (KI), in place.  Between the two FFTs the forward post-processing, the weight
+// and the inverse pre-processing are applied together on each spectral pair (k, N-k) of a
+// job in registers: with V_q = (Z_q + conj Z_{N-q})/2 (pencil a) or
+// (Z_q - conj Z_{N-q})/(2i) (pencil b), the inverse input is built from
+// Y_q = omega_q Re(e^{-i pi q/2N} V_q), omega_q = w(q) (cosine) or w(N-1-q) (sine), the
+// orthonormal scale factors cancelling; V'_q = e^{+i pi q/2N}(Y_q - i Y_{N-q}), Y_N = 0,
+// Z'_q = V'^a_q + i V'^b_q.
 // ---------------------------------------------------------------------------------------
 template <typename T, int N, int KF, int KI>
-__device__ void zmid_body(T* lds, T* field, int m, double mu, const double* sig, const double* sig2s,
+__device__ void xmid_body(T* lds, T* field, int mc, double mu, const double* sig, const double* sig2s,
                           const Tab<T>& tb) {
-  constexpr int W = TileShape<T, N>::W, RS = N + 1;
-  const TileAddr a = tile_addr<T, N>(2, blockIdx.x);
-  load_tile<T, N>(lds, field, 2, a);
-  transform_tile<T, N, KF>(lds, tb);
-  for (int e = threadIdx.x; e < W * N; e += NT) {
-    const int p = e / N, k = e - p * N;
-    const int q = blockIdx.x * W + p;
-    const int xi = q / N, yi = q - xi * N;
-    double lam, sg;
-    lambda_of(m, xi, yi, k, sig, sig2s, lam, sg);
-    lds[p * RS + k] *= T(sg * sg / (mu * lam));
+  using S = TileCfg<T, N, KF>;
+  constexpr int W = S::W, NJ = S::NJ, ZS = S::ZS, NT = S::NT;
+  const TileAddr a = tile_addr<W, N>(0, blockIdx.x);
+  const int yi = blockIdx.x / (N / W), z0 = (blockIdx.x % (N / W)) * W;
+  fft_tile<T, N, KF>(lds, GlobSrc<T>{field, a.base, a.nstride}, tb);
+  C2<T>* cb = reinterpret_cast<C2<T>*>(lds);
+  constexpr int PAIRS = N / 2 + 1;
+  for (int t = threadIdx.x; t < NJ * PAIRS; t += NT) {
+    const int j = t % NJ, k = t / NJ;
+    const int kr = (N - k) & (N - 1);
+    const C2<T> Zk = cb[j * ZS + k], Zr = cb[j * ZS + kr];
+    // weights sigma_mc^2 / Lambda_mc of the two pencils at DCT-domain indices k and kr;
+    // x is the cosine axis for mc = 0 and a sine axis otherwise
+    T om[2][2];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int q = h ? kr : k;
+      const int mode = (KF == DST2) ? N - 1 - q : q;
+      const T lx = (mc == 0) ? tb.sg2[mode] : tb.sg2s[mode];
+#pragma unroll
+      for (int w = 0; w < 2; ++w) {
+        const int zi = z0 + 2 * j + w;
+        const T ly = (mc == 1) ? tb.sg2[yi] : tb.sg2s[yi];
+        const T lz = (mc == 2) ? tb.sg2[zi] : tb.sg2s[zi];
+        const T num = (mc == 0) ? lx : (mc == 1) ? ly : lz;
+        om[w][h] = num / (T(mu) * (lx + ly + lz));
+      }
+    }
+    const C2<T> mkk = tb.mk[k], mkr = tb.mk[kr];
+    const C2<T> Vak = {(Zk.x + Zr.x) * T(0.5), (Zk.y - Zr.y) * T(0.5)};
+    const C2<T> Vbk = {(Zk.y + Zr.y) * T(0.5), (Zr.x - Zk.x) * T(0.5)};
+    const C2<T> Var = {(Zr.x + Zk.x) * T(0.5), (Zr.y - Zk.y) * T(0.5)};
+    const C2<T> Vbr = {(Zr.y + Zk.y) * T(0.5), (Zk.x - Zr.x) * T(0.5)};
+    const T Yak = om[0][0] * (mkk.x * Vak.x - mkk.y * Vak.y);
+    const T Ybk = om[1][0] * (mkk.x * Vbk.x - mkk.y * Vbk.y);
+    const T Yar = (k == 0) ? T(0) : om[0][1] * (mkr.x * Var.x - mkr.y * Var.y);
+    const T Ybr = (k == 0) ? T(0) : om[1][1] * (mkr.x * Vbr.x - mkr.y * Vbr.y);
+    // V'_k = conj(mk_k)(Y_k - i Y_{N-k}),  V'_{N-k} = conj(mk_{N-k})(Y_{N-k} - i Y_k)
+    const C2<T> ck = {mkk.x, -mkk.y}, cr = {mkr.x, -mkr.y};
+    const C2<T> Wak = cmul(ck, C2<T>{Yak, -Yar}), Wbk = cmul(ck, C2<T>{Ybk, -Ybr});
+    cb[j * ZS + k] = {Wak.x - Wbk.y, Wak.y + Wbk.x};
+    if (k != 0 && kr != k) {
+      const C2<T> War = cmul(cr, C2<T>{Yar, -Yak}), Wbr = cmul(cr, C2<T>{Ybr, -Ybk});
+      cb[j * ZS + kr] = {War.x - Wbr.y, War.y + Wbr.x};
+    }
   }
   __syncthreads();
-  transform_tile<T, N, KI>(lds, tb);
+  fft_core<T, N, KI>(lds, [&](int j, int n) { return cb[j * ZS + n]; }, tb);
   for (int e = threadIdx.x; e < W * N; e += NT) {
-    const int p = e / N, n = e - p * N;
-    field[a.base + p * N + n] = lds[p * RS + n];
+    const int k = e / W, p = e - k * W;
+    field[a.base + p * a.pstride + k * a.nstride] = post_value<T, N, KI>(lds, tb, p, k);
   }
 }
 
 template <typename T, int N>
-__global__ __launch_bounds__(NT) void k_zmid(T* A1, T* B2, T* B3, double mu, const double* sig,
+__global__ __launch_bounds__(256) void k_xmid(T* A0, T* A1, T* A2, double mu, const double* sig,
                                              const double* sig2s, Tab<T> tb) {
   extern __shared__ __align__(16) unsigned char smem[];
   T* lds = reinterpret_cast<T*>(smem);
-  const int m = blockIdx.y;
-  if (m == 0)
-    zmid_body<T, N, DST2, DST3>(lds, A1, 0, mu, sig, sig2s, tb);
-  else if (m == 1)
-    zmid_body<T, N, DST2, DST3>(lds, B2, 1, mu, sig, sig2s, tb);
+  const int mc = blockIdx.y;
+  if (mc == 0)
+    xmid_body<T, N, DCT2, DCT3>(lds, A0, 0, mu, sig, sig2s, tb);
+  else if (mc == 1)
+    xmid_body<T, N, DST2, DST3>(lds, A1, 1, mu, sig, sig2s, tb);
   else
-    zmid_body<T, N, DCT2, DCT3>(lds, B3, 2, mu, sig, sig2s, tb);
+    xmid_body<T, N, DST2, DST3>(lds, A2, 2, mu, sig, sig2s, tb);
 }
 
 // z-pass of the right-hand side: scale by sigma_m / Lambda_m, inverse z (KI)
 template <typename T, int N, int KI>
-__global__ __launch_bounds__(NT) void k_zscale_inv(const T* __restrict__ in, T* __restrict__ out, int m, double mu,
+__global__ __launch_bounds__(256) void k_zscale_inv(const T* __restrict__ in, T* __restrict__ out, int m, double mu,
                                                    const double* sig, const double* sig2s, Tab<T> tb) {
   extern __shared__ __align__(16) unsigned char smem[];
   T* lds = reinterpret_cast<T*>(smem);
-  constexpr int W = TileShape<T, N>::W, RS = N + 1;
-  const TileAddr a = tile_addr<T, N>(2, blockIdx.x);
-  load_tile<T, N>(lds, in, 2, a);
+  using S = TileCfg<T, N, KI>;
+  constexpr int W = S::W, RS = N + 1, NT = S::NT;
+  const TileAddr a = tile_addr<W, N>(2, blockIdx.x);
+  load_tile<T, N, NT>(lds, in, 2, a);
   for (int e = threadIdx.x; e < W * N; e += NT) {
     const int p = e / N, k = e - p * N;
     const int q = blockIdx.x * W + p;
@@ -154,63 +204,54 @@ __global__ __launch_bounds__(NT) void k_zscale_inv(const T* __restrict__ in, T* 
     lds[p * RS + k] *= T(sg / (mu * lam));
   }
   __syncthreads();
-  transform_tile<T, N, KI>(lds, tb);
-  for (int e = threadIdx.x; e < W * N; e += NT) {
-    const int p = e / N, n = e - p * N;
-    out[a.base + p * N + n] = lds[p * RS + n];
-  }
+  transform_store<T, N, KI>(lds, LdsSrc<T, N>{lds}, tb, 2, [&](int p, int n, T v) { out[a.base + p * N + n] = v; });
 }
 
 // ---------------------------------------------------------------------------------------
-// CG x-passes with fused vector updates
+// CG z-passes with fused vector updates
 // ---------------------------------------------------------------------------------------
+// d = r + beta d_old (written back) and T1 = DST-II_z(d)
 template <typename T, int N>
-__global__ __launch_bounds__(NT) void k_xfwd_cg(const T* __restrict__ r, T* __restrict__ d, T* __restrict__ A,
+__global__ __launch_bounds__(256) void k_zfwd_cg(const T* __restrict__ r, T* __restrict__ d, T* __restrict__ T1,
                                                 const double* __restrict__ scal, Tab<T> tb) {
   extern __shared__ __align__(16) unsigned char smem[];
   T* lds = reinterpret_cast<T*>(smem);
-  constexpr int W = TileShape<T, N>::W, RS = N + 1;
+  using S = TileCfg<T, N, DST2>;
+  constexpr int W = S::W, RS = N + 1, NT = S::NT;
   const T beta = T(scal[2]);
-  const TileAddr a = tile_addr<T, N>(0, blockIdx.x);
+  const TileAddr a = tile_addr<W, N>(2, blockIdx.x);
   for (int e = threadIdx.x; e < W * N; e += NT) {
-    int p, n;
-    tile_elem<T, N>(0, e, p, n);
-    const long gi = a.base + p * a.pstride + n * a.nstride;
+    const int p = e / N, n = e - p * N;
+    const long gi = a.base + (long)p * N + n;
     const T v = r[gi] + beta * d[gi];
     d[gi] = v;
     lds[p * RS + n] = v;
   }
   __syncthreads();
-  transform_tile<T, N, DCT2>(lds, tb);
-  for (int e = threadIdx.x; e < W * N; e += NT) {
-    int p, n;
-    tile_elem<T, N>(0, e, p, n);
-    A[a.base + p * a.pstride + n * a.nstride] = lds[p * RS + n];
-  }
+  transform_store<T, N, DST2>(lds, LdsSrc<T, N>{lds}, tb, 2, [&](int p, int n, T v) { T1[a.base + p * N + n] = v; });
 }
 
+// q += DCT-III_z(B) + c d; per-block partial sums of d.q, q, d
 template <typename T, int N>
-__global__ __launch_bounds__(NT) void k_xinv_cg(const T* __restrict__ B, T* __restrict__ q, const T* __restrict__ d,
+__global__ __launch_bounds__(256) void k_zinv_cg(const T* __restrict__ B, T* __restrict__ q, const T* __restrict__ d,
                                                 double c, double* __restrict__ partials, Tab<T> tb) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ double red[NT / 64];
+  __shared__ double red[4];
   T* lds = reinterpret_cast<T*>(smem);
-  constexpr int W = TileShape<T, N>::W, RS = N + 1;
-  const TileAddr a = tile_addr<T, N>(0, blockIdx.x);
-  load_tile<T, N>(lds, B, 0, a);
-  transform_tile<T, N, DST3>(lds, tb);
+  using S = TileCfg<T, N, DCT3>;
+  constexpr int W = S::W, NT = S::NT;
+  const TileAddr a = tile_addr<W, N>(2, blockIdx.x);
+  load_tile<T, N, NT>(lds, B, 2, a);
   double sdq = 0, sq = 0, sd = 0;
-  for (int e = threadIdx.x; e < W * N; e += NT) {
-    int p, n;
-    tile_elem<T, N>(0, e, p, n);
-    const long gi = a.base + p * a.pstride + n * a.nstride;
+  transform_store<T, N, DCT3>(lds, LdsSrc<T, N>{lds}, tb, 2, [&](int p, int n, T v) {
+    const long gi = a.base + (long)p * N + n;
     const T dv = d[gi];
-    const T qv = q[gi] + lds[p * RS + n] + T(c) * dv;
+    const T qv = q[gi] + v + T(c) * dv;
     q[gi] = qv;
     sdq += (double)dv * (double)qv;
     sq += (double)qv;
     sd += (double)dv;
-  }
+  });
   double t0 = block_sum(sdq, red);
   double t1 = block_sum(sq, red);
   double t2 = block_sum(sd, red);
@@ -222,13 +263,13 @@ __global__ __launch_bounds__(NT) void k_xinv_cg(const T* __restrict__ B, T* __re
 }
 
 template <typename T>
-__global__ __launch_bounds__(NT) void k_cg_update(int64_t M, T* __restrict__ x, T* __restrict__ r,
+__global__ __launch_bounds__(EW_NT) void k_cg_update(int64_t M, T* __restrict__ x, T* __restrict__ r,
                                                   const T* __restrict__ d, const T* __restrict__ q,
                                                   const double* __restrict__ scal, double* __restrict__ partials) {
-  __shared__ double red[NT / 64];
+  __shared__ double red[EW_NT / 64];
   const T alpha = T(scal[1]), mq = T(scal[3]);
   double s = 0;
-  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < M; i += (int64_t)gridDim.x * NT) {
+  for (int64_t i = (int64_t)blockIdx.x * EW_NT + threadIdx.x; i < M; i += (int64_t)gridDim.x * EW_NT) {
     x[i] += alpha * d[i];
     const T rv = r[i] - alpha * (q[i] - mq);
     r[i] = rv;
@@ -239,31 +280,31 @@ __global__ __launch_bounds__(NT) void k_cg_update(int64_t M, T* __restrict__ x, 
 }
 
 template <typename T>
-__global__ __launch_bounds__(NT) void k_dot_partials(int64_t M, const T* __restrict__ a, const T* __restrict__ b,
+__global__ __launch_bounds__(EW_NT) void k_dot_partials(int64_t M, const T* __restrict__ a, const T* __restrict__ b,
                                                      double* __restrict__ partials) {
-  __shared__ double red[NT / 64];
+  __shared__ double red[EW_NT / 64];
   double s = 0;
-  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < M; i += (int64_t)gridDim.x * NT)
+  for (int64_t i = (int64_t)blockIdx.x * EW_NT + threadIdx.x; i < M; i += (int64_t)gridDim.x * EW_NT)
     s += (double)a[i] * (double)b[i];
   double t = block_sum(s, red);
   if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
 template <typename T>
-__global__ __launch_bounds__(NT) void k_sum_partials(int64_t M, const T* __restrict__ a, double* __restrict__ partials) {
-  __shared__ double red[NT / 64];
+__global__ __launch_bounds__(EW_NT) void k_sum_partials(int64_t M, const T* __restrict__ a, double* __restrict__ partials) {
+  __shared__ double red[EW_NT / 64];
   double s = 0;
-  for (int64_t i = (int64_t)blockIdx.x * NT + threadIdx.x; i < M; i += (int64_t)gridDim.x * NT) s += (double)a[i];
+  for (int64_t i = (int64_t)blockIdx.x * EW_NT + threadIdx.x; i < M; i += (int64_t)gridDim.x * EW_NT) s += (double)a[i];
   double t = block_sum(s, red);
   if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
-__global__ __launch_bounds__(NT) void k_reduce(const double* __restrict__ partials, int nparts, int nper,
+__global__ __launch_bounds__(EW_NT) void k_reduce(const double* __restrict__ partials, int nparts, int nper,
                                                double* __restrict__ scal, int op, int stokes, int64_t M,
                                                double* __restrict__ out) {
-  __shared__ double red[NT / 64];
+  __shared__ double red[EW_NT / 64];
   double acc[3] = {0, 0, 0};
-  for (int i = threadIdx.x; i < nparts; i += NT)
+  for (int i = threadIdx.x; i < nparts; i += EW_NT)
     for (int c = 0; c < nper; ++c) acc[c] += partials[(int64_t)i * nper + c];
   double tot[3];
   for (int c = 0; c < 3; ++c) tot[c] = block_sum(c < nper ? acc[c] : 0.0, red);
@@ -587,10 +628,11 @@ static void ensure_lds(K kernel, size_t bytes) {
 
 template <typename T, int N, int KIND, bool ACC>
 static hipError_t pass_n(int axis, const T* in, T* out, const Tab<T>& tb, hipStream_t s) {
-  const size_t lds = TileLDS<T, N, KIND>::BYTES;
-  const int blocks = N * N / TileShape<T, N>::W;
+  using S = TileCfg<T, N, KIND>;
+  const size_t lds = S::BYTES;
+  const int blocks = N * N / S::W;
   ensure_lds(k_pass<T, N, KIND, ACC>, lds);
-  hipLaunchKernelGGL((k_pass<T, N, KIND, ACC>), dim3(blocks), dim3(NT), lds, s, in, out, axis, tb);
+  hipLaunchKernelGGL((k_pass<T, N, KIND, ACC>), dim3(blocks), dim3(S::NT), lds, s, in, out, axis, tb);
   return hipGetLastError();
 }
 
@@ -627,15 +669,16 @@ hipError_t launch_zscale_inv(int N, int m, int wkind, const T* in, T* out, doubl
   const Tab<T> t = tab_of(tb);
 #define KFBI_M(NN)                                                                                          \
   {                                                                                                         \
-    const int blocks = NN * NN / TileShape<T, NN>::W;                                                           \
-    const size_t lds = TileLDS<T, NN, DCT3>::BYTES;                                                         \
+    using S = TileCfg<T, NN, DCT3>;                                                                         \
+    const int blocks = NN * NN / S::W;                                                                      \
+    const size_t lds = S::BYTES;                                                                            \
     ensure_lds(k_zscale_inv<T, NN, DCT3>, lds);                                                             \
     ensure_lds(k_zscale_inv<T, NN, DST3>, lds);                                                             \
     if (m == 2)                                                                                             \
-      hipLaunchKernelGGL((k_zscale_inv<T, NN, DCT3>), dim3(blocks), dim3(NT), lds, s, in, out, m, mu, tb.sig, \
+      hipLaunchKernelGGL((k_zscale_inv<T, NN, DCT3>), dim3(blocks), dim3(S::NT), lds, s, in, out, m, mu, tb.sig, \
                          tb.sig2s, t);                                                                      \
     else                                                                                                    \
-      hipLaunchKernelGGL((k_zscale_inv<T, NN, DST3>), dim3(blocks), dim3(NT), lds, s, in, out, m, mu, tb.sig, \
+      hipLaunchKernelGGL((k_zscale_inv<T, NN, DST3>), dim3(blocks), dim3(S::NT), lds, s, in, out, m, mu, tb.sig, \
                          tb.sig2s, t);                                                                      \
   }
   KFBI_DISPATCH_N(N, KFBI_M)
@@ -644,14 +687,15 @@ hipError_t launch_zscale_inv(int N, int m, int wkind, const T* in, T* out, doubl
 }
 
 template <typename T>
-hipError_t launch_zmid(int N, T* A1, T* B2, T* B3, double mu, const DevTables<T>& tb, hipStream_t s) {
+hipError_t launch_xmid(int N, T* A0, T* A1, T* A2, double mu, const DevTables<T>& tb, hipStream_t s) {
   const Tab<T> t = tab_of(tb);
 #define KFBI_M(NN)                                                                                              \
   {                                                                                                             \
-    const int blocks = NN * NN / TileShape<T, NN>::W;                                                               \
-    const size_t lds = TileLDS<T, NN, DCT2>::BYTES;                                                             \
-    ensure_lds(k_zmid<T, NN>, lds);                                                                             \
-    hipLaunchKernelGGL((k_zmid<T, NN>), dim3(blocks, 3), dim3(NT), lds, s, A1, B2, B3, mu, tb.sig, tb.sig2s, t); \
+    using S = TileCfg<T, NN, DCT2>;                                                                             \
+    const int blocks = NN * NN / S::W;                                                                          \
+    const size_t lds = S::BYTES;                                                                                \
+    ensure_lds(k_xmid<T, NN>, lds);                                                                             \
+    hipLaunchKernelGGL((k_xmid<T, NN>), dim3(blocks, 3), dim3(S::NT), lds, s, A0, A1, A2, mu, tb.sig, tb.sig2s, t); \
   }
   KFBI_DISPATCH_N(N, KFBI_M)
 #undef KFBI_M
@@ -659,32 +703,34 @@ hipError_t launch_zmid(int N, T* A1, T* B2, T* B3, double mu, const DevTables<T>
 }
 
 template <typename T>
-hipError_t launch_xfwd_cg(int N, const T* r, T* d, T* A, const double* scal, const DevTables<T>& tb, hipStream_t s) {
+hipError_t launch_zfwd_cg(int N, const T* r, T* d, T* T1, const double* scal, const DevTables<T>& tb, hipStream_t s) {
   const Tab<T> t = tab_of(tb);
 #define KFBI_M(NN)                                                                                  \
   {                                                                                                 \
-    const int blocks = NN * NN / TileShape<T, NN>::W;                                                   \
-    const size_t lds = TileLDS<T, NN, DCT2>::BYTES;                                                 \
-    ensure_lds(k_xfwd_cg<T, NN>, lds);                                                              \
-    hipLaunchKernelGGL((k_xfwd_cg<T, NN>), dim3(blocks), dim3(NT), lds, s, r, d, A, scal, t);       \
+    using S = TileCfg<T, NN, DST2>;                                                                 \
+    const int blocks = NN * NN / S::W;                                                              \
+    const size_t lds = S::BYTES;                                                                    \
+    ensure_lds(k_zfwd_cg<T, NN>, lds);                                                              \
+    hipLaunchKernelGGL((k_zfwd_cg<T, NN>), dim3(blocks), dim3(S::NT), lds, s, r, d, T1, scal, t);   \
   }
   KFBI_DISPATCH_N(N, KFBI_M)
 #undef KFBI_M
   return hipGetLastError();
 }
 
-int xinv_blocks(int N, int elem_size) { return N * N / std::min(128 / elem_size, N); }
+int zinv_blocks(int N, int elem_size) { return N * N / std::min(128 / elem_size, N); }
 
 template <typename T>
-hipError_t launch_xinv_cg(int N, const T* B, T* q, const T* d, double c, double* partials, const DevTables<T>& tb,
+hipError_t launch_zinv_cg(int N, const T* B, T* q, const T* d, double c, double* partials, const DevTables<T>& tb,
                           hipStream_t s) {
   const Tab<T> t = tab_of(tb);
 #define KFBI_M(NN)                                                                                   \
   {                                                                                                  \
-    const int blocks = NN * NN / TileShape<T, NN>::W;                                                    \
-    const size_t lds = TileLDS<T, NN, DST3>::BYTES;                                                  \
-    ensure_lds(k_xinv_cg<T, NN>, lds);                                                               \
-    hipLaunchKernelGGL((k_xinv_cg<T, NN>), dim3(blocks), dim3(NT), lds, s, B, q, d, c, partials, t); \
+    using S = TileCfg<T, NN, DCT3>;                                                                  \
+    const int blocks = NN * NN / S::W;                                                               \
+    const size_t lds = S::BYTES;                                                                     \
+    ensure_lds(k_zinv_cg<T, NN>, lds);                                                               \
+    hipLaunchKernelGGL((k_zinv_cg<T, NN>), dim3(blocks), dim3(S::NT), lds, s, B, q, d, c, partials, t); \
   }
   KFBI_DISPATCH_N(N, KFBI_M)
 #undef KFBI_M
@@ -694,7 +740,7 @@ hipError_t launch_xinv_cg(int N, const T* B, T* q, const T* d, double c, double*
 template <typename T>
 hipError_t launch_cg_update(int64_t M, T* x, T* r, const T* d, const T* q, const double* scal, double* partials,
                             int nblocks, hipStream_t s) {
-  hipLaunchKernelGGL((k_cg_update<T>), dim3(nblocks), dim3(NT), 0, s, M, x, r, d, q, scal, partials);
+  hipLaunchKernelGGL((k_cg_update<T>), dim3(nblocks), dim3(EW_NT), 0, s, M, x, r, d, q, scal, partials);
   return hipGetLastError();
 }
 
@@ -711,18 +757,18 @@ hipError_t launch_backsub_combine(int N, int m, const T* F, const T* P, T* G, do
 
 hipError_t launch_reduce(const double* partials, int nparts, int nper, double* scal, int op, int stokes, int64_t M,
                          hipStream_t s, double* out) {
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(NT), 0, s, partials, nparts, nper, scal, op, stokes, M, out);
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(EW_NT), 0, s, partials, nparts, nper, scal, op, stokes, M, out);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_dot_partials(int64_t M, const T* a, const T* b, double* partials, int nblocks, hipStream_t s) {
-  hipLaunchKernelGGL((k_dot_partials<T>), dim3(nblocks), dim3(NT), 0, s, M, a, b, partials);
+  hipLaunchKernelGGL((k_dot_partials<T>), dim3(nblocks), dim3(EW_NT), 0, s, M, a, b, partials);
   return hipGetLastError();
 }
 template <typename T>
 hipError_t launch_sum_partials(int64_t M, const T* a, double* partials, int nblocks, hipStream_t s) {
-  hipLaunchKernelGGL((k_sum_partials<T>), dim3(nblocks), dim3(NT), 0, s, M, a, partials);
+  hipLaunchKernelGGL((k_sum_partials<T>), dim3(nblocks), dim3(EW_NT), 0, s, M, a, partials);
   return hipGetLastError();
 }
 template <typename T>
@@ -836,9 +882,9 @@ hipError_t launch_check_finite(int64_t n, const double* a, int* flag, hipStream_
 #define KFBI_INST(T)                                                                                                 \
   template hipError_t launch_pass<T>(int, int, int, const T*, T*, bool, const DevTables<T>&, hipStream_t);           \
   template hipError_t launch_zscale_inv<T>(int, int, int, const T*, T*, double, const DevTables<T>&, hipStream_t);   \
-  template hipError_t launch_zmid<T>(int, T*, T*, T*, double, const DevTables<T>&, hipStream_t);                     \
-  template hipError_t launch_xfwd_cg<T>(int, const T*, T*, T*, const double*, const DevTables<T>&, hipStream_t);     \
-  template hipError_t launch_xinv_cg<T>(int, const T*, T*, const T*, double, double*, const DevTables<T>&,           \
+  template hipError_t launch_xmid<T>(int, T*, T*, T*, double, const DevTables<T>&, hipStream_t);                     \
+  template hipError_t launch_zfwd_cg<T>(int, const T*, T*, T*, const double*, const DevTables<T>&, hipStream_t);     \
+  template hipError_t launch_zinv_cg<T>(int, const T*, T*, const T*, double, double*, const DevTables<T>&,           \
                                         hipStream_t);                                                                \
   template hipError_t launch_cg_update<T>(int64_t, T*, T*, const T*, const T*, const double*, double*, int,          \
                                           hipStream_t);                                                              \

@@ -7,18 +7,21 @@
 // are reordered (even samples ascending, odd samples descending) so that a length-N complex
 // FFT plus one twiddle per output gives the cosine sums (Makhoul's algorithm); DST-II is the
 // DCT-II of the sign-alternated pencil read backwards; DST-I is the FFT of the odd extension
-// of length 2N.  The complex FFT is a Stockham autosort FFT with radix-4 stages (and one
-// radix-2 stage when log2 L is odd), register staged so that one LDS buffer holds the data.
+// of length 2N.
+//
+// The complex FFT of length L = R1 * R2 is done in two register passes: each thread loads
+// R1 strided samples, does an R1-point DFT in registers and applies the L-point twiddles,
+// the results are transposed through LDS (rows padded by one element so the transposed
+// reads hit distinct banks), and each thread does an R2-point DFT in registers.  Small
+// DFTs are unrolled radix-4/2 butterflies with literal twiddles.
 //
 // A workgroup owns a tile of W real pencils (W*sizeof(T) = 128 bytes, so every row of the
 // tile along the contiguous z axis is one 128-byte segment), stored in LDS as rows of length
-// N + 1 (the padding breaks bank conflicts of the strided x/y loads).
+// N + 1.
 #pragma once
 #include <hip/hip_runtime.h>
 
 namespace kfbi {
-
-constexpr int NT = 256;  // threads per workgroup of every transform kernel
 
 enum Kind { DCT2 = 0, DST2 = 1, DCT3 = 2, DST3 = 3, DST1 = 4 };
 
@@ -34,97 +37,104 @@ struct Tab {
   const C2<T>* mk;   // e^{-i pi k / 2N}, k < N
   const T* sc;       // orthonormal DCT-II scale s_k: sqrt(1/N) (k=0), sqrt(2/N)
   const T* isc;      // 1 / s_k
+  const T* sg2;      // sigma_k^2 = (4/h^2) sin^2(pi k / 2N), k < N   (DCT-II / DST-I modes)
+  const T* sg2s;     // sigma_{k+1}^2, k < N                           (DST-II modes)
 };
 
 template <typename T>
-__device__ __forceinline__ C2<T> cmul(C2<T> a, C2<T> b) {
+__host__ __device__ __forceinline__ C2<T> cmul(C2<T> a, C2<T> b) {
   return {a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
 }
 
-// tile width: one 128-byte row segment, at most the grid size
-template <typename T, int N>
-struct TileShape {
-  static constexpr int W = (int)(128 / sizeof(T)) < N ? (int)(128 / sizeof(T)) : N;
-};
+__host__ __device__ constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
 
+// Tile configuration of one transform kind at grid size N.
 template <typename T, int N, int KIND>
-struct TileLDS {
-  static constexpr int W = TileShape<T, N>::W;
-  static constexpr int RS = N + 1;
-  static constexpr int L = (KIND == DST1) ? 2 * N : N;
-  static constexpr int NJ = W / 2;
+struct TileCfg {
+  static constexpr int W = (int)(128 / sizeof(T)) < N ? (int)(128 / sizeof(T)) : N;  // pencils
+  static constexpr int RS = N + 1;                                                  // row stride
+  static constexpr int L = (KIND == DST1) ? 2 * N : N;                              // FFT length
+  static constexpr int NJ = W / 2;                                                  // complex jobs
+  static constexpr int R1 = 1 << ((ilog2(L) + 1) / 2);                              // first radix
+  static constexpr int R2 = L / R1;                                                 // second radix
+  static constexpr int P2 = R2 + 1;                                                 // padded row
+  static constexpr int YS = R1 * P2 + 2;                     // job stride of the transpose buffer
+  static constexpr int ZS = L + 2;                           // job stride of the spectra
+  static constexpr int NT = (NJ * R2 > 256) ? 256 : (NJ * R2 > 64) ? NJ * R2 : 64;  // threads
   static constexpr int REALS_TILE = W * RS;
-  static constexpr int REALS_CPLX = NJ * L * 2;
-  static constexpr int REALS = REALS_TILE > REALS_CPLX ? REALS_TILE : REALS_CPLX;
+  static constexpr int REALS_Y = NJ * YS * 2;
+  static constexpr int REALS_Z = NJ * ZS * 2;
+  static constexpr int M1 = REALS_TILE > REALS_Y ? REALS_TILE : REALS_Y;
+  static constexpr int REALS = M1 > REALS_Z ? M1 : REALS_Z;
   static constexpr size_t BYTES = (size_t)REALS * sizeof(T);
 };
 
-// radix-R DFT in registers (R = 2 or 4); INV selects the sign of the exponent
+// cos(2 pi m / 32) from the first octant, exact at the quarter points
+__host__ __device__ constexpr double c32oct(int m) {
+  return m == 0 ? 1.0
+       : m == 1 ? 0.98078528040323043
+       : m == 2 ? 0.92387953251128674
+       : m == 3 ? 0.83146961230254524
+       : m == 4 ? 0.70710678118654752
+       : m == 5 ? 0.55557023301960218
+       : m == 6 ? 0.38268343236508977
+       : m == 7 ? 0.19509032201612826
+                : 0.0;
+}
+__host__ __device__ constexpr double cos32(int m) {
+  return (m & 31) <= 8 ? c32oct(m & 31)
+       : (m & 31) <= 16 ? -c32oct(16 - (m & 31))
+       : (m & 31) <= 24 ? -c32oct((m & 31) - 16)
+                        : c32oct(32 - (m & 31));
+}
+__host__ __device__ constexpr double sin32(int m) { return cos32(8 - m); }
+
+// W_R^m = exp(-+ 2 pi i m / R) for R dividing 32
 template <typename T, int R, bool INV>
-__device__ __forceinline__ void dft(C2<T>* v) {
+__host__ __device__ __forceinline__ C2<T> wR(int m) {
+  const int q = m * (32 / R);
+  return {T(cos32(q)), INV ? T(sin32(q)) : T(-sin32(q))};
+}
+
+// R-point DFT in registers, R in {1, 2, 4, 8, 16, 32}; INV selects the exponent sign
+template <typename T, int R, bool INV>
+__host__ __device__ __forceinline__ void dftR(C2<T>* v) {
   if constexpr (R == 2) {
-    C2<T> a = v[0], b = v[1];
+    const C2<T> a = v[0], b = v[1];
     v[0] = {a.x + b.x, a.y + b.y};
     v[1] = {a.x - b.x, a.y - b.y};
-  } else {
-    C2<T> a0 = {v[0].x + v[2].x, v[0].y + v[2].y};
-    C2<T> a1 = {v[0].x - v[2].x, v[0].y - v[2].y};
-    C2<T> a2 = {v[1].x + v[3].x, v[1].y + v[3].y};
-    C2<T> d = {v[1].x - v[3].x, v[1].y - v[3].y};
-    C2<T> a3 = INV ? C2<T>{-d.y, d.x} : C2<T>{d.y, -d.x};
+  } else if constexpr (R == 4) {
+    const C2<T> a0 = {v[0].x + v[2].x, v[0].y + v[2].y};
+    const C2<T> a1 = {v[0].x - v[2].x, v[0].y - v[2].y};
+    const C2<T> a2 = {v[1].x + v[3].x, v[1].y + v[3].y};
+    const C2<T> d = {v[1].x - v[3].x, v[1].y - v[3].y};
+    const C2<T> a3 = INV ? C2<T>{-d.y, d.x} : C2<T>{d.y, -d.x};
     v[0] = {a0.x + a2.x, a0.y + a2.y};
     v[1] = {a1.x + a3.x, a1.y + a3.y};
     v[2] = {a0.x - a2.x, a0.y - a2.y};
     v[3] = {a1.x - a3.x, a1.y - a3.y};
-  }
-}
-
-// one Stockham stage over NJ complex pencils of length L held in LDS
-template <typename T, int L, int NJ, int R, int NS, bool INV>
-__device__ __forceinline__ void stockham_stage(C2<T>* cb, const C2<T>* tw) {
-  constexpr int NBP = L / R;  // butterflies per pencil
-  constexpr int NB = NJ * NBP;
-  constexpr int PB = (NB + NT - 1) / NT;
-  const int tid = threadIdx.x;
-  C2<T> v[PB][R];
+  } else if constexpr (R > 4) {
+    // R = 4 * B:  n = B n1 + n2, k = k1 + 4 k2
+    constexpr int B = R / 4;
+    C2<T> t[R];
 #pragma unroll
-  for (int u = 0; u < PB; ++u) {
-    const int b = tid + u * NT;
-    if (NB % NT == 0 || b < NB) {
-      const int job = b / NBP, j = b - job * NBP, jm = j % NS;
+    for (int n2 = 0; n2 < B; ++n2) {
+      C2<T> u[4];
 #pragma unroll
-      for (int t = 0; t < R; ++t) {
-        C2<T> a = cb[job * L + j + t * NBP];
-        if (NS > 1) {
-          C2<T> w = tw[(L / (NS * R)) * jm * t];
-          if (INV) w.y = -w.y;
-          a = cmul(a, w);
-        }
-        v[u][t] = a;
-      }
+      for (int n1 = 0; n1 < 4; ++n1) u[n1] = v[B * n1 + n2];
+      dftR<T, 4, INV>(u);
+#pragma unroll
+      for (int k1 = 0; k1 < 4; ++k1) t[k1 * B + n2] = (n2 * k1 == 0) ? u[k1] : cmul(u[k1], wR<T, R, INV>(n2 * k1));
     }
-  }
-  __syncthreads();
 #pragma unroll
-  for (int u = 0; u < PB; ++u) {
-    const int b = tid + u * NT;
-    if (NB % NT == 0 || b < NB) {
-      const int job = b / NBP, j = b - job * NBP, jm = j % NS;
-      dft<T, R, INV>(v[u]);
-      const int idxD = (j / NS) * NS * R + jm;
+    for (int k1 = 0; k1 < 4; ++k1) {
+      C2<T> u[B];
 #pragma unroll
-      for (int t = 0; t < R; ++t) cb[job * L + idxD + t * NS] = v[u][t];
+      for (int n2 = 0; n2 < B; ++n2) u[n2] = t[k1 * B + n2];
+      dftR<T, B, INV>(u);
+#pragma unroll
+      for (int k2 = 0; k2 < B; ++k2) v[k1 + 4 * k2] = u[k2];
     }
-  }
-  __syncthreads();
-}
-
-template <typename T, int L, int NJ, int NS, bool INV>
-__device__ __forceinline__ void fft_stages(C2<T>* cb, const C2<T>* tw) {
-  if constexpr (NS < L) {
-    constexpr int R = (NS * 4 <= L) ? 4 : 2;
-    stockham_stage<T, L, NJ, R, NS, INV>(cb, tw);
-    fft_stages<T, L, NJ, NS * R, INV>(cb, tw);
   }
 }
 
@@ -135,123 +145,210 @@ __device__ __forceinline__ int perm_dst(int b, int N) {  // inverse reordering
   return (b & 1) ? N - 1 - (b >> 1) : (b >> 1);
 }
 
-// Transform the W real pencils of the tile in place (tile row p at lds[p * RS]).
-template <typename T, int N, int KIND>
-__device__ void transform_tile(T* lds, const Tab<T>& tb) {
-  using S = TileLDS<T, N, KIND>;
-  constexpr int W = S::W, RS = S::RS, L = S::L, NJ = S::NJ;
+// Sources of real pencil samples: pair(j, i) returns sample i of pencils 2j and 2j+1.
+template <typename T, int N>
+struct LdsSrc {  // tile rows in LDS (row stride N + 1)
+  const T* lds;
+  __device__ __forceinline__ C2<T> pair(int j, int i) const {
+    return {lds[(2 * j) * (N + 1) + i], lds[(2 * j + 1) * (N + 1) + i]};
+  }
+};
+template <typename T>
+struct GlobSrc {  // pencils adjacent in memory (x/y passes): one vector load per pair
+  const T* g;
+  long base, nstride;
+  __device__ __forceinline__ C2<T> pair(int j, int i) const {
+    return *reinterpret_cast<const C2<T>*>(g + base + (long)i * nstride + 2 * j);
+  }
+};
+
+// complex FFT input sample n of job j
+template <typename T, int N, int KIND, class Src>
+__device__ __forceinline__ C2<T> pre_sample(const Src& src, const Tab<T>& tb, int j, int n) {
+  if constexpr (KIND == DCT2 || KIND == DST2) {
+    const int b = perm_src(n, N);
+    C2<T> v = src.pair(j, b);
+    if (KIND == DST2 && (b & 1)) v = {-v.x, -v.y};
+    return v;
+  } else if constexpr (KIND == DCT3 || KIND == DST3) {
+    const int k = n;
+    // Y_k = X'_k / s_k and Y_{N-k} (Y_N = 0); X' = X (DCT-III) or X reversed (DST-III)
+    const int ik = (KIND == DST3) ? N - 1 - k : k;
+    const int ir = (KIND == DST3) ? k - 1 : N - k;  // index of X'_{N-k}
+    const T s1 = tb.isc[k];
+    const C2<T> y = src.pair(j, ik);
+    C2<T> yr = {T(0), T(0)};
+    if (k > 0) {
+      const T s2 = tb.isc[N - k];
+      const C2<T> t = src.pair(j, ir);
+      yr = {t.x * s2, t.y * s2};
+    }
+    // V = conj(mk_k) * (Y_k - i Y_{N-k}); the two pencils are combined as Va + i Vb
+    const C2<T> c = {tb.mk[k].x, -tb.mk[k].y};
+    const C2<T> Va = cmul(c, C2<T>{y.x * s1, -yr.x});
+    const C2<T> Vb = cmul(c, C2<T>{y.y * s1, -yr.y});
+    return {Va.x - Vb.y, Va.y + Vb.x};
+  } else {  // DST1: odd extension of length 2N (samples 0 and N are zero)
+    if (n == 0 || n == N) return {T(0), T(0)};
+    if (n < N) return src.pair(j, n);
+    const C2<T> v = src.pair(j, 2 * N - n);
+    return {-v.x, -v.y};
+  }
+}
+
+// Complex FFTs of the W/2 jobs of the tile; on return the spectra are in LDS at
+// cb[j * ZS + k] (natural order, length L).  LDS may alias the source (pass-1 samples are
+// staged in registers).  Every thread of the block (Cfg::NT) must call it.
+template <typename T, int N, int KIND, class Sampler>
+__device__ void fft_core(T* lds, Sampler&& sample, const Tab<T>& tb);
+
+template <typename T, int N, int KIND, class Src>
+__device__ __forceinline__ void fft_tile(T* lds, const Src& src, const Tab<T>& tb) {
+  fft_core<T, N, KIND>(lds, [&](int j, int n) { return pre_sample<T, N, KIND>(src, tb, j, n); }, tb);
+}
+
+// Same, with the complex FFT input given directly by sample(j, n) (it may read LDS).
+template <typename T, int N, int KIND, class Sampler>
+__device__ void fft_core(T* lds, Sampler&& sample, const Tab<T>& tb) {
+  using S = TileCfg<T, N, KIND>;
+  constexpr int L = S::L, NJ = S::NJ, R1 = S::R1, R2 = S::R2, P2 = S::P2, YS = S::YS, ZS = S::ZS, NT = S::NT;
   constexpr bool INV = (KIND == DCT3 || KIND == DST3);
   C2<T>* cb = reinterpret_cast<C2<T>*>(lds);
+  const C2<T>* tw = (L == N) ? tb.tw : tb.tw2;
   const int tid = threadIdx.x;
-  // ---------------- pre-processing: real tile -> complex sequences
+  // ---------------- pass 1: R1-point DFTs over stride-R2 samples, twiddle, transpose
   {
-    constexpr int CNT = NJ * L;
-    constexpr int PER = (CNT + NT - 1) / NT;
-    C2<T> r[PER];
+    constexpr int TASKS = NJ * R2;
+    constexpr int PT = (TASKS + NT - 1) / NT;
+    C2<T> z[PT][R1];
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int e = tid + u * NT;
-      if (CNT % NT == 0 || e < CNT) {
-        const int j = e / L, n = e - j * L;
-        const T* ra = lds + (2 * j) * RS;
-        const T* rb = lds + (2 * j + 1) * RS;
-        C2<T> z;
-        if constexpr (KIND == DCT2 || KIND == DST2) {
-          const int b = perm_src(n, N);
-          T va = ra[b], vb = rb[b];
-          if (KIND == DST2 && (b & 1)) {
-            va = -va;
-            vb = -vb;
-          }
-          z = {va, vb};
-        } else if constexpr (KIND == DCT3 || KIND == DST3) {
-          const int k = n;
-          // Y_k = X'_k / s_k and Y_{N-k} (Y_N = 0); X' = X (DCT-III) or X reversed (DST-III)
-          const int ik = (KIND == DST3) ? N - 1 - k : k;
-          const int ir = (KIND == DST3) ? k - 1 : N - k;  // index of X'_{N-k}
-          const T s1 = tb.isc[k];
-          const T s2 = (k > 0) ? tb.isc[N - k] : T(0);
-          const T ya = ra[ik] * s1, yb = rb[ik] * s1;
-          const T yra = (k > 0) ? ra[ir] * s2 : T(0);
-          const T yrb = (k > 0) ? rb[ir] * s2 : T(0);
-          // V = conj(mk_k) * (Y_k - i Y_{N-k})
-          const C2<T> c = {tb.mk[k].x, -tb.mk[k].y};
-          const C2<T> Va = cmul(c, C2<T>{ya, -yra});
-          const C2<T> Vb = cmul(c, C2<T>{yb, -yrb});
-          z = {Va.x - Vb.y, Va.y + Vb.x};
-        } else {  // DST1: odd extension of length 2N (samples 0 and N are zero)
-          T va, vb;
-          if (n == 0 || n == N) {
-            va = vb = T(0);
-          } else if (n < N) {
-            va = ra[n];
-            vb = rb[n];
-          } else {
-            va = -ra[2 * N - n];
-            vb = -rb[2 * N - n];
-          }
-          z = {va, vb};
+    for (int u = 0; u < PT; ++u) {
+      const int task = tid + u * NT;
+      if (TASKS % NT == 0 || task < TASKS) {
+        const int j = task % NJ, n2 = task / NJ;
+#pragma unroll
+        for (int n1 = 0; n1 < R1; ++n1) z[u][n1] = sample(j, R2 * n1 + n2);
+        dftR<T, R1, INV>(z[u]);
+#pragma unroll
+        for (int k1 = 1; k1 < R1; ++k1) {
+          C2<T> w = tw[n2 * k1];
+          if (INV) w.y = -w.y;
+          z[u][k1] = cmul(z[u][k1], w);
         }
-        r[u] = z;
       }
     }
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int e = tid + u * NT;
-      if (CNT % NT == 0 || e < CNT) cb[e] = r[u];
+    for (int u = 0; u < PT; ++u) {
+      const int task = tid + u * NT;
+      if (TASKS % NT == 0 || task < TASKS) {
+        const int j = task % NJ, n2 = task / NJ;
+#pragma unroll
+        for (int k1 = 0; k1 < R1; ++k1) cb[j * YS + k1 * P2 + n2] = z[u][k1];
+      }
     }
     __syncthreads();
   }
-  // ---------------- complex FFT of length L
-  fft_stages<T, L, NJ, 1, INV>(cb, (L == N) ? tb.tw : tb.tw2);
-  // ---------------- post-processing: complex spectra -> real tile
+  // ---------------- pass 2: R2-point DFTs, natural-order output
   {
-    constexpr int CNT = W * N;
-    constexpr int PER = (CNT + NT - 1) / NT;
-    T o[PER];
+    constexpr int TASKS = NJ * R1;
+    constexpr int PT = (TASKS + NT - 1) / NT;
+    C2<T> z[PT][R2];
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int e = tid + u * NT;
-      if (CNT % NT == 0 || e < CNT) {
-        const int p = e / N, k = e - p * N;
-        const int j = p >> 1, which = p & 1;
-        const C2<T>* Z = cb + j * L;
-        T val;
-        if constexpr (KIND == DCT2 || KIND == DST2) {
-          const int kk = (KIND == DST2) ? N - 1 - k : k;
-          const C2<T> a = Z[kk], b = Z[(N - kk) & (N - 1)];
-          C2<T> V;
-          if (which == 0)
-            V = {(a.x + b.x) * T(0.5), (a.y - b.y) * T(0.5)};
-          else
-            V = {(a.y + b.y) * T(0.5), (b.x - a.x) * T(0.5)};
-          const C2<T> m = tb.mk[kk];
-          val = tb.sc[kk] * (m.x * V.x - m.y * V.y);
-        } else if constexpr (KIND == DCT3 || KIND == DST3) {
-          const C2<T> z = Z[perm_dst(k, N)];
-          val = (which ? z.y : z.x) * (T(1) / T(N));
-          if (KIND == DST3 && (k & 1)) val = -val;
-        } else {
-          const C2<T> z = Z[k];
-          const T y = which ? z.x * T(0.5) : -z.y * T(0.5);
-          val = (k == 0) ? T(0) : y * tb.sc[1];  // sqrt(2/N)
-        }
-        o[u] = val;
+    for (int u = 0; u < PT; ++u) {
+      const int task = tid + u * NT;
+      if (TASKS % NT == 0 || task < TASKS) {
+        const int j = task % NJ, k1 = task / NJ;
+#pragma unroll
+        for (int n2 = 0; n2 < R2; ++n2) z[u][n2] = cb[j * YS + k1 * P2 + n2];
+        dftR<T, R2, INV>(z[u]);
       }
     }
     __syncthreads();
 #pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int e = tid + u * NT;
-      if (CNT % NT == 0 || e < CNT) {
-        const int p = e / N, k = e - p * N;
-        lds[p * RS + k] = o[u];
+    for (int u = 0; u < PT; ++u) {
+      const int task = tid + u * NT;
+      if (TASKS % NT == 0 || task < TASKS) {
+        const int j = task % NJ, k1 = task / NJ;
+#pragma unroll
+        for (int k2 = 0; k2 < R2; ++k2) cb[j * ZS + k1 + R1 * k2] = z[u][k2];
       }
     }
     __syncthreads();
   }
 }
+
+// Post-processing value of output element (p, k) from the spectra in LDS.
+template <typename T, int N, int KIND>
+__device__ __forceinline__ T post_value(const T* lds, const Tab<T>& tb, int p, int k) {
+  constexpr int ZS = TileCfg<T, N, KIND>::ZS;
+  const C2<T>* Z = reinterpret_cast<const C2<T>*>(lds) + (p >> 1) * ZS;
+  const int which = p & 1;
+  if constexpr (KIND == DCT2 || KIND == DST2) {
+    const int kk = (KIND == DST2) ? N - 1 - k : k;
+    const C2<T> a = Z[kk], b = Z[(N - kk) & (N - 1)];
+    C2<T> V;
+    if (which == 0)
+      V = {(a.x + b.x) * T(0.5), (a.y - b.y) * T(0.5)};
+    else
+      V = {(a.y + b.y) * T(0.5), (b.x - a.x) * T(0.5)};
+    const C2<T> m = tb.mk[kk];
+    return tb.sc[kk] * (m.x * V.x - m.y * V.y);
+  } else if constexpr (KIND == DCT3 || KIND == DST3) {
+    const C2<T> z = Z[perm_dst(k, N)];
+    T val = (which ? z.y : z.x) * (T(1) / T(N));
+    if (KIND == DST3 && (k & 1)) val = -val;
+    return val;
+  } else {
+    const C2<T> z = Z[k];
+    const T y = which ? z.x * T(0.5) : -z.y * T(0.5);
+    return (k == 0) ? T(0) : y * tb.sc[1];  // sqrt(2/N)
+  }
+}
+
+// Transform from the source and hand every output value to store(p, k, value) without
+// staging, in the coalescing order of the given axis (the store must not write LDS).
+template <typename T, int N, int KIND, class Src, class Store>
+__device__ __forceinline__ void transform_store(T* lds, const Src& src, const Tab<T>& tb, int axis, Store&& store) {
+  using S = TileCfg<T, N, KIND>;
+  constexpr int W = S::W, NT = S::NT;
+  fft_tile<T, N, KIND>(lds, src, tb);
+  for (int e = threadIdx.x; e < W * N; e += NT) {
+    int p, k;
+    if (axis == 2) {
+      p = e / N;
+      k = e - p * N;
+    } else {
+      k = e / W;
+      p = e - k * W;
+    }
+    store(p, k, post_value<T, N, KIND>(lds, tb, p, k));
+  }
+}
+
+// Transform the W real pencils of the LDS tile in place (tile row p at lds[p * (N + 1)]).
+template <typename T, int N, int KIND>
+__device__ void transform_tile(T* lds, const Tab<T>& tb) {
+  using S = TileCfg<T, N, KIND>;
+  constexpr int W = S::W, RS = S::RS, NT = S::NT;
+  fft_tile<T, N, KIND>(lds, LdsSrc<T, N>{lds}, tb);
+  constexpr int CNT = W * N;
+  constexpr int PER = (CNT + NT - 1) / NT;
+  T o[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = threadIdx.x + u * NT;
+    if (CNT % NT == 0 || e < CNT) o[u] = post_value<T, N, KIND>(lds, tb, e / N, e % N);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = threadIdx.x + u * NT;
+    if (CNT % NT == 0 || e < CNT) lds[(e / N) * RS + (e % N)] = o[u];
+  }
+  __syncthreads();
+}
+
 
 // Tile addressing.  Field layout [x][y][z], z contiguous, N^3 elements.
 //  axis 2: tile = W consecutive z-pencils (pencil q = blk*W + p, (x, y) = (q / N, q % N))
@@ -261,9 +358,8 @@ struct TileAddr {
   long base, pstride, nstride;
 };
 
-template <typename T, int N>
+template <int W, int N>
 __device__ __forceinline__ TileAddr tile_addr(int axis, int blk) {
-  constexpr int W = TileShape<T, N>::W;
   TileAddr a;
   if (axis == 2) {
     a.base = (long)blk * W * N;
@@ -284,9 +380,8 @@ __device__ __forceinline__ TileAddr tile_addr(int axis, int blk) {
 }
 
 // element e of the tile in coalescing order -> (p, n)
-template <typename T, int N>
+template <int W, int N>
 __device__ __forceinline__ void tile_elem(int axis, int e, int& p, int& n) {
-  constexpr int W = TileShape<T, N>::W;
   if (axis == 2) {
     p = e / N;
     n = e - p * N;
