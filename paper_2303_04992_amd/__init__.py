@@ -23,6 +23,10 @@ LIB_PATH = os.path.join(_HERE, "libkfbi.so")
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"libkfbi.so not found at {LIB_PATH}; build it with python paper_2303_04992_amd/build.py")
 
+# PyTorch owns the device memory and streams the library works on: load it first so that the
+# process has a single HIP runtime (libkfbi.so binds to the one already loaded).
+import torch  # noqa: E402,F401
+
 _lib = C.CDLL(LIB_PATH)
 
 STOKES, NAVIER = 0, 1
@@ -75,6 +79,8 @@ _sig = {
     "kfbi_interface_solve": (C.c_int, [_P, _P, C.c_int32, _P, _P, C.POINTER(Info)]),
     "kfbi_time_pass": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double),
                                  C.POINTER(C.c_double)]),
+    "kfbi_profile_pass": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int64),
+                                    C.POINTER(C.c_double), C.POINTER(C.c_double)]),
     "kfbi_plan_create": (C.c_int, [C.POINTER(Config), C.POINTER(_P)]),
     "kfbi_plan_destroy": (None, [_P]),
     "kfbi_plan_get": (C.c_int64, [_P, C.c_char_p, _P]),
@@ -244,6 +250,14 @@ class Operator:
         ms, by = C.c_double(), C.c_double()
         self._check(_lib.kfbi_time_pass(self._h, int(kind), int(axis), int(reps), C.byref(ms), C.byref(by)))
         return ms.value, by.value
+
+    def profile_pass(self, kind=3, axis=1, enable=True):
+        """Start (enable) or stop live event timing of one transform pass inside evaluations;
+        returns (launches, total_ms, bytes_per_launch) recorded since the previous call."""
+        n, ms, by = C.c_int64(), C.c_double(), C.c_double()
+        self._check(_lib.kfbi_profile_pass(self._h, int(kind), int(axis), int(bool(enable)), C.byref(n),
+                                           C.byref(ms), C.byref(by)))
+        return n.value, ms.value, by.value
 
     def split_u(self, u):
         """Packed exported velocity -> (u1 (N+1,N,N), u2 (N,N+1,N), u3 (N,N,N+1))."""

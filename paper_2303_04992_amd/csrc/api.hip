@@ -74,6 +74,12 @@ struct MacSolver {
   double* host_rr = nullptr;  // pinned, 2 slots
   hipEvent_t ev[2] = {nullptr, nullptr};
   int nparts_x = 0, nparts_u = 1024;
+  // live timing of one transform-pass kind with HIP events on the solver stream
+  int prof_kind = -1, prof_axis = -1;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;
+  size_t prof_used = 0;
+  int64_t prof_launches = 0;
+  double prof_ms = 0;
 
   void init(int N_, double h, int pde_, double mu_, double c_, hipStream_t s_, std::vector<void*>& owned) {
     N = N_;
@@ -139,13 +145,39 @@ struct MacSolver {
   void release() {
     if (host_rr) (void)hipHostFree(host_rr);
     host_rr = nullptr;
+    for (auto& e : prof_ev) {
+      (void)hipEventDestroy(e.first);
+      (void)hipEventDestroy(e.second);
+    }
+    prof_ev.clear();
     for (auto& e : ev)
       if (e) (void)hipEventDestroy(e);
     ev[0] = ev[1] = nullptr;
   }
 
   void pass(int kind, int axis, const T* in, T* out, bool acc = false) {
+    const bool timed = (kind == prof_kind && axis == prof_axis && !acc);
+    if (timed) {
+      if (prof_used == prof_ev.size()) {
+        hipEvent_t a, b;
+        HIPCHK(hipEventCreate(&a));
+        HIPCHK(hipEventCreate(&b));
+        prof_ev.push_back({a, b});
+      }
+      HIPCHK(hipEventRecord(prof_ev[prof_used].first, s));
+    }
     HIPCHK(launch_pass<T>(N, kind, axis, in, out, acc, tb, s));
+    if (timed) HIPCHK(hipEventRecord(prof_ev[prof_used++].second, s));
+  }
+  // accumulate the recorded launch durations (call after the stream has drained)
+  void prof_collect() {
+    for (size_t i = 0; i < prof_used; ++i) {
+      float ms = 0;
+      HIPCHK(hipEventElapsedTime(&ms, prof_ev[i].first, prof_ev[i].second));
+      prof_ms += ms;
+      ++prof_launches;
+    }
+    prof_used = 0;
   }
   void project_mean(T* v) {
     if (pde != KFBI_STOKES) return;
@@ -235,6 +267,10 @@ struct MacSolver {
       pass(m == 0 ? DST1 : DST3, 0, A, u + m * M);
     }
     if (p) HIPCHK(hipMemcpyAsync(p, x, M * sizeof(T), hipMemcpyDeviceToDevice, s));
+    if (prof_used) {
+      HIPCHK(hipStreamSynchronize(s));
+      prof_collect();
+    }
     return conv ? it : -1;
   }
 };
@@ -810,6 +846,27 @@ kfbi_status kfbi_interface_solve(kfbi_ctx* C, const double* phi, int32_t use_for
     if (u_ext) HIPCHK(launch_export_u(S.N, C->u, u_ext, C->s));
     if (p_ext) HIPCHK(hipMemcpyAsync(p_ext, C->p, S.M * sizeof(double), hipMemcpyDeviceToDevice, C->s));
     HIPCHK(hipStreamSynchronize(C->s));
+  });
+}
+
+kfbi_status kfbi_profile_pass(kfbi_ctx* C, int32_t kind, int32_t axis, int32_t enable, int64_t* launches,
+                              double* total_ms, double* bytes_per_launch) {
+  if (!C || kind < 0 || kind > 4 || axis < 0 || axis > 2) return KFBI_EINVAL;
+  return guarded(C, [&] {
+    auto go = [&](auto& sv) {
+      using T = std::remove_reference_t<decltype(*sv.A)>;
+      if (launches) *launches = sv.prof_launches;
+      if (total_ms) *total_ms = sv.prof_ms;
+      if (bytes_per_launch) *bytes_per_launch = 2.0 * (double)sv.M * sizeof(T);
+      sv.prof_kind = enable ? kind : -1;
+      sv.prof_axis = enable ? axis : -1;
+      sv.prof_launches = 0;
+      sv.prof_ms = 0;
+    };
+    if (C->mixed)
+      go(C->s32);
+    else
+      go(C->s64);
   });
 }
 
