@@ -141,8 +141,8 @@ kfbi_status kfbi_interface_solve(kfbi_ctx* ctx, const double* phi_dev, int32_t u
 kfbi_status kfbi_time_pass(kfbi_ctx* ctx, int32_t kind, int32_t axis, int32_t reps, double* avg_ms,
                            double* bytes_per_launch);
 
-/* Measurement helper: live timing of one transform-pass kernel (kind, axis as above) inside
- * the evaluations.  Calling it returns the launches and summed duration recorded since the
+/* Measurement helper: live timing of one transform-pass kernel (kind as above, axis 0..2 or
+ * -1 for every axis) inside the evaluations.  Calling it returns the launches and summed duration recorded since the
  * previous call (HIP events around every matching launch on the context stream) and the
  * algorithmic bytes of one launch, then resets the counters and enables (enable != 0) or
  * disables the timing. */

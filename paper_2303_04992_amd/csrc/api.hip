@@ -156,7 +156,7 @@ struct MacSolver {
   }
 
   void pass(int kind, int axis, const T* in, T* out, bool acc = false) {
-    const bool timed = (kind == prof_kind && axis == prof_axis && !acc);
+    const bool timed = (kind == prof_kind && (prof_axis < 0 || axis == prof_axis) && !acc);
     if (timed) {
       if (prof_used == prof_ev.size()) {
         hipEvent_t a, b;
@@ -851,7 +851,7 @@ kfbi_status kfbi_interface_solve(kfbi_ctx* C, const double* phi, int32_t use_for
 
 kfbi_status kfbi_profile_pass(kfbi_ctx* C, int32_t kind, int32_t axis, int32_t enable, int64_t* launches,
                               double* total_ms, double* bytes_per_launch) {
-  if (!C || kind < 0 || kind > 4 || axis < 0 || axis > 2) return KFBI_EINVAL;
+  if (!C || kind < 0 || kind > 4 || axis < -1 || axis > 2) return KFBI_EINVAL;
   return guarded(C, [&] {
     auto go = [&](auto& sv) {
       using T = std::remove_reference_t<decltype(*sv.A)>;
