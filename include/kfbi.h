@@ -132,6 +132,23 @@ kfbi_status kfbi_solve_bvp(kfbi_ctx* ctx, const double* g_dev, kfbi_vec_fn f, vo
 kfbi_status kfbi_interface_solve(kfbi_ctx* ctx, const double* phi_dev, int32_t use_force,
                                  double* u_dev, double* p_dev, kfbi_info* info);
 
+/* Probes for losses on interior values (the differentiation layer; not in the paper): m
+ * points, host array [m][3]; each velocity component is interpolated trilinearly from its
+ * face grid, so the 8 nodes of every probe's cell must be interior nodes (EINVAL otherwise).
+ * Replaces earlier probes. */
+kfbi_status kfbi_set_probes(kfbi_ctx* ctx, const double* xyz_host, int64_t m);
+/* Velocity at the probes ([m][3] device) of the unified interface solve with density phi
+ * (and the stored body force of the last kfbi_solve_bvp if use_force != 0). */
+kfbi_status kfbi_probe(kfbi_ctx* ctx, const double* phi_dev, int32_t use_force, double* vals_dev,
+                       kfbi_info* info);
+/* Transpose of phi -> probe values (the affine body-force part drops out): phi_bar [n][3]. */
+kfbi_status kfbi_probe_adjoint(kfbi_ctx* ctx, const double* vals_bar_dev, double* phi_bar_dev,
+                               kfbi_info* info);
+/* y = K^{-T} rhs by unrestarted GMRES with kfbi_eval_adjoint as the operator (zero initial
+ * guess, gmres_rtol, gmres_maxit): the adjoint of the second-kind equation of Sec. 3, used for
+ * gradients with respect to the Dirichlet data. */
+kfbi_status kfbi_solve_adjoint(kfbi_ctx* ctx, const double* rhs_dev, double* y_dev, kfbi_info* info);
+
 /* Measurement helper: launches the sine/cosine transform pass kernel of the context's MAC
  * solver (kind 0 DCT-II, 1 DST-II, 2 DCT-III, 3 DST-III, 4 DST-I; axis 0..2; precision of
  * the context's inner solver) reps times back to back on the context stream between two HIP

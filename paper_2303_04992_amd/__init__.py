@@ -2,13 +2,14 @@
 
 Every step of the operator runs in the HIP library; PyTorch supplies device memory and
 streams.  Importing this package loads ``libkfbi.so`` from the package directory and fails
-loudly if it is missing (build it with ``python -m paper_2303_04992_amd.build``).
+loudly if it is missing (build it with ``python paper_2303_04992_amd/build.py``).
 
 Names follow include/kfbi.h: ``Operator.eval`` is kfbi_eval (K phi = 1/2 phi - M phi, the
 interior trace of the double-layer interface problem), ``Operator.eval_adjoint`` its
 transpose, ``Operator.solve_bvp`` the Dirichlet boundary-value solve (GMRES on the
 second-kind integral equation), ``Operator.interface_solve`` the grid solution of the
-unified interface problem.  ``BIEEval`` and ``BIESolve`` wrap them as autograd functions.
+unified interface problem, ``Operator.probe`` the velocity at interior probes.  ``BIEEval``,
+``BIESolve`` and ``ProbeEval`` wrap them as autograd functions with hand-written transposes.
 """
 from __future__ import annotations
 
@@ -77,6 +78,10 @@ _sig = {
     "kfbi_eval_adjoint": (C.c_int, [_P, _P, _P, C.POINTER(Info)]),
     "kfbi_solve_bvp": (C.c_int, [_P, _P, VecFn, _P, _P, _P, _P, C.POINTER(Info)]),
     "kfbi_interface_solve": (C.c_int, [_P, _P, C.c_int32, _P, _P, C.POINTER(Info)]),
+    "kfbi_set_probes": (C.c_int, [_P, _P, C.c_int64]),
+    "kfbi_probe": (C.c_int, [_P, _P, C.c_int32, _P, C.POINTER(Info)]),
+    "kfbi_probe_adjoint": (C.c_int, [_P, _P, _P, C.POINTER(Info)]),
+    "kfbi_solve_adjoint": (C.c_int, [_P, _P, _P, C.POINTER(Info)]),
     "kfbi_time_pass": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double),
                                  C.POINTER(C.c_double)]),
     "kfbi_profile_pass": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int64),
@@ -245,6 +250,41 @@ class Operator:
         self.last_info = info.as_dict()
         return u, p
 
+    def set_probes(self, xyz):
+        xyz = np.ascontiguousarray(np.asarray(xyz, dtype=np.float64).reshape(-1, 3))
+        self._check(_lib.kfbi_set_probes(self._h, xyz.ctypes.data_as(C.c_void_p), len(xyz)))
+        self.nprobe = len(xyz)
+
+    def probe(self, phi, use_force=False):
+        """Velocity at the probes of the unified interface solve with density phi."""
+        torch = _torch()
+        phi = self._vec(phi)
+        out = torch.empty((self.nprobe, 3), dtype=torch.float64, device=self.device)
+        info = Info()
+        self._check(_lib.kfbi_probe(self._h, _ptr(phi), int(bool(use_force)), _ptr(out), C.byref(info)))
+        self.last_info = info.as_dict()
+        return out
+
+    def probe_adjoint(self, vbar):
+        torch = _torch()
+        vbar = torch.as_tensor(vbar, dtype=torch.float64, device=self.device).reshape(self.nprobe, 3).contiguous()
+        out = torch.empty((self.n, 3), dtype=torch.float64, device=self.device)
+        info = Info()
+        self._check(_lib.kfbi_probe_adjoint(self._h, _ptr(vbar), _ptr(out), C.byref(info)))
+        self.last_info = info.as_dict()
+        return out
+
+    def solve_adjoint(self, rhs):
+        """y = K^{-T} rhs (GMRES with the transposed operator)."""
+        torch = _torch()
+        rhs = self._vec(rhs)
+        out = torch.empty_like(rhs)
+        info = Info()
+        st = _lib.kfbi_solve_adjoint(self._h, _ptr(rhs), _ptr(out), C.byref(info))
+        self.last_info = info.as_dict()
+        self._check(st)
+        return out
+
     def time_pass(self, kind=1, axis=1, reps=20):
         """Mean duration (ms) and algorithmic bytes of one transform-pass launch."""
         ms, by = C.c_double(), C.c_double()
@@ -270,7 +310,7 @@ def _autograd():
     torch = _torch()
 
     class BIEEval(torch.autograd.Function):
-        """K phi with the hand-written transpose as backward."""
+        """K phi with the hand-written transpose (kfbi_eval_adjoint) as backward."""
 
         @staticmethod
         def forward(ctx, phi, op):
@@ -282,60 +322,37 @@ def _autograd():
             return ctx.op.eval_adjoint(gout.contiguous()), None
 
     class BIESolve(torch.autograd.Function):
-        """phi = K^{-1} (g - b) by GMRES; backward = adjoint GMRES solve with K^T."""
+        """phi = K^{-1}(g - b) by GMRES (b = volume trace of the body force f, if any);
+        backward: g_bar = K^{-T} phi_bar (GMRES with the transposed operator)."""
 
         @staticmethod
-        def forward(ctx, g, op):
+        def forward(ctx, g, op, f=None):
             ctx.op = op
-            phi, _, _ = op.solve_bvp(g.detach(), None, return_fields=False)
+            phi, _, _ = op.solve_bvp(g.detach(), f, return_fields=False)
             return phi
 
         @staticmethod
         def backward(ctx, gphi):
-            return adjoint_gmres(ctx.op, gphi.contiguous()), None
+            return ctx.op.solve_adjoint(gphi.contiguous()), None, None
 
-    return BIEEval, BIESolve
+    class ProbeEval(torch.autograd.Function):
+        """Velocity at the interior probes of the unified interface solve with density phi."""
 
+        @staticmethod
+        def forward(ctx, phi, op, use_force=False):
+            ctx.op = op
+            return op.probe(phi.detach(), use_force)
 
-def adjoint_gmres(op, rhs, tol=None, maxit=200):
-    """Solve K^T y = rhs by GMRES with kfbi_eval_adjoint as the operator (float64 on the
-    device; orthogonalisation by torch tensor ops of the same device)."""
-    torch = _torch()
-    tol = tol if tol is not None else 1e-10
-    b = rhs.reshape(-1)
-    beta = torch.linalg.norm(b).item()
-    if beta == 0:
-        return torch.zeros_like(rhs)
-    V = [b / beta]
-    H = np.zeros((maxit + 1, maxit))
-    cs, sn, g = np.zeros(maxit), np.zeros(maxit), np.zeros(maxit + 1)
-    g[0] = beta
-    k = 0
-    for k in range(maxit):
-        w = op.eval_adjoint(V[k].reshape(-1, 3)).reshape(-1)
-        for i in range(k + 1):
-            H[i, k] = torch.dot(V[i], w).item()
-            w = w - H[i, k] * V[i]
-        H[k + 1, k] = torch.linalg.norm(w).item()
-        V.append(w / H[k + 1, k] if H[k + 1, k] > 0 else torch.zeros_like(w))
-        for i in range(k):
-            a, c = H[i, k], H[i + 1, k]
-            H[i, k], H[i + 1, k] = cs[i] * a + sn[i] * c, -sn[i] * a + cs[i] * c
-        r = np.hypot(H[k, k], H[k + 1, k])
-        cs[k], sn[k] = H[k, k] / r, H[k + 1, k] / r
-        H[k, k], H[k + 1, k] = r, 0.0
-        g[k + 1], g[k] = -sn[k] * g[k], cs[k] * g[k]
-        if abs(g[k + 1]) / beta < tol:
-            break
-    m = k + 1
-    y = np.linalg.solve(np.triu(H[:m, :m]), g[:m])
-    x = sum(float(y[i]) * V[i] for i in range(m))
-    return x.reshape(rhs.shape)
+        @staticmethod
+        def backward(ctx, gv):
+            return ctx.op.probe_adjoint(gv.contiguous()), None, None
+
+    return BIEEval, BIESolve, ProbeEval
 
 
 def __getattr__(name):
-    if name in ("BIEEval", "BIESolve"):
-        E, S = _autograd()
-        globals()["BIEEval"], globals()["BIESolve"] = E, S
+    if name in ("BIEEval", "BIESolve", "ProbeEval"):
+        E, S, P = _autograd()
+        globals()["BIEEval"], globals()["BIESolve"], globals()["ProbeEval"] = E, S, P
         return globals()[name]
     raise AttributeError(name)

@@ -317,6 +317,11 @@ struct kfbi_ctx {
   double* rpart = nullptr;
   // GMRES
   double *V = nullptr, *H = nullptr, *gtmp = nullptr;
+  // interior probes (trilinear interpolation on T^1..T^3) and the transposed map
+  int64_t nprobe = 0, nprobe_nodes = 0;
+  int64_t *pr_idx = nullptr, *prT_ptr = nullptr, *prT_node = nullptr;
+  int32_t* prT_row = nullptr;
+  double *pr_w = nullptr, *prT_w = nullptr;
   int gm_max = 0;
   kfbi_info last;
   ~kfbi_ctx() {
@@ -591,14 +596,13 @@ void eval_impl(kfbi_ctx* C, const double* phi, double* out, bool vol, kfbi_info*
   }
 }
 
-void adjoint_impl(kfbi_ctx* C, const double* w, double* out, kfbi_info* info) {
+// Transpose of (density -> grid velocity of the double-layer interface problem), applied to
+// the velocity cotangent already in C->F (F_p part zero); adds the interpolation jump term
+// for the cotangent w of K phi when w != nullptr.
+void transpose_from_velocity(kfbi_ctx* C, const double* w, double* out, kfbi_info* info) {
   const Setup& S = C->S;
   const int64_t M = S.M;
   hipStream_t s = C->s;
-  double t0 = now_ms();
-  // u-bar = W^T w (F holds the solve's right-hand side (u-bar, 0))
-  HIPCHK(launch_fill<double>(4 * M, C->F, 0.0, s));
-  HIPCHK(launch_interp_T((int64_t)S.uT_node.size(), C->uT_ptr, C->uT_node, C->uT_row, C->uT_w, w, C->F, s));
   // transpose of the MAC solve: (F_u-bar, F_p-bar) = (u', -p') with (u', p') = solve(u-bar, 0)
   mac_solve(C, C->F, C->u, C->p, info);
   HIPCHK(hipMemcpyAsync(C->F, C->u, 3 * M * sizeof(double), hipMemcpyDeviceToDevice, s));
@@ -608,6 +612,17 @@ void adjoint_impl(kfbi_ctx* C, const double* w, double* out, kfbi_info* info) {
   HIPCHK(launch_jump_T(S.T, C->cp_of, C->jmap, C->emap, C->jbar, w, C->fitbar, s));
   HIPCHK(launch_fit_T(S.n, C->fT_ptr, C->fT_entry, C->fT_target, C->fitw, C->fitbar, out, s));
   HIPCHK(hipStreamSynchronize(s));
+}
+
+void adjoint_impl(kfbi_ctx* C, const double* w, double* out, kfbi_info* info) {
+  const Setup& S = C->S;
+  const int64_t M = S.M;
+  hipStream_t s = C->s;
+  double t0 = now_ms();
+  // u-bar = W^T w (F holds the solve's right-hand side (u-bar, 0))
+  HIPCHK(launch_fill<double>(4 * M, C->F, 0.0, s));
+  HIPCHK(launch_interp_T((int64_t)S.uT_node.size(), C->uT_ptr, C->uT_node, C->uT_row, C->uT_w, w, C->F, s));
+  transpose_from_velocity(C, w, out, info);
   if (info) info->ms_total += now_ms() - t0;
 }
 
@@ -657,7 +672,11 @@ __global__ void k_scale_inv_norm(int64_t n, double* y, const double* nsq, double
 namespace {
 
 // unrestarted GMRES (modified Gram-Schmidt, Givens rotations) on K phi = rhs, zero guess
-int gmres(kfbi_ctx* C, const double* rhs, double* phi, double tol, int maxit, double* relres, kfbi_info* info) {
+void adjoint_impl(kfbi_ctx* C, const double* w, double* out, kfbi_info* info);
+
+// unrestarted GMRES (modified Gram-Schmidt, Givens rotations) on K x = rhs (or K^T x = rhs)
+int gmres(kfbi_ctx* C, const double* rhs, double* phi, double tol, int maxit, double* relres, kfbi_info* info,
+          bool transpose = false) {
   const Setup& S = C->S;
   const int64_t n3 = 3 * S.n;
   hipStream_t s = C->s;
@@ -689,7 +708,10 @@ int gmres(kfbi_ctx* C, const double* rhs, double* phi, double tol, int maxit, do
   for (k = 0; k < maxit; ++k) {
     double* vk = C->V + (size_t)k * n3;
     double* w = C->V + (size_t)(k + 1) * n3;
-    eval_impl(C, vk, w, false, info);
+    if (transpose)
+      adjoint_impl(C, vk, w, info);
+    else
+      eval_impl(C, vk, w, false, info);
     double* Hc = C->H + (size_t)k * LD;
     for (int i = 0; i <= k; ++i) {
       dev_dot(C, C->V + (size_t)i * n3, w, n3, Hc + i);
@@ -967,6 +989,121 @@ int64_t kfbi_plan_get(const kfbi_plan* p, const char* name, void* out) {
   if (n == "side2") return copy_out(S.side[2], out);
   if (n == "sidep") return copy_out(S.side[3], out);
   return -1;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------------------
+// interior probes and the adjoint solves used by the autograd layer
+// ---------------------------------------------------------------------------------------
+extern "C" {
+
+kfbi_status kfbi_set_probes(kfbi_ctx* C, const double* xyz, int64_t m) {
+  if (!C || (!xyz && m > 0) || m < 0) return KFBI_EINVAL;
+  return guarded(C, [&] {
+    const Setup& S = C->S;
+    const int N = S.N;
+    std::vector<int64_t> idx(m * 24);
+    std::vector<double> w(m * 24);
+    for (int64_t i = 0; i < m; ++i)
+      for (int c = 0; c < 3; ++c) {
+        int base[3];
+        double t[3];
+        for (int d = 0; d < 3; ++d) {
+          const double off = (d == c) ? 0.0 : 0.5;
+          const double u = (xyz[3 * i + d] - S.lo) / S.h - off;
+          if (!std::isfinite(u)) throw std::invalid_argument("non-finite probe");
+          base[d] = (int)std::floor(u);
+          t[d] = u - base[d];
+          const int lo_ok = (d == c) ? 1 : 0;
+          if (base[d] < lo_ok || base[d] + 1 > N - 1) throw std::invalid_argument("probe outside the interior nodes");
+        }
+        for (int k = 0; k < 8; ++k) {
+          int a[3];
+          double wt = 1.0;
+          for (int d = 0; d < 3; ++d) {
+            const int bit = (k >> (2 - d)) & 1;
+            a[d] = base[d] + bit;
+            wt *= bit ? t[d] : 1.0 - t[d];
+          }
+          idx[(i * 3 + c) * 8 + k] = (int64_t)c * S.M + ((int64_t)a[0] * N + a[1]) * N + a[2];
+          w[(i * 3 + c) * 8 + k] = wt;
+        }
+      }
+    // transpose: CSR over distinct grid nodes
+    std::vector<std::tuple<int64_t, int32_t, double>> ent;
+    ent.reserve(m * 24);
+    for (int64_t r = 0; r < 3 * m; ++r)
+      for (int k = 0; k < 8; ++k) ent.emplace_back(idx[r * 8 + k], (int32_t)r, w[r * 8 + k]);
+    std::sort(ent.begin(), ent.end());
+    std::vector<int64_t> ptr(1, 0), node;
+    std::vector<int32_t> row;
+    std::vector<double> tw;
+    for (size_t e = 0; e < ent.size(); ++e) {
+      if (e == 0 || std::get<0>(ent[e]) != std::get<0>(ent[e - 1])) {
+        if (e > 0) ptr.push_back((int64_t)e);
+        node.push_back(std::get<0>(ent[e]));
+      }
+      row.push_back(std::get<1>(ent[e]));
+      tw.push_back(std::get<2>(ent[e]));
+    }
+    ptr.push_back((int64_t)ent.size());
+    auto& o = C->owned;
+    C->pr_idx = dupload(idx, o, C->s);
+    C->pr_w = dupload(w, o, C->s);
+    C->prT_ptr = dupload(ptr, o, C->s);
+    C->prT_node = dupload(node, o, C->s);
+    C->prT_row = dupload(row, o, C->s);
+    C->prT_w = dupload(tw, o, C->s);
+    C->nprobe = m;
+    C->nprobe_nodes = (int64_t)node.size();
+    HIPCHK(hipStreamSynchronize(C->s));
+  });
+}
+
+kfbi_status kfbi_probe(kfbi_ctx* C, const double* phi, int32_t use_force, double* vals, kfbi_info* info) {
+  if (!C || !phi || !vals) return KFBI_EINVAL;
+  if (info) std::memset(info, 0, sizeof(*info));
+  if (C->nprobe == 0) {
+    C->err = "no probes set";
+    return KFBI_EINVAL;
+  }
+  return guarded(C, [&] {
+    check_finite(C, phi, 3 * C->S.n);
+    assemble_rhs(C, phi, use_force != 0);
+    mac_solve(C, C->F, C->u, C->p, info);
+    // trilinear interpolation: 8 weights per (probe, component)
+    HIPCHK(launch_interp8(C->nprobe, C->pr_idx, C->pr_w, C->u, vals, C->s));
+    HIPCHK(hipStreamSynchronize(C->s));
+  });
+}
+
+kfbi_status kfbi_probe_adjoint(kfbi_ctx* C, const double* vals_bar, double* phi_bar, kfbi_info* info) {
+  if (!C || !vals_bar || !phi_bar) return KFBI_EINVAL;
+  if (info) std::memset(info, 0, sizeof(*info));
+  if (C->nprobe == 0) {
+    C->err = "no probes set";
+    return KFBI_EINVAL;
+  }
+  return guarded(C, [&] {
+    check_finite(C, vals_bar, 3 * C->nprobe);
+    HIPCHK(launch_fill<double>(4 * C->S.M, C->F, 0.0, C->s));
+    HIPCHK(launch_interp_T(C->nprobe_nodes, C->prT_ptr, C->prT_node, C->prT_row, C->prT_w, vals_bar, C->F, C->s));
+    transpose_from_velocity(C, nullptr, phi_bar, info);
+  });
+}
+
+kfbi_status kfbi_solve_adjoint(kfbi_ctx* C, const double* rhs, double* y, kfbi_info* info) {
+  if (!C || !rhs || !y) return KFBI_EINVAL;
+  if (info) std::memset(info, 0, sizeof(*info));
+  return guarded(C, [&] {
+    const int64_t n3 = 3 * C->S.n;
+    check_finite(C, rhs, n3);
+    if (!C->gtmp) C->gtmp = dalloc<double>(n3, C->owned);
+    HIPCHK(hipMemcpyAsync(C->gtmp, rhs, n3 * sizeof(double), hipMemcpyDeviceToDevice, C->s));
+    double rr = 0;
+    gmres(C, C->gtmp, y, C->cfg.gmres_rtol, C->cfg.gmres_maxit, &rr, info, true);
+  });
 }
 
 }  // extern "C"

@@ -93,6 +93,8 @@ hipError_t launch_interp_jump(int64_t n, const int64_t* cp_target, const double*
                               const double* efmap, const double* Fj, double* ejump, hipStream_t s);
 hipError_t launch_correct(int64_t nirr, const int64_t* irr_node, const int64_t* irr_ptr, const int32_t* arm_t,
                           const int8_t* arm_o, const double* arm_a, const double* jumps, double* F, hipStream_t s);
+// probes: out[r] = sum_{q<8} w[8r+q] u[idx[8r+q]], r < 3 m (trilinear)
+hipError_t launch_interp8(int64_t m, const int64_t* idx, const double* w, const double* u, double* out, hipStream_t s);
 hipError_t launch_interp(int64_t n, const int64_t* idx, const double* w, const double* u, const double* ejump,
                          double* out, hipStream_t s);
 // adjoint

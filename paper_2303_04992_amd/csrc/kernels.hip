@@ -504,6 +504,16 @@ __global__ void k_interp(int64_t n, const int64_t* __restrict__ idx, const doubl
   out[r] = s;
 }
 
+__global__ void k_interp8(int64_t m, const int64_t* __restrict__ idx, const double* __restrict__ w,
+                          const double* __restrict__ u, double* __restrict__ out) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= 3 * m) return;
+  double s = 0;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) s += w[8 * r + q] * u[idx[8 * r + q]];
+  out[r] = s;
+}
+
 __global__ void k_interp_T(int64_t nnode, const int64_t* __restrict__ ptr, const int64_t* __restrict__ node,
                            const int32_t* __restrict__ row, const double* __restrict__ w,
                            const double* __restrict__ wbar, double* __restrict__ ubar) {
@@ -533,7 +543,7 @@ __global__ void k_jump_T(int64_t T, const int64_t* __restrict__ cp_of, const dou
   for (int c = 0; c < 18; ++c) {
     double s = 0;
     for (int r = 0; r < 5; ++r) s += jmap[(t * 5 + r) * 18 + c] * jbar[5 * t + r];
-    if (cp >= 0)
+    if (cp >= 0 && wbar)
       for (int m = 0; m < 3; ++m) s += emap[(cp * 3 + m) * 18 + c] * wbar[3 * cp + m];
     fitbar[18 * t + c] = s;
   }
@@ -839,6 +849,10 @@ hipError_t launch_correct(int64_t nirr, const int64_t* irr_node, const int64_t* 
 hipError_t launch_interp(int64_t n, const int64_t* idx, const double* w, const double* u, const double* ejump,
                          double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_interp, dim3(gb(3 * n)), dim3(256), 0, s, n, idx, w, u, ejump, out);
+  return hipGetLastError();
+}
+hipError_t launch_interp8(int64_t m, const int64_t* idx, const double* w, const double* u, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_interp8, dim3(gb(3 * m)), dim3(256), 0, s, m, idx, w, u, out);
   return hipGetLastError();
 }
 hipError_t launch_interp_T(int64_t nnode, const int64_t* ptr, const int64_t* node, const int32_t* row,

@@ -1,0 +1,121 @@
+"""GPU checks of the differentiation layer: probe values against the oracle's grid solution,
+exact transposes (dot-product tests), the adjoint GMRES, and the gradient of a probe misfit
+with respect to the Dirichlet data against central finite differences.
+
+The loss l(g) = 1/2 sum |u_h(x_p) - t(x_p)|^2 over interior probes is exactly quadratic in g
+(every step from g to the probe values is affine), so a central difference of step 1e-2 |g|
+equals the directional derivative up to the solver tolerances; agreement is required to
+1e-6 relative.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import kfbi_inputs as KI
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(m):
+    print(m, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def K():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2303_04992_amd as K
+    return K
+
+
+def _trilinear(grid_u, xyz, N, lo, h):
+    """Reference trilinear interpolation of the three exported velocity grids (numpy)."""
+    out = np.zeros((len(xyz), 3))
+    for m in range(3):
+        off = np.array([0.0 if d == m else 0.5 for d in range(3)])
+        u = (xyz - lo) / h - off
+        b = np.floor(u).astype(int)
+        t = u - b
+        for corner in range(8):
+            bits = np.array([(corner >> (2 - d)) & 1 for d in range(3)])
+            w = np.prod(np.where(bits, t, 1 - t), axis=1)
+            idx = b + bits
+            out[:, m] += w * grid_u[m][idx[:, 0], idx[:, 1], idx[:, 2]]
+    return out
+
+
+def test_probe_values_match_oracle_grid_solution(K):
+    from oracle.kfbi import Oracle
+    cfg = KI.WORKLOADS["sphere32"]
+    _say("[probe parity] sphere32")
+    op = K.Operator(cfg, K.FP64, cg_rtol=1e-13)
+    O = Oracle(cfg)
+    probes = KI.probe_points(cfg, 512, seed=0)
+    op.set_probes(probes)
+    phi = KI.random_density(op.n)
+    vg = op.probe(phi).cpu().numpy()
+    _, uo, _ = O.interface_solve(phi)
+    vo = _trilinear(uo, probes, cfg.N, cfg.lo, cfg.h)
+    r = np.linalg.norm(vg - vo) / np.linalg.norm(vo)
+    _say(f"   rel {r:.3e}")
+    assert r < 1e-10
+
+
+def test_probe_adjoint_and_adjoint_solve(K):
+    import torch
+    cfg = KI.WORKLOADS["ellip128"].with_N(32)
+    _say("[probe/solve adjoint] ellip N=32")
+    op = K.Operator(cfg, K.FP64, cg_rtol=1e-13, gmres_rtol=1e-12)
+    op.set_probes(KI.probe_points(cfg, 256, seed=3))
+    rng = np.random.default_rng(4)
+    x = rng.standard_normal((op.n, 3))
+    v = rng.standard_normal((op.nprobe, 3))
+    lhs = float(np.vdot(op.probe(x).cpu().numpy(), v))
+    rhs = float(np.vdot(x, op.probe_adjoint(v).cpu().numpy()))
+    _say(f"   <Px,v>={lhs:.12e} <x,P^T v>={rhs:.12e}")
+    assert abs(lhs - rhs) < 1e-10 * (abs(lhs) + np.linalg.norm(x) * np.linalg.norm(v))
+    r = torch.as_tensor(rng.standard_normal((op.n, 3)), device="cuda")
+    y = op.solve_adjoint(r)
+    res = torch.linalg.norm(op.eval_adjoint(y) - r) / torch.linalg.norm(r)
+    _say(f"   adjoint GMRES iters {op.last_info['gmres_iters']} residual {res.item():.3e}")
+    assert res.item() < 1e-10
+
+
+@pytest.mark.parametrize("name,N,ndir,gtol", [("sphere32", 32, 16, 1e-12), ("star128", 64, 4, 1e-10)])
+def test_gradient_wrt_dirichlet_data_matches_central_differences(K, name, N, ndir, gtol):
+    import torch
+    cfg = KI.WORKLOADS[name].with_N(N)
+    _say(f"[fd] {name} N={N}")
+    op = K.Operator(cfg, K.FP64, cg_rtol=1e-13, gmres_rtol=gtol, gmres_maxit=600)
+    probes = KI.probe_points(cfg, 4096, seed=0)
+    op.set_probes(probes)
+    target = torch.as_tensor(KI.probe_target(cfg, probes), device="cuda")
+    xyz, _ = op.points()
+    g0 = torch.as_tensor(KI.exact_u(cfg.solution, xyz[:, 0], xyz[:, 1], xyz[:, 2]), device="cuda")
+    f = lambda x, y, z: KI.body_force(cfg.solution, x, y, z, cfg.mu, cfg.lam)
+
+    def loss(g):
+        phi = K.BIESolve.apply(g, op, f)
+        v = K.ProbeEval.apply(phi, op, True)
+        return 0.5 * ((v - target) ** 2).sum()
+
+    g = g0.clone().requires_grad_(True)
+    L = loss(g)
+    L.backward()
+    adj_iters = op.last_info["gmres_iters"]  # the last call of the backward pass is the adjoint GMRES
+    grad = g.grad.detach()
+    dirs = torch.as_tensor(KI.random_directions(op.n, ndir, seed=1), device="cuda")
+    eps = 1e-2 * torch.linalg.norm(g0).item()
+    worst = 0.0
+    with torch.no_grad():
+        for d in dirs:
+            fd = (loss(g0 + eps * d) - loss(g0 - eps * d)).item() / (2 * eps)
+            an = float((grad * d).sum().item())
+            rel = abs(fd - an) / max(abs(fd), 1e-30)
+            worst = max(worst, rel)
+    _say(f"   loss {L.item():.6e}  worst rel diff {worst:.3e} over {ndir} directions, "
+         f"adjoint GMRES iterations {adj_iters}")
+    assert worst < 1e-6
