@@ -55,6 +55,18 @@ typedef enum { KFBI_FP64 = 0, KFBI_MIXED_FP32 = 1 } kfbi_precision;
 
 typedef enum { KFBI_SPHERE = 0, KFBI_ELLIPSOID = 1, KFBI_STAR = 2, KFBI_TORUS = 3 } kfbi_shape_kind;
 
+/* How the trace K phi = 1/2 phi - M phi is read off the grid solution (Prop. 4.2 / 4.4,
+ * Sec. 4.4).  AVERAGE (the default): 1/2 phi plus the mean of the interior and exterior
+ * limits (-M phi = (u+ + u-)/2), both interpolated from the same ten grid nodes with the jump
+ * function whose value part is the least-squares fitted value at the control point;
+ * equivalently u+ + (1/2 - alpha)(phi - S phi) with alpha the exterior weight fraction of the
+ * stencil and S phi the fitted value.  INTERIOR: the interior limit u+ alone, with the
+ * density itself as the value part of the jump function.  The forms agree to the fit's
+ * O(h^3) error on smooth densities; on grid-scale oscillations AVERAGE acts like 1/2 (as the
+ * second-kind equation does) while INTERIOR acts like alpha in [0, 1], so GMRES needs a
+ * mesh-dependent and several times larger number of iterations with INTERIOR. */
+typedef enum { KFBI_TRACE_AVERAGE = 0, KFBI_TRACE_INTERIOR = 1 } kfbi_trace;
+
 /* Omega = {psi <= 0}.  param: sphere R | ellipsoid semi-axes a,b,c (body axes rotated by
  * rot_z_deg about z) | star r0, eps, k, l with r = r0 + eps sin(k theta) cos(l phi),
  * theta = arccos(z/|x|), phi = atan2(y,x) | torus tube radius a, centre-line radius c. */
@@ -79,6 +91,7 @@ typedef struct {
   double gmres_rtol;  /* <= 0: 1e-8 */
   int32_t gmres_maxit;/* <= 0: 200 */
   void* stream;       /* hipStream_t; NULL = default stream */
+  kfbi_trace trace;   /* trace form of K (eval, adjoint and the GMRES operator) */
 } kfbi_config;
 
 typedef struct {
@@ -116,7 +129,7 @@ kfbi_status kfbi_sizes(const kfbi_ctx* ctx, int64_t* n_crossings, int64_t* n_irr
  * float64 device arrays (may not alias).  info may be NULL. */
 kfbi_status kfbi_eval(kfbi_ctx* ctx, const double* phi_dev, double* out_dev, kfbi_info* info);
 
-/* Transpose of kfbi_eval: out = K^T w (same shapes). */
+/* Transpose of kfbi_eval (in the context's trace form): out = K^T w (same shapes). */
 kfbi_status kfbi_eval_adjoint(kfbi_ctx* ctx, const double* w_dev, double* out_dev, kfbi_info* info);
 
 /* Dirichlet BVP (Sec. 3, Algorithm 1 step 3): u = g at the control points, body force f
@@ -175,7 +188,8 @@ void kfbi_plan_destroy(kfbi_plan* plan);
  * for an unknown name.  Names: xyz normal t1 t2 kappa (float64, per crossing), fam line1
  * line2 (int32), cp_target (int64), nb_ptr (int64) nb_idx (int32) fitw (float64, 6 per
  * neighbour entry), jmap (5x18 per crossing) jfmap (5x3) emap (3x18 per control point, then
- * 3x3), irr_node irr_ptr (int64) arm_t (int32) arm_o (int8) arm_a (3 per arm), itp_idx
+ * 3x3), stab_a (1/2 - exterior weight fraction, 3 per control point), sv_ptr (int64) sv_idx
+ * (int32) sv_w (fitted-value weights of the control points, CSR over control points), irr_node irr_ptr (int64) arm_t (int32) arm_o (int8) arm_a (3 per arm), itp_idx
  * (int64) itp_w (10 per control point and component), side0 side1 side2 sidep (uint8 N^3,
  * face index 0..N-1 along the face normal). */
 int64_t kfbi_plan_get(const kfbi_plan* plan, const char* name, void* out);

@@ -54,14 +54,19 @@ def weights(x, nodes, m, lo, h):
     return np.linalg.solve(V.T, e0), z       # first row of V^{-1}
 
 
-def interpolation_matrices(cr, sides, N, lo, h):
-    """W (3n x |u|): grid part; E (3n x T*34): jump-function part.
+def interpolation_matrices(cr, sides, N, lo, h, both_sides=False):
+    """W (3n x |u|): grid part; E (3n x T*34): jump-function part of the interior limit u+
+    (the jump function J_i at the stencil nodes outside Omega).
+
+    With both_sides, also returns E_all: the jump function at every stencil node, so that the
+    exterior limit is u- = W u + (E - E_all) jumps (stencil nodes inside Omega carry -J_i).
 
     The flat velocity vector concatenates u0 (N+1,N,N), u1 (N,N+1,N), u2 (N,N,N+1)."""
     n = len(cr.cp_target)
     sizes = [(N + 1) * N * N] * 3
     uoff = np.concatenate([[0], np.cumsum(sizes)])
     Wr, Wc, Wv, Er, Ec, Ev = [], [], [], [], [], []
+    Ar, Ac, Av = [], [], []
     for c in range(n):
         t = cr.cp_target[c]
         x = cr.xyz[t]
@@ -79,14 +84,21 @@ def interpolation_matrices(cr, sides, N, lo, h):
                 Wr.append(row)
                 Wc.append(uoff[m] + np.ravel_multi_index(tuple(a), shape))
                 Wv.append(w[i])
+                dz = z[i] - x
+                base = t * NJ
+                # jump function J_i: second-order Taylor polynomial of the jump from x to z_i
+                cols = [base + jidx_u(m)]
+                vals = [w[i]]
+                for k in range(3):
+                    cols.append(base + jidx_du(m, k)); vals.append(w[i] * dz[k])
+                    for l in range(3):
+                        cols.append(base + jidx_ddu(m, k, l)); vals.append(w[i] * 0.5 * dz[k] * dz[l])
+                Ar += [row] * len(cols); Ac += cols; Av += vals
                 if not sides[m][tuple(a)]:
-                    dz = z[i] - x
-                    base = t * NJ
-                    Er.append(row); Ec.append(base + jidx_u(m)); Ev.append(w[i])
-                    for k in range(3):
-                        Er.append(row); Ec.append(base + jidx_du(m, k)); Ev.append(w[i] * dz[k])
-                        for l in range(3):
-                            Er.append(row); Ec.append(base + jidx_ddu(m, k, l)); Ev.append(w[i] * 0.5 * dz[k] * dz[l])
+                    Er += [row] * len(cols); Ec += cols; Ev += vals
     W = sps.csr_matrix((Wv, (Wr, Wc)), shape=(3 * n, uoff[-1]))
     E = sps.csr_matrix((Ev, (Er, Ec)), shape=(3 * n, len(cr.fam) * NJ))
+    if both_sides:
+        Eall = sps.csr_matrix((Av, (Ar, Ac)), shape=(3 * n, len(cr.fam) * NJ))
+        return W, E, Eall
     return W, E

@@ -17,6 +17,18 @@ described in mac.MAC.solve_transpose).
 
 GMRES reading: unrestarted, modified Gram-Schmidt Arnoldi, Givens rotations, stop when the
 residual norm relative to the initial one (= ||b|| for the zero guess) is below tol.
+
+Two forms of the trace (a reading; the paper interpolates the interior limit only):
+  form="interior": K phi = u+, the interior limit interpolated with the jump function built
+      from the jumps at the control point, whose value part is the density itself;
+  form="average" (default):  K phi = 1/2 phi + (u+ + u-)/2, i.e. 1/2 phi - M phi with the double-layer
+      integral -M phi taken as the mean of the two one-sided limits (Prop. 4.2 / 4.4), both
+      interpolated from the same ten nodes with the jump function whose value part is the
+      least-squares fitted value at the control point (the derivative parts are the same in
+      both forms).  For smooth densities the two forms differ by the fit's O(h^3) value error;
+      for densities that oscillate on the grid scale (which the grid solution cannot carry)
+      the interior form acts like the exterior weight fraction of the stencil, which ranges
+      over [0, 1], while the average form acts like 1/2, as the second-kind equation does.
 """
 from __future__ import annotations
 
@@ -40,7 +52,10 @@ def _blockdiag(A):
 
 
 class Oracle:
-    def __init__(self, cfg, cg_rtol=1e-13, workers=None):
+    def __init__(self, cfg, cg_rtol=1e-13, workers=None, form="average"):
+        if form not in ("interior", "average"):
+            raise ValueError("form must be 'interior' or 'average'")
+        self.form = form
         self.cfg = cfg
         self.N, self.lo, self.hi = cfg.N, cfg.lo, cfg.hi
         self.h = (cfg.hi - cfg.lo) / cfg.N
@@ -52,14 +67,23 @@ class Oracle:
         self.sides = node_sides(self.grid, self.ls)
         self.n = len(self.cr.cp_target)
         self.T = len(self.cr.fam)
-        P, self.neighbours = fit_matrix(self.cr, self.h)
+        P, self.neighbours, Sraw = fit_matrix(self.cr, self.h, raw_values=True)
         self.Fit = sps.kron(P, sps.identity(3), format="csr")            # (18T, 3n)
         A, B = jump_matrix(self.pde, self.mu, self.lam, self.cr)
         self.Jmat = _blockdiag(A)                                          # (34T, 18T)
         self.Bmat = _blockdiag(B)                                          # (34T, 3T)
         self.mac = MAC(cfg.N, cfg.lo, cfg.hi, self.pde, self.mu, self.lam, workers=workers)
         self.Cmat = correction_matrix(self.mac, self.sides, self.cr)
-        self.W, self.E = interpolation_matrices(self.cr, self.sides, cfg.N, cfg.lo, self.h)
+        self.W, self.E, Eall = interpolation_matrices(self.cr, self.sides, cfg.N, cfg.lo, self.h, both_sides=True)
+        if form == "average":
+            # jump function of the mean limit: exterior nodes +J/2, interior nodes -J/2
+            self.Eavg = (self.E - 0.5 * Eall).tocsr()
+            # fit with the fitted value (not the density) at the control-point targets
+            tgt = np.asarray(self.cr.cp_target)
+            Pv = P.tolil()
+            for c, t in enumerate(tgt):
+                Pv[6 * t] = Sraw[c]
+            self.FitRaw = sps.kron(Pv.tocsr(), sps.identity(3), format="csr")
         self.rhs_off = rhs_layout(cfg.N)
         self.last_cg_iters = 0
 
@@ -114,7 +138,14 @@ class Oracle:
         """K phi = u+ at the control points for the double-layer interface problem (f None);
         with f, the trace of the unified interface problem (volume + double layer)."""
         jumps, u, p = self.interface_solve(phi, f)
-        out = self.W @ self.join_u(u) + self.E @ jumps
+        if self.form == "interior":
+            out = self.W @ self.join_u(u) + self.E @ jumps
+        else:
+            phi = np.asarray(phi, float).reshape(self.n, 3)
+            jr = self.Jmat @ (self.FitRaw @ phi.ravel())
+            if f is not None:
+                jr = jr + self.Bmat @ self.volume_source(f)[1].ravel()
+            out = 0.5 * phi.ravel() + self.W @ self.join_u(u) + self.Eavg @ jr
         return out.reshape(self.n, 3)
 
     def eval_adjoint(self, w):
@@ -125,8 +156,12 @@ class Oracle:
         Fu_bar, Fp_bar, it = self.mac.solve_transpose(ubar, rtol=self.cg_rtol)
         self.last_cg_iters = it
         rhs_bar = np.concatenate([x.ravel() for x in Fu_bar] + [Fp_bar.ravel()])
-        jbar = self.Cmat.T @ rhs_bar + self.E.T @ w
-        return (self.Fit.T @ (self.Jmat.T @ jbar)).reshape(self.n, 3)
+        if self.form == "interior":
+            jbar = self.Cmat.T @ rhs_bar + self.E.T @ w
+            return (self.Fit.T @ (self.Jmat.T @ jbar)).reshape(self.n, 3)
+        out = self.Fit.T @ (self.Jmat.T @ (self.Cmat.T @ rhs_bar))
+        out += self.FitRaw.T @ (self.Jmat.T @ (self.Eavg.T @ w)) + 0.5 * w
+        return out.reshape(self.n, 3)
 
     # ------------------------------------------------------------------ GMRES + BVP
     @staticmethod

@@ -39,12 +39,13 @@ from .geometry import GeometryError
 STOKES, NAVIER = 0, 1
 
 
-def fit_matrix(cr, h):
+def fit_matrix(cr, h, raw_values=False):
     """Least-squares fit weights as a sparse matrix of shape (6*T, n).
 
     Row 6*t+q gives quantity q of target t (0 value, 1-2 first derivatives d/dxi_a in physical
     units, 3-5 second derivatives 11, 12, 22) as a combination of the density at control
-    points."""
+    points.  With raw_values, also returns the (n, n) matrix S whose row c is the fitted
+    value (before the exact density replaces it) at control point c."""
     X = cr.xyz[cr.cp_target]
     Ncp = cr.normal[cr.cp_target]
     tree = cKDTree(X)
@@ -71,6 +72,7 @@ def fit_matrix(cr, h):
                 raise GeometryError("fewer than 12 control points within 4h of a target")
         pending = np.array(still, dtype=np.int64)
     scale = np.array([1.0, 1 / h, 1 / h, 1 / h ** 2, 1 / h ** 2, 1 / h ** 2])
+    Sr, Sc, Sv = [], [], []
     for t in range(T):
         L = nb[t]
         d = X[L] - cr.xyz[t]
@@ -79,6 +81,9 @@ def fit_matrix(cr, h):
         A = np.stack([np.ones_like(xi1), xi1, xi2, 0.5 * xi1 ** 2, xi1 * xi2, 0.5 * xi2 ** 2], 1)
         P = np.linalg.pinv(A) * scale[:, None]          # (6, K)
         if cr.cp[t] >= 0:                                # control point target: exact value
+            Sr.append(np.full(len(L), cr.cp[t]))
+            Sc.append(L)
+            Sv.append(P[0].copy())
             P[0, :] = 0.0
             P[0, np.nonzero(L == cr.cp[t])[0][0]] = 1.0
         for q in range(6):
@@ -87,6 +92,10 @@ def fit_matrix(cr, h):
             vals.append(P[q])
     M = sps.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
                        shape=(6 * T, len(cr.cp_target)))
+    if raw_values:
+        n = len(cr.cp_target)
+        S = sps.csr_matrix((np.concatenate(Sv), (np.concatenate(Sr), np.concatenate(Sc))), shape=(n, n))
+        return M, nb, S
     return M, nb
 
 

@@ -32,6 +32,8 @@ _lib = C.CDLL(LIB_PATH)
 
 STOKES, NAVIER = 0, 1
 FP64, MIXED_FP32 = 0, 1
+TRACE_AVERAGE, TRACE_INTERIOR = 0, 1
+_TRACE = {"interior": TRACE_INTERIOR, "average": TRACE_AVERAGE}
 OK, EINVAL, ENOMEM, EGEOM, ENOCONV, EDEVICE = 0, -1, -2, -3, -4, -5
 _STATUS = {EINVAL: "EINVAL", ENOMEM: "ENOMEM", EGEOM: "EGEOM", ENOCONV: "ENOCONV", EDEVICE: "EDEVICE"}
 
@@ -50,7 +52,7 @@ class Config(C.Structure):
     _fields_ = [("N", C.c_int32), ("lo", C.c_double), ("hi", C.c_double), ("pde", C.c_int), ("mu", C.c_double),
                 ("lam", C.c_double), ("shape", Shape), ("precision", C.c_int), ("cg_rtol", C.c_double),
                 ("cg_maxit", C.c_int32), ("inner_rtol", C.c_double), ("gmres_rtol", C.c_double),
-                ("gmres_maxit", C.c_int32), ("stream", C.c_void_p)]
+                ("gmres_maxit", C.c_int32), ("stream", C.c_void_p), ("trace", C.c_int)]
 
 
 class Info(C.Structure):
@@ -97,13 +99,14 @@ for _name, (_res, _args) in _sig.items():
 
 
 def make_config(cfg, precision=FP64, cg_rtol=0.0, cg_maxit=0, inner_rtol=0.0, gmres_rtol=0.0, gmres_maxit=0,
-                stream=None) -> Config:
-    """Marshal a workload description (kfbi_inputs.Config-like object) into kfbi_config."""
+                stream=None, trace="average") -> Config:
+    """Marshal a workload description (kfbi_inputs.Config-like object) into kfbi_config.
+    trace: "average" (1/2 phi + mean of the two limits, default) or "interior" (K phi = u+)."""
     sh = Shape(int(cfg.shape.kind), (C.c_double * 3)(*cfg.shape.center), (C.c_double * 6)(*cfg.shape.param),
                float(cfg.shape.rot_z_deg))
     return Config(int(cfg.N), float(cfg.lo), float(cfg.hi), int(cfg.pde), float(cfg.mu), float(cfg.lam), sh,
                   int(precision), float(cg_rtol), int(cg_maxit), float(inner_rtol), float(gmres_rtol),
-                  int(gmres_maxit), stream)
+                  int(gmres_maxit), stream, _TRACE[trace])
 
 
 class Plan:
@@ -114,7 +117,7 @@ class Plan:
                "nb_idx": np.int32, "fitw": np.float64, "jmap": np.float64, "jfmap": np.float64, "emap": np.float64,
                "irr_node": np.int64, "irr_ptr": np.int64, "arm_t": np.int32, "arm_o": np.int8, "arm_a": np.float64,
                "itp_idx": np.int64, "itp_w": np.float64, "side0": np.uint8, "side1": np.uint8, "side2": np.uint8,
-               "sidep": np.uint8}
+               "sidep": np.uint8, "stab_a": np.float64, "sv_ptr": np.int64, "sv_idx": np.int32, "sv_w": np.float64}
 
     def __init__(self, cfg, **kw):
         c = make_config(cfg, **kw)
@@ -154,7 +157,7 @@ class Operator:
     """One geometry + grid + PDE: K phi, K^T w, the BVP solve."""
 
     def __init__(self, cfg, precision=FP64, cg_rtol=0.0, cg_maxit=0, inner_rtol=0.0, gmres_rtol=0.0, gmres_maxit=0,
-                 device=None):
+                 device=None, trace="average"):
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("kfbi needs a HIP device (torch.cuda.is_available() is False)")
@@ -163,13 +166,14 @@ class Operator:
             stream = torch.cuda.current_stream(self.device)
             self.stream = stream
             c = make_config(cfg, precision, cg_rtol, cg_maxit, inner_rtol, gmres_rtol, gmres_maxit,
-                            C.c_void_p(stream.cuda_stream))
+                            C.c_void_p(stream.cuda_stream), trace)
             h = C.c_void_p()
             st = _lib.kfbi_create(C.byref(c), C.byref(h))
         if st != OK:
             raise KfbiError(st, _lib.kfbi_create_error().decode())
         self._h = h
         self.cfg = cfg
+        self.trace = trace
         n = C.c_int64()
         _lib.kfbi_num_points(h, C.byref(n))
         self.n = int(n.value)
@@ -178,9 +182,11 @@ class Operator:
         self.n_crossings, self.n_irregular = int(nt.value), int(ni.value)
         self.last_info = None
 
-    def __del__(self):
+    def __del__(self, _destroy=_lib.kfbi_destroy):
+        # the destroy function is bound at definition time: module globals may already be
+        # cleared when the interpreter finalises
         if getattr(self, "_h", None):
-            _lib.kfbi_destroy(self._h)
+            _destroy(self._h)
             self._h = None
 
     def _check(self, st):

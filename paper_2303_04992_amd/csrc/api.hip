@@ -294,8 +294,9 @@ struct kfbi_ctx {
   int64_t M = 0;
   // surface maps
   int64_t *nb_ptr, *irr_node, *irr_ptr, *itp_idx, *cp_target, *cp_of, *uT_ptr, *uT_node, *cT_ptr, *cT_node;
-  int64_t *fT_ptr, *fT_entry;
-  int32_t *nb_idx, *arm_t, *uT_row, *fT_target;
+  int64_t *fT_ptr, *fT_entry, *sv_ptr, *svT_ptr;
+  int32_t *nb_idx, *arm_t, *uT_row, *fT_target, *sv_idx, *svT_row;
+  double *stab_a, *sv_w, *svT_w;
   int8_t *arm_o, *cT_slot;
   double *fitw, *jmap, *jfmap, *emap, *efmap, *arm_a, *itp_w, *uT_w, *cT_a;
   // work
@@ -311,7 +312,7 @@ struct kfbi_ctx {
   MacSolver<float> s32;
   bool mixed = false;
   // mixed refinement fields (float64 and float32)
-  double *ru = nullptr, *Feff = nullptr;
+  double* ru = nullptr;  // spare float64 iterate of the refinement
   float *r32 = nullptr, *x32 = nullptr;
   double* rscal = nullptr;
   double* rpart = nullptr;
@@ -352,6 +353,7 @@ static const char* validate(const kfbi_config* c) {
   if (c->pde != KFBI_STOKES && c->pde != KFBI_NAVIER) return "unknown pde";
   if (c->precision != KFBI_FP64 && c->precision != KFBI_MIXED_FP32) return "unknown precision";
   if (c->shape.kind < KFBI_SPHERE || c->shape.kind > KFBI_TORUS) return "unknown shape";
+  if (c->trace != KFBI_TRACE_INTERIOR && c->trace != KFBI_TRACE_AVERAGE) return "unknown trace form";
   return nullptr;
 }
 
@@ -421,6 +423,13 @@ kfbi_status kfbi_create(const kfbi_config* cfg_in, kfbi_ctx** out) {
     C->fT_ptr = dupload(S.fT_ptr, o, s);
     C->fT_entry = dupload(S.fT_entry, o, s);
     C->fT_target = dupload(S.fT_target, o, s);
+    C->stab_a = dupload(S.stab_a, o, s);
+    C->sv_ptr = dupload(S.sv_ptr, o, s);
+    C->sv_idx = dupload(S.sv_idx, o, s);
+    C->sv_w = dupload(S.sv_w, o, s);
+    C->svT_ptr = dupload(S.svT_ptr, o, s);
+    C->svT_row = dupload(S.svT_row, o, s);
+    C->svT_w = dupload(S.svT_w, o, s);
     C->jumps = dalloc<double>(5 * S.T, o);
     C->fitvals = dalloc<double>(18 * S.T, o);
     C->ejump = dalloc<double>(3 * S.n, o);
@@ -435,11 +444,10 @@ kfbi_status kfbi_create(const kfbi_config* cfg_in, kfbi_ctx** out) {
     if (C->mixed) {
       C->s32.init(S.N, S.h, S.pde, S.mu, c, s, o);
       C->ru = dalloc<double>(4 * S.M, o);
-      C->Feff = dalloc<double>(4 * S.M, o);
       C->r32 = dalloc<float>(4 * S.M, o);
       C->x32 = dalloc<float>(4 * S.M, o);
       C->rscal = dalloc<double>(16, o);
-      C->rpart = dalloc<double>(1024, o);
+      C->rpart = dalloc<double>(4096, o);
     } else {
       C->s64.init(S.N, S.h, S.pde, S.mu, c, s, o);
     }
@@ -528,46 +536,59 @@ int mac_solve(kfbi_ctx* C, const double* F, double* u, double* p, kfbi_info* inf
     }
     return it;
   }
-  // mixed: float32 inner solves inside float64 residual refinement of the full system
-  double* Fe = C->Feff;
-  HIPCHK(hipMemcpyAsync(Fe, F, 4 * M * sizeof(double), hipMemcpyDeviceToDevice, s));
+  // mixed: float32 inner solves inside float64 residual refinement of the full system.
+  // Round k: x32 = (float32 MAC solve of r32); (u, p) += x32 and r32 = F - A(u, p), formed in
+  // float64 in one fused pass; stop when |r| <= cg_rtol |F| (Stokes: pressure parts taken
+  // modulo constants, which the inner solve projects out).
   const bool stokes = S.pde == KFBI_STOKES;
-  auto project = [&](double* v) {
-    if (!stokes) return;
-    HIPCHK(launch_sum_partials<double>(M, v, C->rpart, 1024, s));
-    HIPCHK(launch_reduce(C->rpart, 1024, 1, C->rscal, R_SUM, 1, M, s));
-    HIPCHK(launch_add_scalar<double>(M, v, C->rscal, 5, -1.0 / (double)M, s));
-  };
-  auto norm2 = [&](const double* v, int64_t n) {
-    HIPCHK(launch_dot_partials<double>(n, v, v, C->rpart, 1024, s));
-    HIPCHK(launch_reduce(C->rpart, 1024, 1, C->rscal, R_SUM, 0, n, s));
-    double h = 0;
-    HIPCHK(hipMemcpyAsync(&h, C->rscal + 5, sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    return std::sqrt(h);
-  };
-  project(Fe + 3 * M);
-  const double f0 = norm2(Fe, 4 * M);
-  HIPCHK(launch_fill<double>(3 * M, u, 0.0, s));
-  HIPCHK(launch_fill<double>(M, p, 0.0, s));
-  HIPCHK(hipMemcpyAsync(C->ru, Fe, 4 * M * sizeof(double), hipMemcpyDeviceToDevice, s));
   const double c = stokes ? 0.0 : 1.0 / (S.lam + S.mu);
+  constexpr int NP = 1024;  // blocks of the fused passes (3 partial sums each)
+  auto norm = [&](int op) {
+    HIPCHK(launch_reduce(C->rpart, NP, 3, C->rscal, op, stokes, M, s));
+    double h2 = 0;
+    HIPCHK(hipMemcpyAsync(&h2, C->rscal + 5, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    return std::sqrt(std::max(h2, 0.0));
+  };
+  HIPCHK(launch_refine_prep(M, F, C->rpart, NP, s));
+  const double f0 = norm(R_RESNORM0);
+  const double* shift = stokes ? C->rscal + 6 : nullptr;  // mean of F_p (Stokes)
+  if (!(f0 > 0)) {
+    HIPCHK(launch_fill<double>(3 * M, u, 0.0, s));
+    HIPCHK(launch_fill<double>(M, p, 0.0, s));
+    if (info) info->refine_rounds = 0;
+    return 0;
+  }
+  // the iterate alternates between (u, p) and the spare float64 fields (neighbour values of
+  // the old iterate are read while the new one is written)
+  double* cu = u;
+  double* cp = p;
+  HIPCHK(launch_refine_convert(M, F, shift, C->r32, s));
   int total = 0, rounds = 0;
   double rn = f0;
-  while (f0 > 0 && rn > C->cfg.cg_rtol * f0) {
+  while (rn > C->cfg.cg_rtol * f0) {
     if (rounds >= 30) throw std::runtime_error("ENOCONV: mixed refinement did not converge");
-    HIPCHK((launch_convert<float, double>(4 * M, C->r32, C->ru, s)));
     int it = C->s32.solve(C->r32, C->r32 + 3 * M, C->x32, C->x32 + 3 * M, C->cfg.inner_rtol, C->cfg.cg_maxit);
     if (it < 0) throw std::runtime_error("ENOCONV: inner float32 CG reached cg_maxit");
     total += it;
-    HIPCHK(launch_add_into_f64<float>(3 * M, u, C->x32, s));
-    HIPCHK(launch_add_into_f64<float>(M, p, C->x32 + 3 * M, s));
-    HIPCHK(launch_mac_residual(S.N, S.h, S.mu, c, u, p, Fe, Fe + 3 * M, C->ru, C->ru + 3 * M, s));
-    project(C->ru + 3 * M);
-    rn = norm2(C->ru, 4 * M);
+    double* nu = (rounds == 0 || cu != u) ? u : C->ru;
+    double* np = (rounds == 0 || cu != u) ? p : C->ru + 3 * M;
+    HIPCHK(launch_refine_residual(rounds == 0, S.N, S.h, S.mu, c, cu, cp, C->x32, F, shift, nu, np, C->r32, C->rpart,
+                                  NP, s));
+    cu = nu;
+    cp = np;
+    rn = norm(R_RESNORM);
     ++rounds;
   }
-  if (stokes) project(p);
+  if (cu != u) {
+    HIPCHK(hipMemcpyAsync(u, cu, 3 * M * sizeof(double), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(p, cp, M * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
+  if (stokes) {
+    HIPCHK(launch_sum_partials<double>(M, p, C->rpart, NP, s));
+    HIPCHK(launch_reduce(C->rpart, NP, 1, C->rscal, R_SUM, 1, M, s));
+    HIPCHK(launch_add_scalar<double>(M, p, C->rscal, 5, -1.0 / (double)M, s));
+  }
   if (info) {
     info->cg_iters += total;
     info->refine_rounds = rounds;
@@ -586,6 +607,8 @@ void eval_impl(kfbi_ctx* C, const double* phi, double* out, bool vol, kfbi_info*
   HIPCHK(hipStreamSynchronize(s));
   double t2 = now_ms();
   HIPCHK(launch_interp(S.n, C->itp_idx, C->itp_w, C->u, C->ejump, out, s));
+  if (C->cfg.trace == KFBI_TRACE_AVERAGE)
+    HIPCHK(launch_stab(S.n, C->sv_ptr, C->sv_idx, C->sv_w, C->stab_a, phi, out, s));
   HIPCHK(hipStreamSynchronize(s));
   double t3 = now_ms();
   if (info) {
@@ -623,6 +646,10 @@ void adjoint_impl(kfbi_ctx* C, const double* w, double* out, kfbi_info* info) {
   HIPCHK(launch_fill<double>(4 * M, C->F, 0.0, s));
   HIPCHK(launch_interp_T((int64_t)S.uT_node.size(), C->uT_ptr, C->uT_node, C->uT_row, C->uT_w, w, C->F, s));
   transpose_from_velocity(C, w, out, info);
+  if (C->cfg.trace == KFBI_TRACE_AVERAGE) {
+    HIPCHK(launch_stab_T(S.n, C->svT_ptr, C->svT_row, C->svT_w, C->stab_a, w, out, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
   if (info) info->ms_total += now_ms() - t0;
 }
 
@@ -685,7 +712,7 @@ int gmres(kfbi_ctx* C, const double* rhs, double* phi, double tol, int maxit, do
     C->H = dalloc<double>((size_t)(maxit + 2) * (maxit + 1) + 16, C->owned);
     C->gm_max = maxit;
   }
-  if (!C->rpart) C->rpart = dalloc<double>(1024, C->owned);
+  if (!C->rpart) C->rpart = dalloc<double>(4096, C->owned);
   if (!C->rscal) C->rscal = dalloc<double>(16, C->owned);
   const int LD = maxit + 2;  // column stride of H
   double* scratch = C->rscal;  // scratch[5] = norm^2
@@ -977,6 +1004,10 @@ int64_t kfbi_plan_get(const kfbi_plan* p, const char* name, void* out) {
   if (n == "jmap") return copy_out(S.jmap, out);
   if (n == "jfmap") return copy_out(S.jfmap, out);
   if (n == "emap") return copy_out(S.emap, out);
+  if (n == "stab_a") return copy_out(S.stab_a, out);
+  if (n == "sv_ptr") return copy_out(S.sv_ptr, out);
+  if (n == "sv_idx") return copy_out(S.sv_idx, out);
+  if (n == "sv_w") return copy_out(S.sv_w, out);
   if (n == "irr_node") return copy_out(S.irr_node, out);
   if (n == "irr_ptr") return copy_out(S.irr_ptr, out);
   if (n == "arm_t") return copy_out(S.arm_t, out);

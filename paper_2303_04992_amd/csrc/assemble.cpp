@@ -197,6 +197,7 @@ static std::string build_interpolation(Setup& S) {
   S.itp_idx.assign(n * 30, 0);
   S.itp_w.assign(n * 30, 0.0);
   S.emap.assign(n * 3 * 18, 0.0);
+  S.stab_a.assign(n * 3, 0.5);
   std::vector<double> efmap(n * 9, 0.0);
   std::string err;
 #pragma omp parallel for schedule(static)
@@ -258,6 +259,7 @@ static std::string build_interpolation(Setup& S) {
         S.itp_idx[(c * 3 + m) * 10 + q] = (int64_t)m * S.M + li;
         S.itp_w[(c * 3 + m) * 10 + q] = w[q];
         if (S.side[m][li]) continue;  // interior node: no jump term
+        S.stab_a[c * 3 + m] -= w[q];  // exterior weight fraction
         for (int in = 0; in < 21; ++in) {
           const double* o = resp[in];
           double J = o[m];

@@ -57,7 +57,7 @@ hipError_t launch_backsub_combine(int N, int m, const T* F, const T* P, T* G, do
 
 // ---- reductions (float64, deterministic)
 // scal layout: [0] rr, [1] alpha, [2] beta, [3] mean q, [4] rr0, [5] scratch sum, [6] aux
-enum ReduceOp { R_ALPHA = 0, R_BETA = 1, R_SUM = 2, R_INIT_RR = 3 };
+enum ReduceOp { R_ALPHA = 0, R_BETA = 1, R_SUM = 2, R_INIT_RR = 3, R_RESNORM = 4, R_RESNORM0 = 5 };
 hipError_t launch_reduce(const double* partials, int nparts, int nper, double* scal, int op, int stokes,
                          int64_t M, hipStream_t s, double* out = nullptr);  // R_SUM: *out (or scal[5])
 template <typename T>
@@ -82,6 +82,15 @@ hipError_t launch_rhs_minus_t(int64_t M, T* b, const T* Fp, hipStream_t s);
 
 // ---- full-system residual of the MAC scheme (float64)
 // r_u = F_u - (-mu lap u + G p), r_p = F_p - (D u + c p), internal layout
+// mixed refinement: partial sums of F (3 per block, nparts blocks)
+hipError_t launch_refine_prep(int64_t M, const double* F, double* partials, int nparts, hipStream_t s);
+// r32 = (float) F, pressure part minus *shift (shift may be null)
+hipError_t launch_refine_convert(int64_t M, const double* F, const double* shift, float* r32, hipStream_t s);
+// un, pn = u, p (+ 0 if first) + x32; r32 = float32 of the float64 residual F - A(un, pn) (pressure
+// part minus *shift); partial sums
+hipError_t launch_refine_residual(bool first, int N, double h, double mu, double c, const double* u, const double* p,
+                                  const float* x32, const double* F, const double* shift, double* un, double* pn,
+                                  float* r32, double* partials, int nparts, hipStream_t s);
 hipError_t launch_mac_residual(int N, double h, double mu, double c, const double* u, const double* p,
                                const double* Fu, const double* Fp, double* ru, double* rp, hipStream_t s);
 
@@ -95,6 +104,10 @@ hipError_t launch_correct(int64_t nirr, const int64_t* irr_node, const int64_t* 
                           const int8_t* arm_o, const double* arm_a, const double* jumps, double* F, hipStream_t s);
 // probes: out[r] = sum_{q<8} w[8r+q] u[idx[8r+q]], r < 3 m (trilinear)
 hipError_t launch_interp8(int64_t m, const int64_t* idx, const double* w, const double* u, double* out, hipStream_t s);
+hipError_t launch_stab(int64_t n, const int64_t* ptr, const int32_t* idx, const double* sw, const double* a,
+                       const double* phi, double* out, hipStream_t s);
+hipError_t launch_stab_T(int64_t n, const int64_t* ptr, const int32_t* row, const double* sw, const double* a,
+                         const double* w, double* out, hipStream_t s);
 hipError_t launch_interp(int64_t n, const int64_t* idx, const double* w, const double* u, const double* ejump,
                          double* out, hipStream_t s);
 // adjoint

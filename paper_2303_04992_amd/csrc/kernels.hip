@@ -317,6 +317,11 @@ __global__ __launch_bounds__(EW_NT) void k_reduce(const double* __restrict__ par
     } else if (op == R_BETA) {
       scal[2] = (scal[0] > 0.0) ? tot[0] / scal[0] : 0.0;
       scal[0] = tot[0];
+    } else if (op == R_RESNORM || op == R_RESNORM0) {
+      // |r_u|^2 + |r_p - mean r_p|^2 (Stokes: the pressure equation is taken modulo constants);
+      // R_RESNORM0 also keeps the mean of the pressure part in scal[6]
+      scal[5] = tot[0] + tot[2] - (stokes ? tot[1] * tot[1] / (double)M : 0.0);
+      if (op == R_RESNORM0) scal[6] = tot[1] / (double)M;
     } else if (op == R_INIT_RR) {
       scal[0] = tot[0];
       scal[4] = tot[0];
@@ -428,6 +433,115 @@ __global__ void k_res_p(int N, double h, double cc, const double* __restrict__ u
 }
 
 // ---------------------------------------------------------------------------------------
+// mixed-precision refinement (float64 residual of the full MAC system, float32 correction)
+// ---------------------------------------------------------------------------------------
+// per-block partial sums of F_u.F_u, sum F_p, F_p.F_p (four fields F)
+__global__ __launch_bounds__(EW_NT) void k_refine_prep(int64_t M, const double* __restrict__ F,
+                                                    double* __restrict__ partials) {
+  __shared__ double red[EW_NT / 64];
+  double su = 0, sp = 0, spp = 0;
+  for (int64_t i = (int64_t)blockIdx.x * EW_NT + threadIdx.x; i < M; i += (int64_t)gridDim.x * EW_NT) {
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      const double v = F[m * M + i];
+      su += v * v;
+    }
+    const double v = F[3 * M + i];
+    sp += v;
+    spp += v * v;
+  }
+  const double t0 = block_sum(su, red), t1 = block_sum(sp, red), t2 = block_sum(spp, red);
+  if (threadIdx.x == 0) {
+    partials[3 * blockIdx.x] = t0;
+    partials[3 * blockIdx.x + 1] = t1;
+    partials[3 * blockIdx.x + 2] = t2;
+  }
+}
+
+// r32 = (float) F, the pressure part shifted by -(*shift) (Stokes: the mean of F_p, which
+// the float32 solve would otherwise have to cancel against a much smaller residual)
+__global__ void k_refine_convert(int64_t M, const double* __restrict__ F, const double* __restrict__ shift,
+                                 float* __restrict__ r32) {
+  const double sh = shift ? *shift : 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 4 * M; i += (int64_t)gridDim.x * blockDim.x)
+    r32[i] = (float)(i >= 3 * M ? F[i] - sh : F[i]);
+}
+
+// One refinement update and the new residual, in one pass over the cells (internal layout,
+// z fastest): u' = u + x32_u, p' = p + x32_p (u = p = 0 in the first round), then
+//   r_u = F_u - (-mu lap_h u' + G p'),   r_p = F_p - (D u' + c p')
+// in float64 (face 0 and face N of each u_m are the box faces, zero; tangential ghosts by
+// reflection), written as float32 for the next inner solve (pressure part shifted by
+// -(*shift), as in k_refine_convert), with per-block partial sums of r_u.r_u and of the
+// shifted r_p and r_p.r_p.  Neighbour values of u' are formed on the fly, so u', p' go to
+// buffers other than u, p.
+template <bool FIRST>
+__global__ __launch_bounds__(EW_NT) void k_refine_residual(int N, double h, double mu, double cc,
+                                                        const double* __restrict__ u, const double* __restrict__ p,
+                                                        const float* __restrict__ x32, const double* __restrict__ F,
+                                                        const double* __restrict__ shift, double* __restrict__ un,
+                                                        double* __restrict__ pn, float* __restrict__ r32,
+                                                        double* __restrict__ partials) {
+  __shared__ double red[EW_NT / 64];
+  const double sh = shift ? *shift : 0.0;
+  const int64_t M = (int64_t)N * N * N;
+  const double ih2 = 1.0 / (h * h), ih = 1.0 / h;
+  const int64_t st[3] = {(int64_t)N * N, N, 1};
+  auto U = [&](int m, int64_t j) -> double {
+    const double v = (double)x32[m * M + j];
+    return FIRST ? v : u[m * M + j] + v;
+  };
+  auto P = [&](int64_t j) -> double {
+    const double v = (double)x32[3 * M + j];
+    return FIRST ? v : p[j] + v;
+  };
+  double su = 0, sp = 0, spp = 0;
+  for (int64_t i = (int64_t)blockIdx.x * EW_NT + threadIdx.x; i < M; i += (int64_t)gridDim.x * EW_NT) {
+    const int id[3] = {(int)(i / st[0]), (int)((i / N) % N), (int)(i % N)};
+    const double pc = P(i);
+    double div = 0;
+#pragma unroll
+    for (int m = 0; m < 3; ++m) {
+      const double c = (id[m] == 0) ? 0.0 : U(m, i);  // face 0 is the box face
+      double lap = 0, hi_m = 0;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        double lo, hi;
+        if (d == m) {
+          lo = (id[d] > 1) ? U(m, i - st[d]) : 0.0;     // face a-1 (face 0 is zero)
+          hi = (id[d] + 1 < N) ? U(m, i + st[d]) : 0.0;  // face N is the box face
+          hi_m = hi;
+        } else {
+          lo = (id[d] > 0) ? U(m, i - st[d]) : -c;       // ghost reflection
+          hi = (id[d] + 1 < N) ? U(m, i + st[d]) : -c;
+        }
+        lap += (lo - 2.0 * c + hi) * ih2;
+      }
+      div += (hi_m - c) * ih;
+      double r = 0.0;
+      if (id[m] > 0) {
+        const double gp = (pc - P(i - st[m])) * ih;     // cells a-1, a
+        r = F[m * M + i] - (-mu * lap + gp);
+      }
+      un[m * M + i] = c;
+      r32[m * M + i] = (float)r;
+      su += r * r;
+    }
+    const double rp = F[3 * M + i] - (div + cc * pc) - sh;
+    pn[i] = pc;
+    r32[3 * M + i] = (float)rp;
+    sp += rp;
+    spp += rp * rp;
+  }
+  const double t0 = block_sum(su, red), t1 = block_sum(sp, red), t2 = block_sum(spp, red);
+  if (threadIdx.x == 0) {
+    partials[3 * blockIdx.x] = t0;
+    partials[3 * blockIdx.x + 1] = t1;
+    partials[3 * blockIdx.x + 2] = t2;
+  }
+}
+
+// ---------------------------------------------------------------------------------------
 // surface stages (float64)
 // ---------------------------------------------------------------------------------------
 __global__ void k_fit_jump(int64_t T, const int64_t* __restrict__ nb_ptr, const int32_t* __restrict__ nb_idx,
@@ -502,6 +616,37 @@ __global__ void k_interp(int64_t n, const int64_t* __restrict__ idx, const doubl
 #pragma unroll
   for (int q = 0; q < 10; ++q) s += w[10 * r + q] * u[idx[10 * r + q]];
   out[r] = s;
+}
+
+// average trace form (control point c, component m, r = 3c + m):
+//   out[r] += a[r] (phi[r] - sum_e sw[e] phi[3 idx[e] + m]),  a = 1/2 - exterior weight fraction
+__global__ void k_stab(int64_t n, const int64_t* __restrict__ ptr, const int32_t* __restrict__ idx,
+                       const double* __restrict__ sw, const double* __restrict__ a, const double* __restrict__ phi,
+                       double* __restrict__ out) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= 3 * n) return;
+  const int64_t c = r / 3;
+  const int m = (int)(r - 3 * c);
+  double s = 0;
+  for (int64_t e = ptr[c]; e < ptr[c + 1]; ++e) s += sw[e] * phi[3 * (int64_t)idx[e] + m];
+  out[r] += a[r] * (phi[r] - s);
+}
+
+// its transpose, gathered over the transposed CSR (rows ascending):
+//   out[r] += a[r] w[r] - sum_e swT[e] a[3 row[e] + m] w[3 row[e] + m]
+__global__ void k_stab_T(int64_t n, const int64_t* __restrict__ ptr, const int32_t* __restrict__ row,
+                         const double* __restrict__ sw, const double* __restrict__ a, const double* __restrict__ w,
+                         double* __restrict__ out) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= 3 * n) return;
+  const int64_t j = r / 3;
+  const int m = (int)(r - 3 * j);
+  double s = a[r] * w[r];
+  for (int64_t e = ptr[j]; e < ptr[j + 1]; ++e) {
+    const int64_t q = 3 * (int64_t)row[e] + m;
+    s -= sw[e] * a[q] * w[q];
+  }
+  out[r] += s;
 }
 
 __global__ void k_interp8(int64_t m, const int64_t* __restrict__ idx, const double* __restrict__ w,
@@ -826,6 +971,26 @@ hipError_t launch_mac_residual(int N, double h, double mu, double c, const doubl
   return hipGetLastError();
 }
 
+hipError_t launch_refine_prep(int64_t M, const double* F, double* partials, int nparts, hipStream_t s) {
+  hipLaunchKernelGGL(k_refine_prep, dim3(nparts), dim3(EW_NT), 0, s, M, F, partials);
+  return hipGetLastError();
+}
+hipError_t launch_refine_convert(int64_t M, const double* F, const double* shift, float* r32, hipStream_t s) {
+  hipLaunchKernelGGL(k_refine_convert, dim3(ew_blocks(4 * M)), dim3(256), 0, s, M, F, shift, r32);
+  return hipGetLastError();
+}
+hipError_t launch_refine_residual(bool first, int N, double h, double mu, double c, const double* u, const double* p,
+                                  const float* x32, const double* F, const double* shift, double* un, double* pn,
+                                  float* r32, double* partials, int nparts, hipStream_t s) {
+  if (first)
+    hipLaunchKernelGGL(k_refine_residual<true>, dim3(nparts), dim3(EW_NT), 0, s, N, h, mu, c, u, p, x32, F, shift, un,
+                       pn, r32, partials);
+  else
+    hipLaunchKernelGGL(k_refine_residual<false>, dim3(nparts), dim3(EW_NT), 0, s, N, h, mu, c, u, p, x32, F, shift,
+                       un, pn, r32, partials);
+  return hipGetLastError();
+}
+
 static inline int gb(int64_t n) { return (int)((n + 255) / 256 > 0 ? (n + 255) / 256 : 1); }
 
 hipError_t launch_fit_jump(int64_t T, const int64_t* nb_ptr, const int32_t* nb_idx, const double* fitw,
@@ -849,6 +1014,16 @@ hipError_t launch_correct(int64_t nirr, const int64_t* irr_node, const int64_t* 
 hipError_t launch_interp(int64_t n, const int64_t* idx, const double* w, const double* u, const double* ejump,
                          double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_interp, dim3(gb(3 * n)), dim3(256), 0, s, n, idx, w, u, ejump, out);
+  return hipGetLastError();
+}
+hipError_t launch_stab(int64_t n, const int64_t* ptr, const int32_t* idx, const double* sw, const double* a,
+                       const double* phi, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_stab, dim3(gb(3 * n)), dim3(256), 0, s, n, ptr, idx, sw, a, phi, out);
+  return hipGetLastError();
+}
+hipError_t launch_stab_T(int64_t n, const int64_t* ptr, const int32_t* row, const double* sw, const double* a,
+                         const double* w, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_stab_T, dim3(gb(3 * n)), dim3(256), 0, s, n, ptr, row, sw, a, w, out);
   return hipGetLastError();
 }
 hipError_t launch_interp8(int64_t m, const int64_t* idx, const double* w, const double* u, double* out, hipStream_t s) {

@@ -89,6 +89,18 @@ struct Setup {
   std::vector<int64_t> fT_ptr;           // fit^T: CSR over control points
   std::vector<int64_t> fT_entry;         // neighbour-entry index e (target found by search)
   std::vector<int32_t> fT_target;
+
+  // average trace form: K phi += (1/2 - alpha)(phi - S phi) per control point and component,
+  // alpha = exterior weight fraction of the interpolation stencil, S phi = least-squares
+  // fitted value at the control point (before the density replaces it); CSR over control
+  // points with its transpose
+  std::vector<double> stab_a;            // 1/2 - alpha, 3 per control point
+  std::vector<int64_t> sv_ptr;
+  std::vector<int32_t> sv_idx;
+  std::vector<double> sv_w;
+  std::vector<int64_t> svT_ptr;
+  std::vector<int32_t> svT_row;
+  std::vector<double> svT_w;
 };
 
 // Builds everything; returns "" on success or an error message (prefixed "GEOM:" for

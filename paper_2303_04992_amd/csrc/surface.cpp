@@ -209,7 +209,7 @@ std::string build_fits(Setup& S) {
   for (int64_t c = 0; c < n; ++c) items[fill[cid[c]]++] = c;  // ascending within a cell
 
   std::vector<std::vector<int32_t>> nb(T);
-  std::vector<std::vector<double>> W(T);
+  std::vector<std::vector<double>> W(T), raw0(T);  // raw0: fitted value weights (control targets)
   std::string err;
 #pragma omp parallel for schedule(dynamic, 64)
   for (int64_t t = 0; t < T; ++t) {
@@ -270,6 +270,7 @@ std::string build_fits(Setup& S) {
     for (int r2 = 0; r2 < 6; ++r2)
       for (int q = 0; q < K; ++q) P[r2 * K + q] *= sc[r2];
     if (S.cp_of[t] >= 0) {
+      raw0[t].assign(P.begin(), P.begin() + K);
       for (int q = 0; q < K; ++q) P[q] = (L[q] == S.cp_of[t]) ? 1.0 : 0.0;
     }
     nb[t] = L;
@@ -286,6 +287,28 @@ std::string build_fits(Setup& S) {
     std::copy(nb[t].begin(), nb[t].end(), S.nb_idx.begin() + S.nb_ptr[t]);
     std::copy(W[t].begin(), W[t].end(), S.fitw.begin() + 6 * S.nb_ptr[t]);
   }
+  // fitted-value rows of the control points and their transpose
+  S.sv_ptr.assign(n + 1, 0);
+  for (int64_t c = 0; c < n; ++c) S.sv_ptr[c + 1] = S.sv_ptr[c] + (int64_t)nb[S.cp_target[c]].size();
+  S.sv_idx.resize(S.sv_ptr[n]);
+  S.sv_w.resize(S.sv_ptr[n]);
+  S.svT_ptr.assign(n + 1, 0);
+  for (int64_t c = 0; c < n; ++c) {
+    const int64_t t = S.cp_target[c];
+    std::copy(nb[t].begin(), nb[t].end(), S.sv_idx.begin() + S.sv_ptr[c]);
+    std::copy(raw0[t].begin(), raw0[t].end(), S.sv_w.begin() + S.sv_ptr[c]);
+    for (int32_t j : nb[t]) S.svT_ptr[j + 1]++;
+  }
+  for (int64_t j = 0; j < n; ++j) S.svT_ptr[j + 1] += S.svT_ptr[j];
+  S.svT_row.resize(S.sv_ptr[n]);
+  S.svT_w.resize(S.sv_ptr[n]);
+  std::vector<int64_t> pos(S.svT_ptr.begin(), S.svT_ptr.end() - 1);
+  for (int64_t c = 0; c < n; ++c)  // ascending c within each transposed row
+    for (int64_t e = S.sv_ptr[c]; e < S.sv_ptr[c + 1]; ++e) {
+      const int64_t q = pos[S.sv_idx[e]]++;
+      S.svT_row[q] = (int32_t)c;
+      S.svT_w[q] = S.sv_w[e];
+    }
   return "";
 }
 

@@ -84,7 +84,9 @@ def test_probe_adjoint_and_adjoint_solve(K):
     assert res.item() < 1e-10
 
 
-@pytest.mark.parametrize("name,N,ndir,gtol", [("sphere32", 32, 16, 1e-12), ("star128", 64, 4, 1e-10)])
+# the last case is the full-size workload: Stokes star at 256^3, 4096 probes, 16 directions
+@pytest.mark.parametrize("name,N,ndir,gtol", [("sphere32", 32, 16, 1e-12), ("star128", 64, 4, 1e-10),
+                                              ("star256", 256, 16, 1e-10)])
 def test_gradient_wrt_dirichlet_data_matches_central_differences(K, name, N, ndir, gtol):
     import torch
     cfg = KI.WORKLOADS[name].with_N(N)
@@ -116,6 +118,8 @@ def test_gradient_wrt_dirichlet_data_matches_central_differences(K, name, N, ndi
             an = float((grad * d).sum().item())
             rel = abs(fd - an) / max(abs(fd), 1e-30)
             worst = max(worst, rel)
+            if N >= 256:
+                _say(f"   direction: fd {fd:.10e} adjoint {an:.10e} rel {rel:.2e}")
     _say(f"   loss {L.item():.6e}  worst rel diff {worst:.3e} over {ndir} directions, "
          f"adjoint GMRES iterations {adj_iters}")
     assert worst < 1e-6

@@ -93,10 +93,11 @@ def test_full_size_matches_stored_oracle(K):
     if not os.path.exists(path):
         pytest.skip("oracle reference at 256^3 not generated")
     ko = np.load(path)
+    form = json.load(open(path.replace(".npy", ".json"))).get("form", "interior")
     cfg = KI.WORKLOADS["star256"]
     for prec, tol in ((0, 1e-10), (1, 1e-6)):
-        _say(f"[full size] star256 precision={prec}")
-        op = K.Operator(cfg, prec, cg_rtol=1e-12 if prec == 0 else 1e-9)
+        _say(f"[full size] star256 precision={prec} trace={form}")
+        op = K.Operator(cfg, prec, cg_rtol=1e-12 if prec == 0 else 1e-9, trace=form)
         xyz, _ = op.points()
         assert xyz.shape == ko.shape
         phi = KI.exact_u(cfg.solution, xyz[:, 0], xyz[:, 1], xyz[:, 2])

@@ -126,3 +126,26 @@ def _compare(name, N):
 @pytest.mark.parametrize("name,N", [("sphere32", 32), ("ellip128", 32), ("star128", 32)])
 def test_host_setup_matches_oracle(name, N):
     _compare(name, N)
+
+
+@pytest.mark.parametrize("name,N", [("sphere32", 32), ("star128", 32)])
+def test_average_trace_maps_match_oracle(name, N):
+    """The library applies the average trace form as (1/2 - alpha)(phi - S phi) with its own
+    exterior weight fractions and fitted-value rows; the oracle forms 1/2 phi + (u+ + u-)/2
+    from two-sided jump-function matrices.  The grid parts are common, so the difference of
+    the two forms must agree."""
+    from oracle.kfbi import Oracle
+    K = _lib()
+    cfg = KI.WORKLOADS[name].with_N(N)
+    P = K.Plan(cfg, trace="average")
+    Oa = Oracle(cfg, form="average")
+    n = Oa.n
+    a = P.get("stab_a").reshape(n, 3)
+    ptr, idx, w = P.get("sv_ptr"), P.get("sv_idx"), P.get("sv_w")
+    S = sps.csr_matrix((w, idx, ptr), shape=(n, n))
+    phi = KI.random_density(n)
+    lib = a * (phi - S @ phi)
+    jr = Oa.Jmat @ (Oa.FitRaw @ phi.ravel())
+    ji = Oa.Jmat @ (Oa.Fit @ phi.ravel())
+    orc = (0.5 * phi.ravel() + Oa.Eavg @ jr - Oa.E @ ji).reshape(n, 3)
+    assert np.abs(lib - orc).max() < 1e-11 * np.abs(orc).max()

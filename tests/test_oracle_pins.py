@@ -252,12 +252,14 @@ def test_fit_convergence_rates_on_sphere():
 # ------------------------------------------------------------------------------------------
 # The operator: exact identities of the continuous problem that the scheme keeps exactly
 # ------------------------------------------------------------------------------------------
+@pytest.mark.parametrize("form", ["interior", "average"])
 @pytest.mark.parametrize("name,N", [("sphere32", 16), ("ellip128", 24), ("star128", 32)])
-def test_K_of_constant_density_is_identity(name, N):
+def test_K_of_constant_density_is_identity(name, N, form):
     """A constant density c gives the interface solution u = c in Omega, 0 outside, p = 0;
     every corrected MAC equation holds exactly and the interpolation reproduces constants,
-    so K c = c to rounding.  This pins the sign of every correction term."""
-    O = Oracle(KI.WORKLOADS[name].with_N(N))
+    so K c = c to rounding.  This pins the sign of every correction term.  In the average
+    form the fitted value of a constant is the constant, so the identity holds there too."""
+    O = Oracle(KI.WORKLOADS[name].with_N(N), form=form)
     c = np.array([0.3, -0.7, 1.1])
     K = O.eval(np.tile(c, (O.n, 1)))
     assert np.abs(K - c).max() < 1e-12
@@ -310,12 +312,56 @@ def test_adjoint_dot_product_and_columns():
             assert abs(col[i] - row[j]) < 1e-12
 
 
+def _exterior_weight_fraction(O):
+    """alpha[c, m] = sum of the interpolation weights of the stencil nodes outside Omega,
+    from the stencil and weight definitions of the interpolation (Sec. 4.4)."""
+    from oracle.interp import stencil, weights
+    alpha = np.zeros((O.n, 3))
+    for c, x in enumerate(O.points):
+        for m in range(3):
+            nodes = stencil(x, m, O.N, O.lo, O.h)
+            w, _ = weights(x, nodes, m, O.lo, O.h)
+            alpha[c, m] = sum(w[i] for i in range(10) if not O.sides[m][tuple(nodes[i])])
+    return alpha
+
+
+def test_average_form_reduces_to_a_value_fit_correction():
+    """The mean of the two limits uses the ten-node weights, which reproduce quadratics at the
+    control point, so every Taylor term of the jump function cancels in (u+ + u-)/2 except
+    the value: average - interior = (1/2 - alpha)(phi - S phi), with alpha the exterior weight
+    fraction and S phi the fitted value.  Pins the two-sided jump-function matrix."""
+    cfg = KI.WORKLOADS["ellip128"].with_N(16)
+    Oi, Oa = Oracle(cfg, form="interior"), Oracle(cfg, form="average")
+    _, _, S = fit_matrix(Oi.cr, Oi.h, raw_values=True)
+    alpha = _exterior_weight_fraction(Oi)
+    x = np.random.default_rng(3).standard_normal((Oi.n, 3))
+    d = Oa.eval(x) - Oi.eval(x)
+    assert np.abs(d - (0.5 - alpha) * (x - S @ x)).max() < 1e-12 * np.abs(d).max()
+    assert alpha.min() < 0.1 and alpha.max() > 0.9  # the stencil's exterior fraction spans [0, 1]
+    y = np.random.default_rng(4).standard_normal((Oi.n, 3))
+    assert abs(np.vdot(Oa.eval(x), y) - np.vdot(x, Oa.eval_adjoint(y))) < 1e-11 * np.abs(d).sum()
+
+
+def test_average_form_converges_faster_on_rough_data():
+    """GMRES on a random (grid-scale rough) right-hand side: the interior form behaves like
+    multiplication by the exterior weight fraction on such data, the average form like 1/2."""
+    cfg = KI.WORKLOADS["sphere32"].with_N(16)
+    its = {}
+    for form in ("interior", "average"):
+        O = Oracle(cfg, form=form)
+        b = KI.random_directions(O.n, 1, seed=1)[0].ravel()
+        _, its[form], hist = O.gmres(lambda v: O.eval(v.reshape(-1, 3)).ravel(), b, 1e-10, 200)
+        assert hist[-1] < 1e-10
+    assert its["average"] < 0.6 * its["interior"], its
+
+
 @pytest.mark.slow
-def test_bvp_second_order_on_sphere():
+@pytest.mark.parametrize("form", ["interior", "average"])
+def test_bvp_second_order_on_sphere(form):
     res = []
     for N in (16, 32):
         cfg = KI.WORKLOADS["sphere32"].with_N(N)
-        O = Oracle(cfg)
+        O = Oracle(cfg, form=form)
         X = O.points
         g = KI.exact_u(cfg.solution, X[:, 0], X[:, 1], X[:, 2])
         f = lambda x, y, z: KI.body_force(cfg.solution, x, y, z, cfg.mu, cfg.lam)
