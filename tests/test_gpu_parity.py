@@ -158,3 +158,30 @@ def test_error_paths(K):
     with pytest.raises(K.KfbiError) as e:
         op2.eval(KI.random_density(op2.n))
     assert e.value.status == K.ENOCONV
+
+
+def test_512_navier_matches_stored_oracle_sample(K):
+    """Navier, lambda = 100 (nu = 0.495), star r = 0.5 + 0.12 sin 5t cos 3p at 512^3: the mixed
+    form's K phi (phi = exact velocity) and K^T w (w = random density) against the oracle's
+    values on a seeded sample of 4096 control points (tests/golden/make_oracle_reference.py
+    --sample 4096 --adjoint), to the mixed form's 1e-6."""
+    path = os.path.join(HERE, "golden", "star512n_sample.npz")
+    if not os.path.exists(path):
+        pytest.skip("oracle sample at 512^3 not generated")
+    meta = json.load(open(path.replace(".npz", ".json")))
+    z = np.load(path)
+    cfg = KI.WORKLOADS["star512n"]
+    _say(f"[512] star512n mixed, trace={meta.get('form', 'interior')}")
+    op = K.Operator(cfg, K.MIXED_FP32, cg_rtol=1e-9, inner_rtol=1e-5, trace=meta.get("form", "interior"))
+    assert op.n == meta["n_points"]
+    xyz, _ = op.points()
+    phi = KI.exact_u(cfg.solution, xyz[:, 0], xyz[:, 1], xyz[:, 2])
+    idx = z["idx"]
+    kg = op.eval(phi).cpu().numpy()[idx]
+    r = _rel(kg, z["Kphi"])
+    _say(f"   K phi: rel l2 over the sample {r:.3e}  info {op.last_info}")
+    assert r < 1e-6
+    kt = op.eval_adjoint(KI.random_density(op.n)).cpu().numpy()[idx]
+    r = _rel(kt, z["KTw"])
+    _say(f"   K^T w: rel l2 over the sample {r:.3e}  info {op.last_info}")
+    assert r < 1e-6
