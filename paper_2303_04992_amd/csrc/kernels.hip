@@ -55,13 +55,26 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
 
 constexpr int EW_NT = 256;  // threads per block of the elementwise and reduction kernels
 
+// Contiguous z tile (W pencils of N, 16-byte aligned) -> LDS rows of stride N + 1.  Every
+// load of the thread is issued before the first LDS write (vector loads, unrolled).
 template <typename T, int N, int NT>
-__device__ __forceinline__ void load_tile(T* lds, const T* __restrict__ g, int axis, const TileAddr& a) {
-  constexpr int W = TileCfg<T, N, DCT2>::W, RS = N + 1;
-  for (int e = threadIdx.x; e < W * N; e += NT) {
-    int p, n;
-    tile_elem<W, N>(axis, e, p, n);
-    lds[p * RS + n] = g[a.base + p * a.pstride + n * a.nstride];
+__device__ __forceinline__ void load_tile_z(T* lds, const T* __restrict__ g) {
+  constexpr int W = TileCfg<T, N, DCT2>::W, RS = N + 1, VEC = V16<T>::n;
+  constexpr int NV = W * N / VEC, PER = (NV + NT - 1) / NT;
+  V16<T> v[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = threadIdx.x + u * NT;
+    if (NV % NT == 0 || e < NV) v[u] = reinterpret_cast<const V16<T>*>(g)[e];
+  }
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = threadIdx.x + u * NT;
+    if (NV % NT == 0 || e < NV) {
+      const int p = (e * VEC) / N, n = (e * VEC) - p * N;
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) lds[p * RS + n + q] = v[u].a[q];
+    }
   }
   __syncthreads();
 }
@@ -87,20 +100,67 @@ __global__ __launch_bounds__(256) void k_pass(const T* in, T* out, int axis, Tab
   extern __shared__ __align__(16) unsigned char smem[];
   T* lds = reinterpret_cast<T*>(smem);
   using S = TileCfg<T, N, KIND>;
+  using O = OutItems<T, N, KIND>;
   constexpr int W = S::W, NT = S::NT;
   const TileAddr a = tile_addr<W, N>(axis, blockIdx.x);
-  auto st = [&](int p, int n, T v) {
-    const long gi = a.base + p * a.pstride + n * a.nstride;
-    if (ACC)
-      out[gi] += v;
-    else
-      out[gi] = v;
-  };
   if (axis == 2) {
-    load_tile<T, N, NT>(lds, in, axis, a);
-    transform_store<T, N, KIND>(lds, LdsSrc<T, N>{lds}, tb, 2, st);
+    load_tile_z<T, N, NT>(lds, in + a.base);
+    fft_tile<T, N, KIND>(lds, LdsSrc<T, N>{lds}, tb);
+    V16<T>* o = reinterpret_cast<V16<T>*>(out + a.base);
+    constexpr int RV = N / O::VEC;  // vectors per pencil
+    V16<T> old[ACC ? 2 * O::PER_Z : 1];
+    if constexpr (ACC) {
+#pragma unroll
+      for (int u = 0; u < O::PER_Z; ++u) {
+        int j, k0;
+        if (O::z(u, j, k0)) {
+          old[2 * u] = o[(2 * j) * RV + k0 / O::VEC];
+          old[2 * u + 1] = o[(2 * j + 1) * RV + k0 / O::VEC];
+        }
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < O::PER_Z; ++u) {
+      int j, k0;
+      if (O::z(u, j, k0)) {
+        V16<T> v0, v1;
+        O::z_values(lds, tb, j, k0, v0, v1);
+        if constexpr (ACC) {
+#pragma unroll
+          for (int q = 0; q < O::VEC; ++q) {
+            v0.a[q] += old[2 * u].a[q];
+            v1.a[q] += old[2 * u + 1].a[q];
+          }
+        }
+        o[(2 * j) * RV + k0 / O::VEC] = v0;
+        o[(2 * j + 1) * RV + k0 / O::VEC] = v1;
+      }
+    }
   } else {
-    transform_store<T, N, KIND>(lds, GlobSrc<T>{in, a.base, a.nstride}, tb, axis, st);
+    fft_tile<T, N, KIND>(lds, GlobSrc<T>{in, a.base, a.nstride}, tb);
+    C2<T>* o = reinterpret_cast<C2<T>*>(out + a.base);
+    const long ns = a.nstride / 2;  // in units of element pairs
+    C2<T> old[ACC ? O::PER_XY : 1];
+    if constexpr (ACC) {
+#pragma unroll
+      for (int u = 0; u < O::PER_XY; ++u) {
+        int j, k;
+        if (O::xy(u, j, k)) old[u] = o[k * ns + j];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < O::PER_XY; ++u) {
+      int j, k;
+      if (O::xy(u, j, k)) {
+        C2<T> v;
+        post_pair<T, N, KIND>(lds, tb, j, k, v.x, v.y);
+        if constexpr (ACC) {
+          v.x += old[u].x;
+          v.y += old[u].y;
+        }
+        o[k * ns + j] = v;
+      }
+    }
   }
 }
 
@@ -165,9 +225,17 @@ __device__ void xmid_body(T* lds, T* field, int mc, double mu, const double* sig
   }
   __syncthreads();
   fft_core<T, N, KI>(lds, [&](int j, int n) { return cb[j * ZS + n]; }, tb);
-  for (int e = threadIdx.x; e < W * N; e += NT) {
-    const int k = e / W, p = e - k * W;
-    field[a.base + p * a.pstride + k * a.nstride] = post_value<T, N, KI>(lds, tb, p, k);
+  using O = OutItems<T, N, KI>;
+  C2<T>* o = reinterpret_cast<C2<T>*>(field + a.base);
+  const long ns = a.nstride / 2;
+#pragma unroll 4
+  for (int u = 0; u < O::PER_XY; ++u) {
+    int j, k;
+    if (O::xy(u, j, k)) {
+      C2<T> v;
+      post_pair<T, N, KI>(lds, tb, j, k, v.x, v.y);
+      o[k * ns + j] = v;
+    }
   }
 }
 
@@ -192,9 +260,10 @@ __global__ __launch_bounds__(256) void k_zscale_inv(const T* __restrict__ in, T*
   extern __shared__ __align__(16) unsigned char smem[];
   T* lds = reinterpret_cast<T*>(smem);
   using S = TileCfg<T, N, KI>;
+  using O = OutItems<T, N, KI>;
   constexpr int W = S::W, RS = N + 1, NT = S::NT;
   const TileAddr a = tile_addr<W, N>(2, blockIdx.x);
-  load_tile<T, N, NT>(lds, in, 2, a);
+  load_tile_z<T, N, NT>(lds, in + a.base);
   for (int e = threadIdx.x; e < W * N; e += NT) {
     const int p = e / N, k = e - p * N;
     const int q = blockIdx.x * W + p;
@@ -204,7 +273,19 @@ __global__ __launch_bounds__(256) void k_zscale_inv(const T* __restrict__ in, T*
     lds[p * RS + k] *= T(sg / (mu * lam));
   }
   __syncthreads();
-  transform_store<T, N, KI>(lds, LdsSrc<T, N>{lds}, tb, 2, [&](int p, int n, T v) { out[a.base + p * N + n] = v; });
+  fft_tile<T, N, KI>(lds, LdsSrc<T, N>{lds}, tb);
+  V16<T>* o = reinterpret_cast<V16<T>*>(out + a.base);
+  constexpr int RV = N / O::VEC;
+#pragma unroll
+  for (int u = 0; u < O::PER_Z; ++u) {
+    int j, k0;
+    if (O::z(u, j, k0)) {
+      V16<T> v0, v1;
+      O::z_values(lds, tb, j, k0, v0, v1);
+      o[(2 * j) * RV + k0 / O::VEC] = v0;
+      o[(2 * j + 1) * RV + k0 / O::VEC] = v1;
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -217,18 +298,48 @@ __global__ __launch_bounds__(256) void k_zfwd_cg(const T* __restrict__ r, T* __r
   extern __shared__ __align__(16) unsigned char smem[];
   T* lds = reinterpret_cast<T*>(smem);
   using S = TileCfg<T, N, DST2>;
-  constexpr int W = S::W, RS = N + 1, NT = S::NT;
+  using O = OutItems<T, N, DST2>;
+  constexpr int W = S::W, RS = N + 1, NT = S::NT, VEC = V16<T>::n;
+  constexpr int NV = W * N / VEC, PER = (NV + NT - 1) / NT;
   const T beta = T(scal[2]);
   const TileAddr a = tile_addr<W, N>(2, blockIdx.x);
-  for (int e = threadIdx.x; e < W * N; e += NT) {
-    const int p = e / N, n = e - p * N;
-    const long gi = a.base + (long)p * N + n;
-    const T v = r[gi] + beta * d[gi];
-    d[gi] = v;
-    lds[p * RS + n] = v;
+  const V16<T>* rv = reinterpret_cast<const V16<T>*>(r + a.base);
+  V16<T>* dv = reinterpret_cast<V16<T>*>(d + a.base);
+  V16<T> x[PER], y[PER];
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = threadIdx.x + u * NT;
+    if (NV % NT == 0 || e < NV) {
+      x[u] = rv[e];
+      y[u] = dv[e];
+    }
+  }
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int e = threadIdx.x + u * NT;
+    if (NV % NT == 0 || e < NV) {
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) x[u].a[q] += beta * y[u].a[q];
+      dv[e] = x[u];
+      const int p = (e * VEC) / N, n = (e * VEC) - p * N;
+#pragma unroll
+      for (int q = 0; q < VEC; ++q) lds[p * RS + n + q] = x[u].a[q];
+    }
   }
   __syncthreads();
-  transform_store<T, N, DST2>(lds, LdsSrc<T, N>{lds}, tb, 2, [&](int p, int n, T v) { T1[a.base + p * N + n] = v; });
+  fft_tile<T, N, DST2>(lds, LdsSrc<T, N>{lds}, tb);
+  V16<T>* o = reinterpret_cast<V16<T>*>(T1 + a.base);
+  constexpr int RV = N / VEC;
+#pragma unroll
+  for (int u = 0; u < O::PER_Z; ++u) {
+    int j, k0;
+    if (O::z(u, j, k0)) {
+      V16<T> v0, v1;
+      O::z_values(lds, tb, j, k0, v0, v1);
+      o[(2 * j) * RV + k0 / VEC] = v0;
+      o[(2 * j + 1) * RV + k0 / VEC] = v1;
+    }
+  }
 }
 
 // q += DCT-III_z(B) + c d; per-block partial sums of d.q, q, d
@@ -239,19 +350,49 @@ __global__ __launch_bounds__(256) void k_zinv_cg(const T* __restrict__ B, T* __r
   __shared__ double red[4];
   T* lds = reinterpret_cast<T*>(smem);
   using S = TileCfg<T, N, DCT3>;
-  constexpr int W = S::W, NT = S::NT;
+  using O = OutItems<T, N, DCT3>;
+  constexpr int W = S::W, NT = S::NT, VEC = V16<T>::n, RV = N / VEC;
   const TileAddr a = tile_addr<W, N>(2, blockIdx.x);
-  load_tile<T, N, NT>(lds, B, 2, a);
+  load_tile_z<T, N, NT>(lds, B + a.base);
+  fft_tile<T, N, DCT3>(lds, LdsSrc<T, N>{lds}, tb);
+  V16<T>* qv = reinterpret_cast<V16<T>*>(q + a.base);
+  const V16<T>* dv = reinterpret_cast<const V16<T>*>(d + a.base);
+  // every q and d vector of the thread is requested before the first use
+  V16<T> qo[2 * O::PER_Z], dd[2 * O::PER_Z];
+#pragma unroll
+  for (int u = 0; u < O::PER_Z; ++u) {
+    int j, k0;
+    if (O::z(u, j, k0)) {
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        qo[2 * u + h] = qv[(2 * j + h) * RV + k0 / VEC];
+        dd[2 * u + h] = dv[(2 * j + h) * RV + k0 / VEC];
+      }
+    }
+  }
   double sdq = 0, sq = 0, sd = 0;
-  transform_store<T, N, DCT3>(lds, LdsSrc<T, N>{lds}, tb, 2, [&](int p, int n, T v) {
-    const long gi = a.base + (long)p * N + n;
-    const T dv = d[gi];
-    const T qv = q[gi] + v + T(c) * dv;
-    q[gi] = qv;
-    sdq += (double)dv * (double)qv;
-    sq += (double)qv;
-    sd += (double)dv;
-  });
+  const T cc = T(c);
+#pragma unroll
+  for (int u = 0; u < O::PER_Z; ++u) {
+    int j, k0;
+    if (O::z(u, j, k0)) {
+      V16<T> v[2];
+      O::z_values(lds, tb, j, k0, v[0], v[1]);
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) {
+          const T dvv = dd[2 * u + h].a[e];
+          const T qn = qo[2 * u + h].a[e] + v[h].a[e] + cc * dvv;
+          v[h].a[e] = qn;
+          sdq += (double)dvv * (double)qn;
+          sq += (double)qn;
+          sd += (double)dvv;
+        }
+        qv[(2 * j + h) * RV + k0 / VEC] = v[h];
+      }
+    }
+  }
   double t0 = block_sum(sdq, red);
   double t1 = block_sum(sq, red);
   double t2 = block_sum(sd, red);

@@ -306,49 +306,100 @@ __device__ __forceinline__ T post_value(const T* lds, const Tab<T>& tb, int p, i
   }
 }
 
-// Transform from the source and hand every output value to store(p, k, value) without
-// staging, in the coalescing order of the given axis (the store must not write LDS).
-template <typename T, int N, int KIND, class Src, class Store>
-__device__ __forceinline__ void transform_store(T* lds, const Src& src, const Tab<T>& tb, int axis, Store&& store) {
-  using S = TileCfg<T, N, KIND>;
-  constexpr int W = S::W, NT = S::NT;
-  fft_tile<T, N, KIND>(lds, src, tb);
-  for (int e = threadIdx.x; e < W * N; e += NT) {
-    int p, k;
-    if (axis == 2) {
-      p = e / N;
-      k = e - p * N;
-    } else {
-      k = e / W;
-      p = e - k * W;
-    }
-    store(p, k, post_value<T, N, KIND>(lds, tb, p, k));
-  }
-}
-
-// Transform the W real pencils of the LDS tile in place (tile row p at lds[p * (N + 1)]).
+// Both outputs of index k of job j (pencils 2j and 2j+1) from one read of the spectra.
 template <typename T, int N, int KIND>
-__device__ void transform_tile(T* lds, const Tab<T>& tb) {
-  using S = TileCfg<T, N, KIND>;
-  constexpr int W = S::W, RS = S::RS, NT = S::NT;
-  fft_tile<T, N, KIND>(lds, LdsSrc<T, N>{lds}, tb);
-  constexpr int CNT = W * N;
-  constexpr int PER = (CNT + NT - 1) / NT;
-  T o[PER];
-#pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int e = threadIdx.x + u * NT;
-    if (CNT % NT == 0 || e < CNT) o[u] = post_value<T, N, KIND>(lds, tb, e / N, e % N);
+__device__ __forceinline__ void post_pair(const T* lds, const Tab<T>& tb, int j, int k, T& v0, T& v1) {
+  constexpr int ZS = TileCfg<T, N, KIND>::ZS;
+  const C2<T>* Z = reinterpret_cast<const C2<T>*>(lds) + j * ZS;
+  if constexpr (KIND == DCT2 || KIND == DST2) {
+    const int kk = (KIND == DST2) ? N - 1 - k : k;
+    const C2<T> a = Z[kk], b = Z[(N - kk) & (N - 1)];
+    const C2<T> m = tb.mk[kk];
+    const T f = tb.sc[kk] * T(0.5);
+    // V_a = (a + conj b)/2, V_b = (a - conj b)/(2i); output = sc Re(m V)
+    v0 = f * (m.x * (a.x + b.x) - m.y * (a.y - b.y));
+    v1 = f * (m.x * (a.y + b.y) - m.y * (b.x - a.x));
+  } else if constexpr (KIND == DCT3 || KIND == DST3) {
+    const C2<T> z = Z[perm_dst(k, N)];
+    const T f = (KIND == DST3 && (k & 1)) ? -(T(1) / T(N)) : (T(1) / T(N));
+    v0 = z.x * f;
+    v1 = z.y * f;
+  } else {
+    const C2<T> z = Z[k];
+    const T f = (k == 0) ? T(0) : tb.sc[1] * T(0.5);  // sqrt(2/N) / 2
+    v0 = -z.y * f;
+    v1 = z.x * f;
   }
-  __syncthreads();
-#pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int e = threadIdx.x + u * NT;
-    if (CNT % NT == 0 || e < CNT) lds[(e / N) * RS + (e % N)] = o[u];
-  }
-  __syncthreads();
 }
 
+// 16-byte vector of T (global loads and stores of whole vectors)
+template <typename T>
+struct alignas(16) V16 {
+  static constexpr int n = 16 / (int)sizeof(T);
+  T a[16 / sizeof(T)];
+};
+
+// Output items of a tile after fft_tile.  Axis 2 (pencils contiguous, N apart): item (j, kv)
+// covers outputs k = kv*VEC .. kv*VEC+VEC-1 of pencils 2j and 2j+1 (two 16-byte stores, a
+// wavefront writes whole pencils).  Axes 0, 1 (pencils adjacent in memory): item (j, k) covers
+// output k of pencils 2j and 2j+1 (one 2-element store, a wavefront writes whole 128-byte rows
+// of the tile).  Thread t handles items t + u*NT, u < PER.
+template <typename T, int N, int KIND>
+struct OutItems {
+  using S = TileCfg<T, N, KIND>;
+  static constexpr int NT = S::NT, NJ = S::NJ, VEC = V16<T>::n;
+  static constexpr int NKV = N / VEC;
+  static constexpr int COUNT_Z = NJ * NKV, PER_Z = (COUNT_Z + NT - 1) / NT;
+  static constexpr int COUNT_XY = NJ * N, PER_XY = (COUNT_XY + NT - 1) / NT;
+  __device__ static bool z(int u, int& j, int& k0) {
+    const int e = threadIdx.x + u * NT;
+    j = e / NKV;
+    k0 = (e - j * NKV) * VEC;
+    return COUNT_Z % NT == 0 || e < COUNT_Z;
+  }
+  __device__ static bool xy(int u, int& j, int& k) {
+    const int e = threadIdx.x + u * NT;
+    k = e / NJ;
+    j = e - k * NJ;
+    return COUNT_XY % NT == 0 || e < COUNT_XY;
+  }
+  __device__ static void z_values(const T* lds, const Tab<T>& tb, int j, int k0, V16<T>& a, V16<T>& b) {
+#pragma unroll
+    for (int q = 0; q < VEC; ++q) post_pair<T, N, KIND>(lds, tb, j, k0 + q, a.a[q], b.a[q]);
+  }
+};
+
+// Transform from the source and hand the outputs to the stores in the coalescing order of
+// the axis: axis 2: store_z(p, k0, V16 values of k0..k0+VEC-1) for rows p = 2j, 2j+1;
+// axes 0, 1: store_xy(j, k, v0, v1) for pencils 2j, 2j+1 (the stores must not write LDS).
+template <typename T, int N, int KIND, class Src, class StoreZ, class StoreXY>
+__device__ __forceinline__ void transform_store(T* lds, const Src& src, const Tab<T>& tb, int axis, StoreZ&& store_z,
+                                                StoreXY&& store_xy) {
+  using O = OutItems<T, N, KIND>;
+  fft_tile<T, N, KIND>(lds, src, tb);
+  if (axis == 2) {
+#pragma unroll
+    for (int u = 0; u < O::PER_Z; ++u) {
+      int j, k0;
+      if (O::z(u, j, k0)) {
+        V16<T> a, b;
+        O::z_values(lds, tb, j, k0, a, b);
+        store_z(2 * j, k0, a);
+        store_z(2 * j + 1, k0, b);
+      }
+    }
+  } else {
+#pragma unroll 4
+    for (int u = 0; u < O::PER_XY; ++u) {
+      int j, k;
+      if (O::xy(u, j, k)) {
+        T v0, v1;
+        post_pair<T, N, KIND>(lds, tb, j, k, v0, v1);
+        store_xy(j, k, v0, v1);
+      }
+    }
+  }
+}
 
 // Tile addressing.  Field layout [x][y][z], z contiguous, N^3 elements.
 //  axis 2: tile = W consecutive z-pencils (pencil q = blk*W + p, (x, y) = (q / N, q % N))
