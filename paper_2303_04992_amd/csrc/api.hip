@@ -190,17 +190,13 @@ struct MacSolver {
   // C_0 = DCT_x DST_y DST_z, C_1 = DST_x DCT_y DST_z, C_2 = DST_x DST_y DCT_z (orthonormal);
   // order z, y, [x fused with the weights], y, z
   void cg_iteration() {
-    HIPCHK(launch_zfwd_cg<T>(N, r, d, A, scal, tb, s));  // d = r + beta d; A = DST_z d
-    pass(DCT2, 2, d, B);                                  // B = DCT_z d
-    pass(DST2, 1, A, A1);                                 // component 0
-    pass(DCT2, 1, A, B2);                                 // component 1
-    pass(DST2, 1, B, B3);                                 // component 2
+    HIPCHK(launch_zfwd_cg<T>(N, r, d, A, B, scal, tb, s));     // d = r + beta d; A = DST_z d; B = DCT_z d
+    HIPCHK(launch_ypair<T>(N, false, A, A, A1, B2, tb, s));    // components 0, 1: DST_y A, DCT_y A
+    pass(DST2, 1, B, B3);                                      // component 2
     HIPCHK(launch_xmid<T>(N, A1, B2, B3, mu, tb, s));
-    pass(DST3, 1, A1, A);                                 // components 0 and 1 share DST_z
-    pass(DCT3, 1, B2, A, true);
+    HIPCHK(launch_ypair<T>(N, true, A1, B2, A, A, tb, s));     // components 0 and 1 share DST_z
     pass(DST3, 1, B3, B);
-    pass(DST3, 2, A, q);
-    HIPCHK(launch_zinv_cg<T>(N, B, q, d, c, partials, tb, s));
+    HIPCHK(launch_zinv_cg<T>(N, A, B, q, d, c, partials, tb, s));
     HIPCHK(launch_reduce(partials, nparts_x, 3, scal, R_ALPHA, pde == KFBI_STOKES, M, s));
     HIPCHK(launch_cg_update<T>(M, x, r, d, q, scal, partials, nparts_u, s));
     HIPCHK(launch_reduce(partials, nparts_u, 1, scal, R_BETA, 0, M, s));
@@ -550,7 +546,7 @@ int mac_solve(kfbi_ctx* C, const double* F, double* u, double* p, kfbi_info* inf
     HIPCHK(hipStreamSynchronize(s));
     return std::sqrt(std::max(h2, 0.0));
   };
-  HIPCHK(launch_refine_prep(M, F, C->rpart, NP, s));
+  HIPCHK(launch_refine_prep(M, F, C->r32, C->rpart, NP, s));
   const double f0 = norm(R_RESNORM0);
   const double* shift = stokes ? C->rscal + 6 : nullptr;  // mean of F_p (Stokes)
   if (!(f0 > 0)) {
@@ -563,7 +559,6 @@ int mac_solve(kfbi_ctx* C, const double* F, double* u, double* p, kfbi_info* inf
   // the old iterate are read while the new one is written)
   double* cu = u;
   double* cp = p;
-  HIPCHK(launch_refine_convert(M, F, shift, C->r32, s));
   int total = 0, rounds = 0;
   double rn = f0;
   while (rn > C->cfg.cg_rtol * f0) {

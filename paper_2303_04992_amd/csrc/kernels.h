@@ -37,14 +37,19 @@ hipError_t launch_zscale_inv(int N, int m, int wkind, const T* in, T* out, doubl
 // fused x-pass of the Schur operator for the three components (fwd x, weight, inverse x)
 template <typename T>
 hipError_t launch_xmid(int N, T* A0, T* A1, T* A2, double mu, const DevTables<T>& tb, hipStream_t s);
-// d = r + beta d_old (beta from scal[2]) and T1 = DST-II_z(d)
+// d = r + beta d_old (beta from scal[2]), A = DST-II_z(d), B = DCT-II_z(d)
 template <typename T>
-hipError_t launch_zfwd_cg(int N, const T* r, T* d, T* T1, const double* scal, const DevTables<T>& tb,
+hipError_t launch_zfwd_cg(int N, const T* r, T* d, T* A, T* B, const double* scal, const DevTables<T>& tb,
                           hipStream_t s);
-// q += DCT-III_z(B) + c d; per-block partial sums of d.q, q, d
+// q = DST-III_z(A) + DCT-III_z(B) + c d; per-block partial sums of d.q, q, d
 template <typename T>
-hipError_t launch_zinv_cg(int N, const T* B, T* q, const T* d, double c, double* partials, const DevTables<T>& tb,
-                          hipStream_t s);
+hipError_t launch_zinv_cg(int N, const T* A, const T* B, T* q, const T* d, double c, double* partials,
+                          const DevTables<T>& tb, hipStream_t s);
+// y passes with two transforms per block: forward (out0 = DST-II_y(in0), out1 = DCT-II_y(in0)),
+// inverse (out0 = DST-III_y(in0) + DCT-III_y(in1))
+template <typename T>
+hipError_t launch_ypair(int N, bool inverse, const T* in0, const T* in1, T* out0, T* out1, const DevTables<T>& tb,
+                        hipStream_t s);
 int zinv_blocks(int N, int elem_size);
 // x += alpha d; r -= alpha (q - mq); partial sums of r.r
 template <typename T>
@@ -82,10 +87,8 @@ hipError_t launch_rhs_minus_t(int64_t M, T* b, const T* Fp, hipStream_t s);
 
 // ---- full-system residual of the MAC scheme (float64)
 // r_u = F_u - (-mu lap u + G p), r_p = F_p - (D u + c p), internal layout
-// mixed refinement: partial sums of F (3 per block, nparts blocks)
-hipError_t launch_refine_prep(int64_t M, const double* F, double* partials, int nparts, hipStream_t s);
-// r32 = (float) F, pressure part minus *shift (shift may be null)
-hipError_t launch_refine_convert(int64_t M, const double* F, const double* shift, float* r32, hipStream_t s);
+// mixed refinement: r32 = (float) F and partial sums of F (3 per block, nparts blocks)
+hipError_t launch_refine_prep(int64_t M, const double* F, float* r32, double* partials, int nparts, hipStream_t s);
 // un, pn = u, p (+ 0 if first) + x32; r32 = float32 of the float64 residual F - A(un, pn) (pressure
 // part minus *shift); partial sums
 hipError_t launch_refine_residual(bool first, int N, double h, double mu, double c, const double* u, const double* p,

@@ -184,8 +184,15 @@ __device__ void xmid_body(T* lds, T* field, int mc, double mu, const double* sig
   fft_tile<T, N, KF>(lds, GlobSrc<T>{field, a.base, a.nstride}, tb);
   C2<T>* cb = reinterpret_cast<C2<T>*>(lds);
   constexpr int PAIRS = N / 2 + 1;
+  static_assert(NT % NJ == 0, "the job of a thread is fixed across the loop");
+  // y and z eigenvalues of the thread's two pencils (its job j = threadIdx.x % NJ is fixed)
+  const int jt = threadIdx.x % NJ;
+  const T ly = (mc == 1) ? tb.sg2[yi] : tb.sg2s[yi];
+  T lz[2];
+#pragma unroll
+  for (int w = 0; w < 2; ++w) lz[w] = (mc == 2) ? tb.sg2[z0 + 2 * jt + w] : tb.sg2s[z0 + 2 * jt + w];
   for (int t = threadIdx.x; t < NJ * PAIRS; t += NT) {
-    const int j = t % NJ, k = t / NJ;
+    const int j = jt, k = t / NJ;
     const int kr = (N - k) & (N - 1);
     const C2<T> Zk = cb[j * ZS + k], Zr = cb[j * ZS + kr];
     // weights sigma_mc^2 / Lambda_mc of the two pencils at DCT-domain indices k and kr;
@@ -198,11 +205,12 @@ __device__ void xmid_body(T* lds, T* field, int mc, double mu, const double* sig
       const T lx = (mc == 0) ? tb.sg2[mode] : tb.sg2s[mode];
 #pragma unroll
       for (int w = 0; w < 2; ++w) {
-        const int zi = z0 + 2 * j + w;
-        const T ly = (mc == 1) ? tb.sg2[yi] : tb.sg2s[yi];
-        const T lz = (mc == 2) ? tb.sg2[zi] : tb.sg2s[zi];
-        const T num = (mc == 0) ? lx : (mc == 1) ? ly : lz;
-        om[w][h] = num / (T(mu) * (lx + ly + lz));
+        const T num = (mc == 0) ? lx : (mc == 1) ? ly : lz[w];
+        const T den = T(mu) * (lx + ly + lz[w]);
+        if constexpr (sizeof(T) == 4)
+          om[w][h] = num * __builtin_amdgcn_rcpf(den);  // 1 ulp: the float32 inner solve
+        else
+          om[w][h] = num / den;
       }
     }
     const C2<T> mkk = tb.mk[k], mkr = tb.mk[kr];
@@ -291,14 +299,31 @@ __global__ __launch_bounds__(256) void k_zscale_inv(const T* __restrict__ in, T*
 // ---------------------------------------------------------------------------------------
 // CG z-passes with fused vector updates
 // ---------------------------------------------------------------------------------------
-// d = r + beta d_old (written back) and T1 = DST-II_z(d)
+// d = r + beta d_old (written back), A = DST-II_z(d), B = DCT-II_z(d): one read of r and d
+// for both transforms (the tile is restaged in LDS from registers for the second)
+template <typename T, int N, int KIND>
+__device__ __forceinline__ void store_z_outputs(const T* lds, const Tab<T>& tb, T* out) {
+  using O = OutItems<T, N, KIND>;
+  V16<T>* o = reinterpret_cast<V16<T>*>(out);
+  constexpr int RV = N / O::VEC;
+#pragma unroll
+  for (int u = 0; u < O::PER_Z; ++u) {
+    int j, k0;
+    if (O::z(u, j, k0)) {
+      V16<T> v0, v1;
+      O::z_values(lds, tb, j, k0, v0, v1);
+      o[(2 * j) * RV + k0 / O::VEC] = v0;
+      o[(2 * j + 1) * RV + k0 / O::VEC] = v1;
+    }
+  }
+}
+
 template <typename T, int N>
-__global__ __launch_bounds__(256) void k_zfwd_cg(const T* __restrict__ r, T* __restrict__ d, T* __restrict__ T1,
-                                                const double* __restrict__ scal, Tab<T> tb) {
+__global__ __launch_bounds__(256) void k_zfwd_cg(const T* __restrict__ r, T* __restrict__ d, T* __restrict__ A,
+                                                T* __restrict__ B, const double* __restrict__ scal, Tab<T> tb) {
   extern __shared__ __align__(16) unsigned char smem[];
   T* lds = reinterpret_cast<T*>(smem);
   using S = TileCfg<T, N, DST2>;
-  using O = OutItems<T, N, DST2>;
   constexpr int W = S::W, RS = N + 1, NT = S::NT, VEC = V16<T>::n;
   constexpr int NV = W * N / VEC, PER = (NV + NT - 1) / NT;
   const T beta = T(scal[2]);
@@ -314,6 +339,18 @@ __global__ __launch_bounds__(256) void k_zfwd_cg(const T* __restrict__ r, T* __r
       y[u] = dv[e];
     }
   }
+  auto stage = [&]() {
+#pragma unroll
+    for (int u = 0; u < PER; ++u) {
+      const int e = threadIdx.x + u * NT;
+      if (NV % NT == 0 || e < NV) {
+        const int p = (e * VEC) / N, n = (e * VEC) - p * N;
+#pragma unroll
+        for (int q = 0; q < VEC; ++q) lds[p * RS + n + q] = x[u].a[q];
+      }
+    }
+    __syncthreads();
+  };
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
     const int e = threadIdx.x + u * NT;
@@ -321,31 +358,22 @@ __global__ __launch_bounds__(256) void k_zfwd_cg(const T* __restrict__ r, T* __r
 #pragma unroll
       for (int q = 0; q < VEC; ++q) x[u].a[q] += beta * y[u].a[q];
       dv[e] = x[u];
-      const int p = (e * VEC) / N, n = (e * VEC) - p * N;
-#pragma unroll
-      for (int q = 0; q < VEC; ++q) lds[p * RS + n + q] = x[u].a[q];
     }
   }
-  __syncthreads();
+  stage();
   fft_tile<T, N, DST2>(lds, LdsSrc<T, N>{lds}, tb);
-  V16<T>* o = reinterpret_cast<V16<T>*>(T1 + a.base);
-  constexpr int RV = N / VEC;
-#pragma unroll
-  for (int u = 0; u < O::PER_Z; ++u) {
-    int j, k0;
-    if (O::z(u, j, k0)) {
-      V16<T> v0, v1;
-      O::z_values(lds, tb, j, k0, v0, v1);
-      o[(2 * j) * RV + k0 / VEC] = v0;
-      o[(2 * j + 1) * RV + k0 / VEC] = v1;
-    }
-  }
+  store_z_outputs<T, N, DST2>(lds, tb, A + a.base);
+  __syncthreads();
+  stage();
+  fft_tile<T, N, DCT2>(lds, LdsSrc<T, N>{lds}, tb);
+  store_z_outputs<T, N, DCT2>(lds, tb, B + a.base);
 }
 
-// q += DCT-III_z(B) + c d; per-block partial sums of d.q, q, d
+// q = DST-III_z(A) + DCT-III_z(B) + c d; per-block partial sums of d.q, q, d
 template <typename T, int N>
-__global__ __launch_bounds__(256) void k_zinv_cg(const T* __restrict__ B, T* __restrict__ q, const T* __restrict__ d,
-                                                double c, double* __restrict__ partials, Tab<T> tb) {
+__global__ __launch_bounds__(256) void k_zinv_cg(const T* __restrict__ A, const T* __restrict__ B,
+                                                T* __restrict__ q, const T* __restrict__ d, double c,
+                                                double* __restrict__ partials, Tab<T> tb) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red[4];
   T* lds = reinterpret_cast<T*>(smem);
@@ -353,23 +381,29 @@ __global__ __launch_bounds__(256) void k_zinv_cg(const T* __restrict__ B, T* __r
   using O = OutItems<T, N, DCT3>;
   constexpr int W = S::W, NT = S::NT, VEC = V16<T>::n, RV = N / VEC;
   const TileAddr a = tile_addr<W, N>(2, blockIdx.x);
+  load_tile_z<T, N, NT>(lds, A + a.base);
+  fft_tile<T, N, DST3>(lds, LdsSrc<T, N>{lds}, tb);
+  V16<T> acc[2 * O::PER_Z];
+#pragma unroll
+  for (int u = 0; u < O::PER_Z; ++u) {
+    int j, k0;
+    if (O::z(u, j, k0)) OutItems<T, N, DST3>::z_values(lds, tb, j, k0, acc[2 * u], acc[2 * u + 1]);
+  }
+  __syncthreads();
   load_tile_z<T, N, NT>(lds, B + a.base);
-  fft_tile<T, N, DCT3>(lds, LdsSrc<T, N>{lds}, tb);
-  V16<T>* qv = reinterpret_cast<V16<T>*>(q + a.base);
+  // the d vectors of the thread are requested before the second transform
   const V16<T>* dv = reinterpret_cast<const V16<T>*>(d + a.base);
-  // every q and d vector of the thread is requested before the first use
-  V16<T> qo[2 * O::PER_Z], dd[2 * O::PER_Z];
+  V16<T> dd[2 * O::PER_Z];
 #pragma unroll
   for (int u = 0; u < O::PER_Z; ++u) {
     int j, k0;
     if (O::z(u, j, k0)) {
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        qo[2 * u + h] = qv[(2 * j + h) * RV + k0 / VEC];
-        dd[2 * u + h] = dv[(2 * j + h) * RV + k0 / VEC];
-      }
+      dd[2 * u] = dv[(2 * j) * RV + k0 / VEC];
+      dd[2 * u + 1] = dv[(2 * j + 1) * RV + k0 / VEC];
     }
   }
+  fft_tile<T, N, DCT3>(lds, LdsSrc<T, N>{lds}, tb);
+  V16<T>* qv = reinterpret_cast<V16<T>*>(q + a.base);
   double sdq = 0, sq = 0, sd = 0;
   const T cc = T(c);
 #pragma unroll
@@ -383,7 +417,7 @@ __global__ __launch_bounds__(256) void k_zinv_cg(const T* __restrict__ B, T* __r
 #pragma unroll
         for (int e = 0; e < VEC; ++e) {
           const T dvv = dd[2 * u + h].a[e];
-          const T qn = qo[2 * u + h].a[e] + v[h].a[e] + cc * dvv;
+          const T qn = acc[2 * u + h].a[e] + v[h].a[e] + cc * dvv;
           v[h].a[e] = qn;
           sdq += (double)dvv * (double)qn;
           sq += (double)qn;
@@ -400,6 +434,69 @@ __global__ __launch_bounds__(256) void k_zinv_cg(const T* __restrict__ B, T* __r
     partials[3 * blockIdx.x + 0] = t0;
     partials[3 * blockIdx.x + 1] = t1;
     partials[3 * blockIdx.x + 2] = t2;
+  }
+}
+
+// y passes of the Schur matvec with two transforms per block.
+// forward: A1 = DST-II_y(A), B2 = DCT-II_y(A) (the tile of A is read twice, the second time
+// from L2); inverse: A = DST-III_y(A1) + DCT-III_y(B2)
+template <typename T, int N, int KIND>
+__device__ __forceinline__ void store_xy_outputs(const T* lds, const Tab<T>& tb, T* out, long nstride) {
+  using O = OutItems<T, N, KIND>;
+  C2<T>* o = reinterpret_cast<C2<T>*>(out);
+  const long ns = nstride / 2;
+#pragma unroll 4
+  for (int u = 0; u < O::PER_XY; ++u) {
+    int j, k;
+    if (O::xy(u, j, k)) {
+      C2<T> v;
+      post_pair<T, N, KIND>(lds, tb, j, k, v.x, v.y);
+      o[k * ns + j] = v;
+    }
+  }
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(256) void k_ypair_fwd(const T* __restrict__ A, T* __restrict__ A1, T* __restrict__ B2,
+                                                  Tab<T> tb) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* lds = reinterpret_cast<T*>(smem);
+  constexpr int W = TileCfg<T, N, DST2>::W;
+  const TileAddr a = tile_addr<W, N>(1, blockIdx.x);
+  fft_tile<T, N, DST2>(lds, GlobSrc<T>{A, a.base, a.nstride}, tb);
+  store_xy_outputs<T, N, DST2>(lds, tb, A1 + a.base, a.nstride);
+  fft_tile<T, N, DCT2>(lds, GlobSrc<T>{A, a.base, a.nstride}, tb);
+  store_xy_outputs<T, N, DCT2>(lds, tb, B2 + a.base, a.nstride);
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(256) void k_ypair_inv(const T* __restrict__ A1, const T* __restrict__ B2,
+                                                  T* __restrict__ A, Tab<T> tb) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* lds = reinterpret_cast<T*>(smem);
+  using O = OutItems<T, N, DST3>;
+  constexpr int W = TileCfg<T, N, DST3>::W;
+  const TileAddr a = tile_addr<W, N>(1, blockIdx.x);
+  fft_tile<T, N, DST3>(lds, GlobSrc<T>{A1, a.base, a.nstride}, tb);
+  C2<T> acc[O::PER_XY];
+#pragma unroll
+  for (int u = 0; u < O::PER_XY; ++u) {
+    int j, k;
+    if (O::xy(u, j, k)) post_pair<T, N, DST3>(lds, tb, j, k, acc[u].x, acc[u].y);
+  }
+  fft_tile<T, N, DCT3>(lds, GlobSrc<T>{B2, a.base, a.nstride}, tb);
+  C2<T>* o = reinterpret_cast<C2<T>*>(A + a.base);
+  const long ns = a.nstride / 2;
+#pragma unroll
+  for (int u = 0; u < O::PER_XY; ++u) {
+    int j, k;
+    if (O::xy(u, j, k)) {
+      C2<T> v;
+      post_pair<T, N, DCT3>(lds, tb, j, k, v.x, v.y);
+      v.x += acc[u].x;
+      v.y += acc[u].y;
+      o[k * ns + j] = v;
+    }
   }
 }
 
@@ -576,18 +673,22 @@ __global__ void k_res_p(int N, double h, double cc, const double* __restrict__ u
 // ---------------------------------------------------------------------------------------
 // mixed-precision refinement (float64 residual of the full MAC system, float32 correction)
 // ---------------------------------------------------------------------------------------
-// per-block partial sums of F_u.F_u, sum F_p, F_p.F_p (four fields F)
+// r32 = (float) F (four fields, unshifted: the first inner solve projects the mean of its
+// pressure right-hand side itself, and F_p is not small against its mean); per-block partial
+// sums of F_u.F_u, sum F_p, F_p.F_p
 __global__ __launch_bounds__(EW_NT) void k_refine_prep(int64_t M, const double* __restrict__ F,
-                                                    double* __restrict__ partials) {
+                                                    float* __restrict__ r32, double* __restrict__ partials) {
   __shared__ double red[EW_NT / 64];
   double su = 0, sp = 0, spp = 0;
   for (int64_t i = (int64_t)blockIdx.x * EW_NT + threadIdx.x; i < M; i += (int64_t)gridDim.x * EW_NT) {
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
       const double v = F[m * M + i];
+      r32[m * M + i] = (float)v;
       su += v * v;
     }
     const double v = F[3 * M + i];
+    r32[3 * M + i] = (float)v;
     sp += v;
     spp += v * v;
   }
@@ -599,22 +700,14 @@ __global__ __launch_bounds__(EW_NT) void k_refine_prep(int64_t M, const double* 
   }
 }
 
-// r32 = (float) F, the pressure part shifted by -(*shift) (Stokes: the mean of F_p, which
-// the float32 solve would otherwise have to cancel against a much smaller residual)
-__global__ void k_refine_convert(int64_t M, const double* __restrict__ F, const double* __restrict__ shift,
-                                 float* __restrict__ r32) {
-  const double sh = shift ? *shift : 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < 4 * M; i += (int64_t)gridDim.x * blockDim.x)
-    r32[i] = (float)(i >= 3 * M ? F[i] - sh : F[i]);
-}
-
 // One refinement update and the new residual, in one pass over the cells (internal layout,
 // z fastest): u' = u + x32_u, p' = p + x32_p (u = p = 0 in the first round), then
 //   r_u = F_u - (-mu lap_h u' + G p'),   r_p = F_p - (D u' + c p')
 // in float64 (face 0 and face N of each u_m are the box faces, zero; tangential ghosts by
-// reflection), written as float32 for the next inner solve (pressure part shifted by
-// -(*shift), as in k_refine_convert), with per-block partial sums of r_u.r_u and of the
-// shifted r_p and r_p.r_p.  Neighbour values of u' are formed on the fly, so u', p' go to
+// reflection), written as float32 for the next inner solve, with per-block partial sums of
+// r_u.r_u and of the shifted r_p and r_p.r_p.  The pressure part is shifted by -(*shift)
+// (Stokes: the mean of F_p, which the residual keeps; left in, the float32 inner solve would
+// have to cancel an O(|F|) constant against an O(1e-5 |F|) residual and stagnates).  Neighbour values of u' are formed on the fly, so u', p' go to
 // buffers other than u, p.
 template <bool FIRST>
 __global__ __launch_bounds__(EW_NT) void k_refine_residual(int N, double h, double mu, double cc,
@@ -625,52 +718,61 @@ __global__ __launch_bounds__(EW_NT) void k_refine_residual(int N, double h, doub
                                                         double* __restrict__ partials) {
   __shared__ double red[EW_NT / 64];
   const double sh = shift ? *shift : 0.0;
-  const int64_t M = (int64_t)N * N * N;
+  // N is a power of two and N^3 < 2^31 (N <= 512): 32-bit indices, shifts and masks
+  const int lg = __builtin_ctz(N), mask = N - 1;
+  const int M = N << (2 * lg);
   const double ih2 = 1.0 / (h * h), ih = 1.0 / h;
-  const int64_t st[3] = {(int64_t)N * N, N, 1};
-  auto U = [&](int m, int64_t j) -> double {
-    const double v = (double)x32[m * M + j];
-    return FIRST ? v : u[m * M + j] + v;
+  const int st[3] = {N * N, N, 1};
+  auto U = [&](int m, int j) -> double {
+    const double v = (double)x32[(int64_t)m * M + j];
+    return FIRST ? v : u[(int64_t)m * M + j] + v;
   };
-  auto P = [&](int64_t j) -> double {
-    const double v = (double)x32[3 * M + j];
+  auto P = [&](int j) -> double {
+    const double v = (double)x32[(int64_t)3 * M + j];
     return FIRST ? v : p[j] + v;
   };
+  // XCD-aware chunking: the hardware deals workgroups round-robin over the 8 XCDs, so block b
+  // takes logical chunk (b % 8) * (nb / 8) + b / 8 and each XCD sweeps one contiguous slab of
+  // x-planes; the x, y and z neighbours of a point are then read by blocks of the same XCD
+  // (same L2) at about the same time.  gridDim.x is a multiple of 8.
+  const int nb = gridDim.x;
+  const int L = (blockIdx.x % 8) * (nb / 8) + blockIdx.x / 8;
+  const int chunk = (M + nb - 1) / nb;
+  const int i1 = (L + 1) * chunk < M ? (L + 1) * chunk : M;
   double su = 0, sp = 0, spp = 0;
-  for (int64_t i = (int64_t)blockIdx.x * EW_NT + threadIdx.x; i < M; i += (int64_t)gridDim.x * EW_NT) {
-    const int id[3] = {(int)(i / st[0]), (int)((i / N) % N), (int)(i % N)};
+  for (int i = L * chunk + threadIdx.x; i < i1; i += EW_NT) {
+    const int id[3] = {i >> (2 * lg), (i >> lg) & mask, i & mask};
     const double pc = P(i);
     double div = 0;
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
-      const double c = (id[m] == 0) ? 0.0 : U(m, i);  // face 0 is the box face
+      // every neighbour is loaded unconditionally (clamped to the point itself) and replaced
+      // by its boundary value afterwards, so all loads of a point are in flight together
+      const double cu = U(m, i);
+      const double c = (id[m] == 0) ? 0.0 : cu;  // face 0 is the box face
       double lap = 0, hi_m = 0;
 #pragma unroll
       for (int d = 0; d < 3; ++d) {
-        double lo, hi;
-        if (d == m) {
-          lo = (id[d] > 1) ? U(m, i - st[d]) : 0.0;     // face a-1 (face 0 is zero)
-          hi = (id[d] + 1 < N) ? U(m, i + st[d]) : 0.0;  // face N is the box face
-          hi_m = hi;
-        } else {
-          lo = (id[d] > 0) ? U(m, i - st[d]) : -c;       // ghost reflection
-          hi = (id[d] + 1 < N) ? U(m, i + st[d]) : -c;
-        }
+        const bool lo_ok = (d == m) ? id[d] > 1 : id[d] > 0;
+        const bool hi_ok = id[d] + 1 < N;
+        const double vlo = U(m, lo_ok ? i - st[d] : i);
+        const double vhi = U(m, hi_ok ? i + st[d] : i);
+        // face a-1 / face N: zero (box faces); tangential ghosts: reflection -c
+        const double lo = lo_ok ? vlo : (d == m ? 0.0 : -c);
+        const double hi = hi_ok ? vhi : (d == m ? 0.0 : -c);
+        if (d == m) hi_m = hi;
         lap += (lo - 2.0 * c + hi) * ih2;
       }
       div += (hi_m - c) * ih;
-      double r = 0.0;
-      if (id[m] > 0) {
-        const double gp = (pc - P(i - st[m])) * ih;     // cells a-1, a
-        r = F[m * M + i] - (-mu * lap + gp);
-      }
-      un[m * M + i] = c;
-      r32[m * M + i] = (float)r;
+      const double gp = (pc - P(id[m] > 0 ? i - st[m] : i)) * ih;  // cells a-1, a
+      const double r = (id[m] > 0) ? F[(int64_t)m * M + i] - (-mu * lap + gp) : 0.0;
+      un[(int64_t)m * M + i] = c;
+      r32[(int64_t)m * M + i] = (float)r;
       su += r * r;
     }
-    const double rp = F[3 * M + i] - (div + cc * pc) - sh;
+    const double rp = F[(int64_t)3 * M + i] - (div + cc * pc) - sh;
     pn[i] = pc;
-    r32[3 * M + i] = (float)rp;
+    r32[(int64_t)3 * M + i] = (float)rp;
     sp += rp;
     spp += rp * rp;
   }
@@ -999,15 +1101,16 @@ hipError_t launch_xmid(int N, T* A0, T* A1, T* A2, double mu, const DevTables<T>
 }
 
 template <typename T>
-hipError_t launch_zfwd_cg(int N, const T* r, T* d, T* T1, const double* scal, const DevTables<T>& tb, hipStream_t s) {
+hipError_t launch_zfwd_cg(int N, const T* r, T* d, T* A, T* B, const double* scal, const DevTables<T>& tb,
+                          hipStream_t s) {
   const Tab<T> t = tab_of(tb);
-#define KFBI_M(NN)                                                                                  \
-  {                                                                                                 \
-    using S = TileCfg<T, NN, DST2>;                                                                 \
-    const int blocks = NN * NN / S::W;                                                              \
-    const size_t lds = S::BYTES;                                                                    \
-    ensure_lds(k_zfwd_cg<T, NN>, lds);                                                              \
-    hipLaunchKernelGGL((k_zfwd_cg<T, NN>), dim3(blocks), dim3(S::NT), lds, s, r, d, T1, scal, t);   \
+#define KFBI_M(NN)                                                                                   \
+  {                                                                                                  \
+    using S = TileCfg<T, NN, DST2>;                                                                  \
+    const int blocks = NN * NN / S::W;                                                               \
+    const size_t lds = S::BYTES;                                                                     \
+    ensure_lds(k_zfwd_cg<T, NN>, lds);                                                               \
+    hipLaunchKernelGGL((k_zfwd_cg<T, NN>), dim3(blocks), dim3(S::NT), lds, s, r, d, A, B, scal, t);  \
   }
   KFBI_DISPATCH_N(N, KFBI_M)
 #undef KFBI_M
@@ -1017,16 +1120,38 @@ hipError_t launch_zfwd_cg(int N, const T* r, T* d, T* T1, const double* scal, co
 int zinv_blocks(int N, int elem_size) { return N * N / std::min(128 / elem_size, N); }
 
 template <typename T>
-hipError_t launch_zinv_cg(int N, const T* B, T* q, const T* d, double c, double* partials, const DevTables<T>& tb,
-                          hipStream_t s) {
+hipError_t launch_zinv_cg(int N, const T* A, const T* B, T* q, const T* d, double c, double* partials,
+                          const DevTables<T>& tb, hipStream_t s) {
   const Tab<T> t = tab_of(tb);
-#define KFBI_M(NN)                                                                                   \
-  {                                                                                                  \
-    using S = TileCfg<T, NN, DCT3>;                                                                  \
-    const int blocks = NN * NN / S::W;                                                               \
-    const size_t lds = S::BYTES;                                                                     \
-    ensure_lds(k_zinv_cg<T, NN>, lds);                                                               \
-    hipLaunchKernelGGL((k_zinv_cg<T, NN>), dim3(blocks), dim3(S::NT), lds, s, B, q, d, c, partials, t); \
+#define KFBI_M(NN)                                                                                         \
+  {                                                                                                        \
+    using S = TileCfg<T, NN, DCT3>;                                                                        \
+    const int blocks = NN * NN / S::W;                                                                     \
+    const size_t lds = S::BYTES;                                                                           \
+    ensure_lds(k_zinv_cg<T, NN>, lds);                                                                     \
+    hipLaunchKernelGGL((k_zinv_cg<T, NN>), dim3(blocks), dim3(S::NT), lds, s, A, B, q, d, c, partials, t); \
+  }
+  KFBI_DISPATCH_N(N, KFBI_M)
+#undef KFBI_M
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_ypair(int N, bool inverse, const T* in0, const T* in1, T* out0, T* out1, const DevTables<T>& tb,
+                        hipStream_t s) {
+  const Tab<T> t = tab_of(tb);
+#define KFBI_M(NN)                                                                                        \
+  {                                                                                                       \
+    using S = TileCfg<T, NN, DCT2>;                                                                       \
+    const int blocks = NN * NN / S::W;                                                                    \
+    const size_t lds = S::BYTES;                                                                          \
+    if (inverse) {                                                                                        \
+      ensure_lds(k_ypair_inv<T, NN>, lds);                                                                \
+      hipLaunchKernelGGL((k_ypair_inv<T, NN>), dim3(blocks), dim3(S::NT), lds, s, in0, in1, out0, t);     \
+    } else {                                                                                              \
+      ensure_lds(k_ypair_fwd<T, NN>, lds);                                                                \
+      hipLaunchKernelGGL((k_ypair_fwd<T, NN>), dim3(blocks), dim3(S::NT), lds, s, in0, out0, out1, t);    \
+    }                                                                                                     \
   }
   KFBI_DISPATCH_N(N, KFBI_M)
 #undef KFBI_M
@@ -1112,17 +1237,14 @@ hipError_t launch_mac_residual(int N, double h, double mu, double c, const doubl
   return hipGetLastError();
 }
 
-hipError_t launch_refine_prep(int64_t M, const double* F, double* partials, int nparts, hipStream_t s) {
-  hipLaunchKernelGGL(k_refine_prep, dim3(nparts), dim3(EW_NT), 0, s, M, F, partials);
-  return hipGetLastError();
-}
-hipError_t launch_refine_convert(int64_t M, const double* F, const double* shift, float* r32, hipStream_t s) {
-  hipLaunchKernelGGL(k_refine_convert, dim3(ew_blocks(4 * M)), dim3(256), 0, s, M, F, shift, r32);
+hipError_t launch_refine_prep(int64_t M, const double* F, float* r32, double* partials, int nparts, hipStream_t s) {
+  hipLaunchKernelGGL(k_refine_prep, dim3(nparts), dim3(EW_NT), 0, s, M, F, r32, partials);
   return hipGetLastError();
 }
 hipError_t launch_refine_residual(bool first, int N, double h, double mu, double c, const double* u, const double* p,
                                   const float* x32, const double* F, const double* shift, double* un, double* pn,
                                   float* r32, double* partials, int nparts, hipStream_t s) {
+  if (nparts % 8) return hipErrorInvalidValue;  // XCD-aware chunking needs a multiple of 8 blocks
   if (first)
     hipLaunchKernelGGL(k_refine_residual<true>, dim3(nparts), dim3(EW_NT), 0, s, N, h, mu, c, u, p, x32, F, shift, un,
                        pn, r32, partials);
@@ -1213,8 +1335,9 @@ hipError_t launch_check_finite(int64_t n, const double* a, int* flag, hipStream_
   template hipError_t launch_pass<T>(int, int, int, const T*, T*, bool, const DevTables<T>&, hipStream_t);           \
   template hipError_t launch_zscale_inv<T>(int, int, int, const T*, T*, double, const DevTables<T>&, hipStream_t);   \
   template hipError_t launch_xmid<T>(int, T*, T*, T*, double, const DevTables<T>&, hipStream_t);                     \
-  template hipError_t launch_zfwd_cg<T>(int, const T*, T*, T*, const double*, const DevTables<T>&, hipStream_t);     \
-  template hipError_t launch_zinv_cg<T>(int, const T*, T*, const T*, double, double*, const DevTables<T>&,           \
+  template hipError_t launch_zfwd_cg<T>(int, const T*, T*, T*, T*, const double*, const DevTables<T>&, hipStream_t); \
+  template hipError_t launch_ypair<T>(int, bool, const T*, const T*, T*, T*, const DevTables<T>&, hipStream_t);      \
+  template hipError_t launch_zinv_cg<T>(int, const T*, const T*, T*, const T*, double, double*, const DevTables<T>&, \
                                         hipStream_t);                                                                \
   template hipError_t launch_cg_update<T>(int64_t, T*, T*, const T*, const T*, const double*, double*, int,          \
                                           hipStream_t);                                                              \
