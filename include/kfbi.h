@@ -162,17 +162,28 @@ kfbi_status kfbi_probe_adjoint(kfbi_ctx* ctx, const double* vals_bar_dev, double
  * gradients with respect to the Dirichlet data. */
 kfbi_status kfbi_solve_adjoint(kfbi_ctx* ctx, const double* rhs_dev, double* y_dev, kfbi_info* info);
 
-/* Measurement helper: launches the sine/cosine transform pass kernel of the context's MAC
- * solver (kind 0 DCT-II, 1 DST-II, 2 DCT-III, 3 DST-III, 4 DST-I; axis 0..2; precision of
- * the context's inner solver) reps times back to back on the context stream between two HIP
- * events, on the solver's own work fields (contents are overwritten).  Returns the mean
- * duration of one launch and the algorithmic HBM bytes of one launch (one read and one write
- * of an N^3 field). */
+/* Kernels of the MAC solver that the measurement helpers can time: the single transform
+ * pass (kind 0 DCT-II, 1 DST-II, 2 DCT-III, 3 DST-III, 4 DST-I, along one axis) and the
+ * fused kernels of one Schur-complement CG iteration. */
+enum {
+  KFBI_K_XMID = 5, /* x: forward transform, spectral weight, inverse, three components */
+  KFBI_K_ZFWD = 6, /* d = r + beta d, DST-II_z d and DCT-II_z d */
+  KFBI_K_ZINV = 7, /* q = DST-III_z A + DCT-III_z B + c d, partial dot products */
+  KFBI_K_YFWD = 8, /* DST-II_y A and DCT-II_y A */
+  KFBI_K_YINV = 9  /* DST-III_y A1 + DCT-III_y B2 */
+};
+
+/* Measurement helper: launches one kernel of the context's MAC solver (kind: a transform
+ * kind 0..4 along axis 0..2, or a KFBI_K_* fused kernel; precision of the context's inner
+ * solver) reps times back to back on the context stream between two HIP events, on the
+ * solver's own work fields (contents are overwritten).  Returns the mean duration of one
+ * launch and the algorithmic HBM bytes of one launch (one read or write per N^3 field
+ * touched: 2 fields for a transform pass, 6 XMID, 5 ZFWD, 4 ZINV, 3 YFWD, 3 YINV). */
 kfbi_status kfbi_time_pass(kfbi_ctx* ctx, int32_t kind, int32_t axis, int32_t reps, double* avg_ms,
                            double* bytes_per_launch);
 
-/* Measurement helper: live timing of one transform-pass kernel (kind as above, axis 0..2 or
- * -1 for every axis) inside the evaluations.  Calling it returns the launches and summed duration recorded since the
+/* Measurement helper: live timing of one kernel (kind as above; for transform passes axis
+ * 0..2 or -1 for every axis) inside the evaluations.  Calling it returns the launches and summed duration recorded since the
  * previous call (HIP events around every matching launch on the context stream) and the
  * algorithmic bytes of one launch, then resets the counters and enables (enable != 0) or
  * disables the timing. */

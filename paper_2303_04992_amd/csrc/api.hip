@@ -155,9 +155,10 @@ struct MacSolver {
     ev[0] = ev[1] = nullptr;
   }
 
-  void pass(int kind, int axis, const T* in, T* out, bool acc = false) {
-    const bool timed = (kind == prof_kind && (prof_axis < 0 || axis == prof_axis) && !acc);
-    if (timed) {
+  // launch under HIP events when kernel id (and axis, for the single passes) is being timed
+  template <class F>
+  void timed(bool on, F&& launch) {
+    if (on) {
       if (prof_used == prof_ev.size()) {
         hipEvent_t a, b;
         HIPCHK(hipEventCreate(&a));
@@ -166,8 +167,24 @@ struct MacSolver {
       }
       HIPCHK(hipEventRecord(prof_ev[prof_used].first, s));
     }
-    HIPCHK(launch_pass<T>(N, kind, axis, in, out, acc, tb, s));
-    if (timed) HIPCHK(hipEventRecord(prof_ev[prof_used++].second, s));
+    HIPCHK(launch());
+    if (on) HIPCHK(hipEventRecord(prof_ev[prof_used++].second, s));
+  }
+  void pass(int kind, int axis, const T* in, T* out, bool acc = false) {
+    timed(kind == prof_kind && (prof_axis < 0 || axis == prof_axis) && !acc,
+          [&] { return launch_pass<T>(N, kind, axis, in, out, acc, tb, s); });
+  }
+  // algorithmic HBM bytes of one launch of kernel id (one read and one write per field touched)
+  double kernel_bytes(int id) const {
+    const double f = (double)M * sizeof(T);
+    switch (id) {
+      case KFBI_K_XMID: return 6 * f;  // three fields read and written
+      case KFBI_K_ZFWD: return 5 * f;  // r, d read; d, A, B written
+      case KFBI_K_ZINV: return 4 * f;  // A, B, d read; q written
+      case KFBI_K_YFWD: return 3 * f;  // A read; A1, B2 written
+      case KFBI_K_YINV: return 3 * f;  // A1, B2 read; A written
+      default: return 2 * f;           // single transform pass
+    }
   }
   // accumulate the recorded launch durations (call after the stream has drained)
   void prof_collect() {
@@ -189,14 +206,21 @@ struct MacSolver {
   // S p for the CG direction d (q = S d); d = r + beta d_old is formed in the first pass
   // C_0 = DCT_x DST_y DST_z, C_1 = DST_x DCT_y DST_z, C_2 = DST_x DST_y DCT_z (orthonormal);
   // order z, y, [x fused with the weights], y, z
+  void zfwd() { timed(prof_kind == KFBI_K_ZFWD, [&] { return launch_zfwd_cg<T>(N, r, d, A, B, scal, tb, s); }); }
+  void yfwd() { timed(prof_kind == KFBI_K_YFWD, [&] { return launch_ypair<T>(N, false, A, A, A1, B2, tb, s); }); }
+  void xmid() { timed(prof_kind == KFBI_K_XMID, [&] { return launch_xmid<T>(N, A1, B2, B3, mu, tb, s); }); }
+  void yinv() { timed(prof_kind == KFBI_K_YINV, [&] { return launch_ypair<T>(N, true, A1, B2, A, A, tb, s); }); }
+  void zinv() {
+    timed(prof_kind == KFBI_K_ZINV, [&] { return launch_zinv_cg<T>(N, A, B, q, d, c, partials, tb, s); });
+  }
   void cg_iteration() {
-    HIPCHK(launch_zfwd_cg<T>(N, r, d, A, B, scal, tb, s));     // d = r + beta d; A = DST_z d; B = DCT_z d
-    HIPCHK(launch_ypair<T>(N, false, A, A, A1, B2, tb, s));    // components 0, 1: DST_y A, DCT_y A
-    pass(DST2, 1, B, B3);                                      // component 2
-    HIPCHK(launch_xmid<T>(N, A1, B2, B3, mu, tb, s));
-    HIPCHK(launch_ypair<T>(N, true, A1, B2, A, A, tb, s));     // components 0 and 1 share DST_z
+    zfwd();                // d = r + beta d; A = DST_z d; B = DCT_z d
+    yfwd();                // components 0, 1: A1 = DST_y A, B2 = DCT_y A
+    pass(DST2, 1, B, B3);  // component 2
+    xmid();                // x: forward, weight sigma^2 / Lambda, inverse (all components)
+    yinv();                // A = DST_y^T A1 + DCT_y^T B2 (components 0 and 1 share DST_z)
     pass(DST3, 1, B3, B);
-    HIPCHK(launch_zinv_cg<T>(N, A, B, q, d, c, partials, tb, s));
+    zinv();                // q = DST_z^T A + DCT_z^T B + c d, partial dots
     HIPCHK(launch_reduce(partials, nparts_x, 3, scal, R_ALPHA, pde == KFBI_STOKES, M, s));
     HIPCHK(launch_cg_update<T>(M, x, r, d, q, scal, partials, nparts_u, s));
     HIPCHK(launch_reduce(partials, nparts_u, 1, scal, R_BETA, 0, M, s));
@@ -895,13 +919,12 @@ kfbi_status kfbi_interface_solve(kfbi_ctx* C, const double* phi, int32_t use_for
 
 kfbi_status kfbi_profile_pass(kfbi_ctx* C, int32_t kind, int32_t axis, int32_t enable, int64_t* launches,
                               double* total_ms, double* bytes_per_launch) {
-  if (!C || kind < 0 || kind > 4 || axis < -1 || axis > 2) return KFBI_EINVAL;
+  if (!C || kind < 0 || kind > KFBI_K_YINV || axis < -1 || axis > 2) return KFBI_EINVAL;
   return guarded(C, [&] {
     auto go = [&](auto& sv) {
-      using T = std::remove_reference_t<decltype(*sv.A)>;
       if (launches) *launches = sv.prof_launches;
       if (total_ms) *total_ms = sv.prof_ms;
-      if (bytes_per_launch) *bytes_per_launch = 2.0 * (double)sv.M * sizeof(T);
+      if (bytes_per_launch) *bytes_per_launch = sv.kernel_bytes(kind);
       sv.prof_kind = enable ? kind : -1;
       sv.prof_axis = enable ? axis : -1;
       sv.prof_launches = 0;
@@ -915,23 +938,34 @@ kfbi_status kfbi_profile_pass(kfbi_ctx* C, int32_t kind, int32_t axis, int32_t e
 }
 
 kfbi_status kfbi_time_pass(kfbi_ctx* C, int32_t kind, int32_t axis, int32_t reps, double* avg_ms, double* bytes) {
-  if (!C || !avg_ms || kind < 0 || kind > 4 || axis < 0 || axis > 2 || reps <= 0) return KFBI_EINVAL;
+  if (!C || !avg_ms || kind < 0 || kind > KFBI_K_YINV || axis < 0 || axis > 2 || reps <= 0) return KFBI_EINVAL;
   return guarded(C, [&] {
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     auto run = [&](auto& sv) {
       using T = std::remove_reference_t<decltype(*sv.A)>;
-      HIPCHK(launch_fill<T>(sv.M, sv.A, T(1), C->s));
-      sv.pass(kind, axis, sv.A, sv.B);  // warm-up
+      for (T* f : {sv.A, sv.B, sv.A1, sv.B2, sv.B3, sv.r, sv.d}) HIPCHK(launch_fill<T>(sv.M, f, T(1), C->s));
+      HIPCHK(hipMemsetAsync(sv.scal, 0, 16 * sizeof(double), C->s));
+      auto once = [&] {
+        switch (kind) {
+          case KFBI_K_XMID: sv.xmid(); break;
+          case KFBI_K_ZFWD: sv.zfwd(); break;
+          case KFBI_K_ZINV: sv.zinv(); break;
+          case KFBI_K_YFWD: sv.yfwd(); break;
+          case KFBI_K_YINV: sv.yinv(); break;
+          default: sv.pass(kind, axis, sv.A, sv.B);
+        }
+      };
+      once();  // warm-up
       HIPCHK(hipEventRecord(e0, C->s));
-      for (int r = 0; r < reps; ++r) sv.pass(kind, axis, sv.A, sv.B);
+      for (int r = 0; r < reps; ++r) once();
       HIPCHK(hipEventRecord(e1, C->s));
       HIPCHK(hipEventSynchronize(e1));
       float ms = 0;
       HIPCHK(hipEventElapsedTime(&ms, e0, e1));
       *avg_ms = ms / reps;
-      if (bytes) *bytes = 2.0 * (double)sv.M * sizeof(T);
+      if (bytes) *bytes = sv.kernel_bytes(kind);
     };
     if (C->mixed)
       run(C->s32);

@@ -174,14 +174,22 @@ __global__ __launch_bounds__(256) void k_pass(const T* in, T* out, int axis, Tab
 // orthonormal scale factors cancelling; V'_q = e^{+i pi q/2N}(Y_q - i Y_{N-q}), Y_N = 0,
 // Z'_q = V'^a_q + i V'^b_q.
 // ---------------------------------------------------------------------------------------
+// Pencils per tile of the fused x kernel: one 128-byte row (half-row tiles, with twice the
+// resident blocks, measured slower: 149 vs 115 us at 256^3 float32).
+template <typename T, int N>
+constexpr int xmid_w() {
+  return TileCfg<T, N, DCT2>::W;
+}
+
 template <typename T, int N, int KF, int KI>
 __device__ void xmid_body(T* lds, T* field, int mc, double mu, const double* sig, const double* sig2s,
                           const Tab<T>& tb) {
-  using S = TileCfg<T, N, KF>;
+  constexpr int XW = xmid_w<T, N>();
+  using S = TileCfg<T, N, KF, XW>;
   constexpr int W = S::W, NJ = S::NJ, ZS = S::ZS, NT = S::NT;
   const TileAddr a = tile_addr<W, N>(0, blockIdx.x);
   const int yi = blockIdx.x / (N / W), z0 = (blockIdx.x % (N / W)) * W;
-  fft_tile<T, N, KF>(lds, GlobSrc<T>{field, a.base, a.nstride}, tb);
+  fft_tile<T, N, KF, XW>(lds, GlobSrc<T>{field, a.base, a.nstride}, tb);
   C2<T>* cb = reinterpret_cast<C2<T>*>(lds);
   constexpr int PAIRS = N / 2 + 1;
   static_assert(NT % NJ == 0, "the job of a thread is fixed across the loop");
@@ -232,8 +240,8 @@ __device__ void xmid_body(T* lds, T* field, int mc, double mu, const double* sig
     }
   }
   __syncthreads();
-  fft_core<T, N, KI>(lds, [&](int j, int n) { return cb[j * ZS + n]; }, tb);
-  using O = OutItems<T, N, KI>;
+  fft_core<T, N, KI, XW>(lds, [&](int j, int n) { return cb[j * ZS + n]; }, tb);
+  using O = OutItems<T, N, KI, XW>;
   C2<T>* o = reinterpret_cast<C2<T>*>(field + a.base);
   const long ns = a.nstride / 2;
 #pragma unroll 4
@@ -382,6 +390,14 @@ __global__ __launch_bounds__(256) void k_zinv_cg(const T* __restrict__ A, const 
   constexpr int W = S::W, NT = S::NT, VEC = V16<T>::n, RV = N / VEC;
   const TileAddr a = tile_addr<W, N>(2, blockIdx.x);
   load_tile_z<T, N, NT>(lds, A + a.base);
+  // the B tile is requested before the first transform and staged in LDS after it
+  constexpr int NV = W * N / VEC, PV = (NV + NT - 1) / NT;
+  V16<T> vb[PV];
+#pragma unroll
+  for (int u = 0; u < PV; ++u) {
+    const int e = threadIdx.x + u * NT;
+    if (NV % NT == 0 || e < NV) vb[u] = reinterpret_cast<const V16<T>*>(B + a.base)[e];
+  }
   fft_tile<T, N, DST3>(lds, LdsSrc<T, N>{lds}, tb);
   V16<T> acc[2 * O::PER_Z];
 #pragma unroll
@@ -390,7 +406,16 @@ __global__ __launch_bounds__(256) void k_zinv_cg(const T* __restrict__ A, const 
     if (O::z(u, j, k0)) OutItems<T, N, DST3>::z_values(lds, tb, j, k0, acc[2 * u], acc[2 * u + 1]);
   }
   __syncthreads();
-  load_tile_z<T, N, NT>(lds, B + a.base);
+#pragma unroll
+  for (int u = 0; u < PV; ++u) {
+    const int e = threadIdx.x + u * NT;
+    if (NV % NT == 0 || e < NV) {
+      const int p = (e * VEC) / N, n = (e * VEC) - p * N;
+#pragma unroll
+      for (int qq = 0; qq < VEC; ++qq) lds[p * (N + 1) + n + qq] = vb[u].a[qq];
+    }
+  }
+  __syncthreads();
   // the d vectors of the thread are requested before the second transform
   const V16<T>* dv = reinterpret_cast<const V16<T>*>(d + a.base);
   V16<T> dd[2 * O::PER_Z];
@@ -1089,7 +1114,7 @@ hipError_t launch_xmid(int N, T* A0, T* A1, T* A2, double mu, const DevTables<T>
   const Tab<T> t = tab_of(tb);
 #define KFBI_M(NN)                                                                                              \
   {                                                                                                             \
-    using S = TileCfg<T, NN, DCT2>;                                                                             \
+    using S = TileCfg<T, NN, DCT2, xmid_w<T, NN>()>;                                                            \
     const int blocks = NN * NN / S::W;                                                                          \
     const size_t lds = S::BYTES;                                                                                \
     ensure_lds(k_xmid<T, NN>, lds);                                                                             \
