@@ -15,6 +15,11 @@ Cartesian MAC grid):
 * ``ellip128``    Navier, lambda=10, mu=1, ellipsoid (0.6,0.45,0.35) rotated 30 deg about z, N=128.
 * ``star256``     Stokes, mu=1, star as star128, N=256 (the headline evaluation size).
 * ``star512n``    Navier, lambda=100, mu=1, star r=0.5+0.12 sin(5 theta) cos(3 phi), N=512.
+* ``ex51`` .. ``ex56``  the six examples of Sec. 5 of the paper, box [-1.2,1.2]^3: Stokes on
+  the unit sphere (5.1, the printed u2 corrected to be divergence-free), on the ellipsoid
+  x^2 + y^2/0.64 + z^2/0.36 = 1 (5.2) and on the torus a = 0.35, c = 0.7 (5.3); Navier with
+  (E, nu) = (1000, 1/10) on the unit sphere (5.4), (4000, 1/20) on the ellipsoid (1, 0.8, 0.6)
+  (5.5) and (2000, 2/5) on the torus (5.6); mu = E / (2(1+nu)), lambda = E nu / ((1+nu)(1-2nu)).
 """
 from __future__ import annotations
 
@@ -81,6 +86,91 @@ WORKLOADS = {
 }
 
 
+def lame(E, nu):
+    """(mu, lambda) of Young's modulus E and Poisson ratio nu."""
+    return E / (2 * (1 + nu)), E * nu / ((1 + nu) * (1 - 2 * nu))
+
+
+_BOX = dict(lo=-1.2, hi=1.2)
+WORKLOADS.update({
+    "ex51": Config(N=64, pde=STOKES, mu=1.0, shape=sphere(1.0), solution="ex51", **_BOX),
+    "ex52": Config(N=64, pde=STOKES, mu=1.0, shape=ellipsoid(1.0, 0.8, 0.6), solution="ex52", **_BOX),
+    "ex53": Config(N=64, pde=STOKES, mu=1.0, shape=torus(0.35, 0.7), solution="ex53", **_BOX),
+    "ex54": Config(N=64, pde=NAVIER, mu=lame(1000, 0.1)[0], lam=lame(1000, 0.1)[1], shape=sphere(1.0),
+                   solution="ex54", **_BOX),
+    "ex55": Config(N=64, pde=NAVIER, mu=lame(4000, 0.05)[0], lam=lame(4000, 0.05)[1],
+                   shape=ellipsoid(1.0, 0.8, 0.6), solution="ex55", **_BOX),
+    "ex56": Config(N=64, pde=NAVIER, mu=lame(2000, 0.4)[0], lam=lame(2000, 0.4)[1], shape=torus(0.35, 0.7),
+                   solution="ex56", **_BOX),
+})
+
+
+def _paper_example_exprs(name, printed=False):
+    """Sympy expressions (u1, u2, u3, p or None) of the exact solutions of Sec. 5.  Example 5.1
+    as printed has div u = -2y; printed=False returns it with y^2(2 - y^2) in u2, which makes
+    it divergence-free."""
+    import sympy as sp
+    x, y, z = sp.symbols("x y z", real=True)
+    r2 = x ** 2 + y ** 2 + z ** 2
+    if name == "ex51":
+        u = (x**2 * (2 - x**2) + 4 * x * y * (x**2 + y**2 - 1) + z**2 * (3 * z**2 - 6 * x**2 - 2),
+             x**2 * (3 * x**2 - 6 * y**2 - 1) + y**2 * ((1 if printed else 2) - y**2),
+             4 * z * x * (z**2 + x**2 - 1))
+        p = 8 * y * (3 * x**2 - y**2) + 8 * x * (3 * z**2 - x**2)
+    elif name == "ex52":
+        u = (2 * x**3 * y / 3 - z**2 * x**2 + sp.exp(z) + sp.sin(sp.pi * z),
+             -x**2 * y**2 + sp.cos(sp.pi * x),
+             2 * z**3 * x / 3 + sp.exp(x) + sp.sin(sp.pi * x))
+        p = (x - 1)**3 * (y - 1)**3 * (z - 1)**3
+    elif name == "ex53":
+        u = (-4 * x * y * (1 - x**2 - y**2) - x**2 * (x**2 + 6 * z**2 - 2) + z**2 * (3 * z**2 - 2)
+             + sp.exp(sp.cos(y)) + sp.exp(sp.sin(z)),
+             x**2 * (3 * x**2 - 6 * y**2 - 2) - y**2 * (y**2 - 2) + sp.exp(sp.sin(x)),
+             -4 * (1 - x**2 - z**2) * x * z + sp.exp(sp.cos(x)))
+        p = sp.exp(1 - y**2 - z**3) * sp.sin(x**2 + 1)
+    elif name == "ex54":
+        s = sp.sin(2 * sp.pi * r2)
+        u = (s * sp.cos(2 * y) * sp.cos(z), s * sp.cos(x) * sp.cos(x + z), s * sp.cos(sp.pi * x) * sp.cos(y))
+        p = None
+    elif name == "ex55":
+        c = sp.cos(x) * sp.cos(y) * sp.cos(z)
+        u = (r2 - 4 + c, r2 - 4 + x * y + c, r2 - 4 + y * z + c)
+        p = None
+    elif name == "ex56":
+        u = (sp.exp(1 - y**2 - z**2) * sp.sin(3 * x**2 + 2), sp.sin(1 - r2), 3 * x**2 + 2 * y**2 + z**2)
+        p = None
+    else:
+        raise ValueError(name)
+    return (x, y, z), u, p
+
+
+_PAPER_CACHE = {}
+
+
+def _paper_example(name, mu, lam):
+    """Numpy callables (u, p, f) of a Sec. 5 example: f = -mu lap u + grad p (Stokes) or
+    f = -mu lap u - (lambda+mu) grad div u (Navier, with p = -(lambda+mu) div u)."""
+    key = (name, mu, lam)
+    if key not in _PAPER_CACHE:
+        import sympy as sp
+        (x, y, z), u, p = _paper_example_exprs(name)
+        X = (x, y, z)
+        div = sum(sp.diff(u[i], X[i]) for i in range(3))
+        lap = [sum(sp.diff(u[i], X[k], 2) for k in range(3)) for i in range(3)]
+        if p is not None:  # Stokes
+            f = [-mu * lap[i] + sp.diff(p, X[i]) for i in range(3)]
+        else:
+            p = -(lam + mu) * div
+            f = [-mu * lap[i] - (lam + mu) * sp.diff(div, X[i]) for i in range(3)]
+        fu = sp.lambdify(X, list(u), "numpy")
+        fp = sp.lambdify(X, p, "numpy")
+        ff = sp.lambdify(X, f, "numpy")
+        stack = lambda g: (lambda a, b, c: np.stack(np.broadcast_arrays(*[np.asarray(v, float) + 0 * a
+                                                                           for v in g(a, b, c)]), axis=-1))
+        _PAPER_CACHE[key] = (stack(fu), lambda a, b, c: np.asarray(fp(a, b, c), float) + 0 * a, stack(ff))
+    return _PAPER_CACHE[key]
+
+
 # ----------------------------------------------------------------------------------------
 # Manufactured exact solutions (problem data).  Each returns arrays shaped like x.
 # ----------------------------------------------------------------------------------------
@@ -99,6 +189,8 @@ def exact_u(sol: str, x, y, z):
     if sol == "navier_exp":
         s = np.exp(x) * np.sin(y + z)
         return s[..., None] * _NAV_A
+    if sol.startswith("ex5"):
+        return _paper_example(sol, 1.0, 0.0)[0](x, y, z)
     raise ValueError(sol)
 
 
@@ -111,6 +203,8 @@ def exact_p(sol: str, x, y, z, lam: float = 0.0, mu: float = 1.0):
         a = _NAV_A
         div = np.exp(x) * (a[0] * np.sin(y + z) + (a[1] + a[2]) * np.cos(y + z))
         return -(lam + mu) * div
+    if sol.startswith("ex5"):
+        return _paper_example(sol, mu, lam)[1](x, y, z)
     raise ValueError(sol)
 
 
@@ -130,6 +224,8 @@ def body_force(sol: str, x, y, z, mu: float = 1.0, lam: float = 0.0):
         b = a[1] + a[2]
         gdiv = np.stack([e * (a[0] * s + b * c), e * (a[0] * c - b * s), e * (a[0] * c - b * s)], axis=-1)
         return -mu * lap_u - (lam + mu) * gdiv
+    if sol.startswith("ex5"):
+        return _paper_example(sol, mu, lam)[2](x, y, z)
     raise ValueError(sol)
 
 

@@ -135,9 +135,9 @@ class Plan:
         _lib.kfbi_plan_get(self._h, name.encode(), out.ctypes.data_as(C.c_void_p))
         return out
 
-    def __del__(self):
+    def __del__(self, _destroy=_lib.kfbi_plan_destroy):
         if getattr(self, "_h", None):
-            _lib.kfbi_plan_destroy(self._h)
+            _destroy(self._h)
             self._h = None
 
 

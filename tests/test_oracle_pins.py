@@ -372,3 +372,35 @@ def test_bvp_second_order_on_sphere(form):
         assert hist[-1] < 1e-8
     for m in range(3):
         assert res[0][f"u{m}_l2"] / res[1][f"u{m}_l2"] > 3.0, res
+
+
+def test_paper_example_solutions_are_consistent():
+    """The manufactured solutions of the paper's Stokes examples are divergence-free (5.1 only
+    after correcting the printed u2: as printed its divergence is -2y), and the body forces of
+    all six examples satisfy the PDE (checked here by central differences of the symbolic
+    solution, independently of the symbolic derivation of f)."""
+    import sympy as sp
+    (x, y, z), u, p = KI._paper_example_exprs("ex51", printed=True)
+    assert sp.simplify(sum(sp.diff(u[i], v) for i, v in enumerate((x, y, z))) + 2 * y) == 0
+    for name in ("ex51", "ex52", "ex53"):
+        (x, y, z), u, p = KI._paper_example_exprs(name)
+        assert sp.simplify(sum(sp.diff(u[i], v) for i, v in enumerate((x, y, z)))) == 0
+    rng = np.random.default_rng(0)
+    P = rng.uniform(-0.5, 0.5, (5, 3))
+    hh = 1e-3
+    for name in ("ex51", "ex52", "ex53", "ex54", "ex55", "ex56"):
+        cfg = KI.WORKLOADS[name]
+        U = lambda q: KI.exact_u(cfg.solution, q[:, 0], q[:, 1], q[:, 2])
+        E = np.eye(3) * hh
+        lap = sum(U(P + E[k]) - 2 * U(P) + U(P - E[k]) for k in range(3)) / hh ** 2
+        if cfg.pde == 0:
+            pf = lambda q: KI.exact_p(cfg.solution, q[:, 0], q[:, 1], q[:, 2])
+            grad = np.stack([(pf(P + E[k]) - pf(P - E[k])) / (2 * hh) for k in range(3)], -1)
+            f = -cfg.mu * lap + grad
+        else:
+            def div(q):
+                return sum((U(q + E[k])[:, k] - U(q - E[k])[:, k]) / (2 * hh) for k in range(3))
+            gdiv = np.stack([(div(P + E[k]) - div(P - E[k])) / (2 * hh) for k in range(3)], -1)
+            f = -cfg.mu * lap - (cfg.lam + cfg.mu) * gdiv
+        fo = KI.body_force(cfg.solution, P[:, 0], P[:, 1], P[:, 2], cfg.mu, cfg.lam)
+        assert np.abs(f - fo).max() < 1e-4 * (1 + np.abs(fo).max()), name
