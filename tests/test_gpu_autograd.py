@@ -123,3 +123,38 @@ def test_gradient_wrt_dirichlet_data_matches_central_differences(K, name, N, ndi
     _say(f"   loss {L.item():.6e}  worst rel diff {worst:.3e} over {ndir} directions, "
          f"adjoint GMRES iterations {adj_iters}")
     assert worst < 1e-6
+
+
+def test_512_navier_density_gradient_matches_central_differences(K):
+    """Navier, lambda = 100, star at 512^3, mixed form: the gradient of the boundary misfit
+    l(phi) = 1/2 |K phi - t|^2 with respect to the density by the hand-written transpose
+    (BIEEval backward = kfbi_eval_adjoint) against central differences on 4 random directions.
+    l is exactly quadratic in phi, so the agreement is limited by the refinement tolerance
+    (1e-10 here), not by the step."""
+    import torch
+    cfg = KI.WORKLOADS["star512n"]
+    _say("[fd 512] star512n mixed")
+    op = K.Operator(cfg, K.MIXED_FP32, cg_rtol=1e-10, inner_rtol=1e-5)
+    xyz, _ = op.points()
+    phi0 = torch.as_tensor(KI.exact_u(cfg.solution, xyz[:, 0], xyz[:, 1], xyz[:, 2]), device="cuda")
+    target = 0.9 * phi0 + 0.05
+
+    def loss(phi):
+        return 0.5 * ((K.BIEEval.apply(phi, op) - target) ** 2).sum()
+
+    phi = phi0.clone().requires_grad_(True)
+    L = loss(phi)
+    L.backward()
+    grad = phi.grad.detach()
+    dirs = torch.as_tensor(KI.random_directions(op.n, 4, seed=1), device="cuda")
+    eps = 1e-2 * torch.linalg.norm(phi0).item()
+    worst = 0.0
+    with torch.no_grad():
+        for d in dirs:
+            fd = (loss(phi0 + eps * d) - loss(phi0 - eps * d)).item() / (2 * eps)
+            an = float((grad * d).sum().item())
+            rel = abs(fd - an) / max(abs(fd), 1e-30)
+            worst = max(worst, rel)
+            _say(f"   direction: fd {fd:.10e} adjoint {an:.10e} rel {rel:.2e}")
+    _say(f"   loss {L.item():.6e}  worst rel diff {worst:.3e}")
+    assert worst < 1e-6

@@ -97,3 +97,25 @@ def test_bvp_mixed_agrees_with_fp64(K, name, N):
     assert d < 1e-6
     for k in e64:
         assert abs(e32[k] - e64[k]) <= 1e-3 * e64[k] + 1e-9
+
+
+def test_near_incompressible_navier_counts(K):
+    """Navier with lambda = 100 (nu = 0.495, outside the paper's tested range) on the 5-lobed
+    star: GMRES and inner CG counts of the mixed form as N grows to 512, and second-order
+    error decay."""
+    errs, its = [], []
+    for N in (128, 256, 512):
+        cfg = KI.WORKLOADS["star512n"].with_N(N)
+        op, phi, u, p, info = _solve(K, cfg, 1)
+        e = _errors(cfg, op, u, p)
+        errs.append(e)
+        its.append(info["gmres_iters"])
+        _say(f"[bvp navier lambda=100] N={N} gmres {info['gmres_iters']} inner CG per eval "
+             f"{info['cg_iters'] / max(1, info['gmres_iters'] + 2):.1f} "
+             + " ".join(f"{k} {v:.3e}" for k, v in e.items()))
+        assert info["final_rel_residual"] < 1e-8
+        del op
+    for a, b in zip(errs[:-1], errs[1:]):
+        for m in range(3):
+            assert a[f"u{m}"] / b[f"u{m}"] > 3.0, (a, b)
+    assert max(its) <= 1.5 * min(its) + 5, its
