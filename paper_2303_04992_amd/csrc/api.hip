@@ -230,20 +230,18 @@ struct MacSolver {
   // Fu: 3 fields (internal layout, face 0 ignored), Fp: 1 field.  Returns CG iterations or
   // -1 if maxit was reached.
   int solve(const T* Fu, const T* Fp, T* u, T* p, double rtol, int maxit) {
-    // 1. spectral right-hand sides T_m F_m
+    // 1.-2. b = P(F_p - sum_m C_m^T [sigma/Lambda_m] T_m F_m).  Per component: T_m along z and
+    // y, then the fused x pass keeps Fh[m] = T_m F_m and leaves C_m,x^T of the weighted
+    // spectrum; the y and z inverses of the three components are shared as in the matvec.
+    T* H[3] = {A1, B2, B3};
     for (int m = 0; m < 3; ++m) {
-      pass(m == 0 ? DST1 : DST2, 0, Fu + m * M, Fh[m]);
+      pass(m == 2 ? DST1 : DST2, 2, Fu + m * M, Fh[m]);
       pass(m == 1 ? DST1 : DST2, 1, Fh[m], Fh[m]);
-      pass(m == 2 ? DST1 : DST2, 2, Fh[m], Fh[m]);
+      HIPCHK(launch_xfuse<T>(N, m, false, Fh[m], Fh[m], H[m], mu, tb, s));
     }
-    // 2. b = P(F_p - sum_m C_m^T [sigma/Lambda_m] T_m F_m)
-    HIPCHK(launch_fill<T>(M, b, T(0), s));
-    for (int m = 0; m < 3; ++m) {
-      HIPCHK(launch_zscale_inv<T>(N, m, W_RHS, Fh[m], tmp, mu, tb, s));
-      pass(m == 1 ? DCT3 : DST3, 1, tmp, tmp);
-      pass(m == 0 ? DCT3 : DST3, 0, tmp, b, true);
-    }
-    HIPCHK(launch_rhs_minus_t<T>(M, b, Fp, s));
+    HIPCHK(launch_ypair<T>(N, true, A1, B2, A, A, tb, s));       // A = DST_y^T H0 + DCT_y^T H1
+    pass(DST3, 1, B3, B);                                        // B = DST_y^T H2
+    HIPCHK(launch_zinv_cg<T>(N, A, B, b, Fp, 1.0, partials, tb, s));  // b = DST_z^T A + DCT_z^T B + F_p
     project_mean(b);
     // 3. CG on S x = b
     HIPCHK(launch_fill<T>(M, x, T(0), s));
@@ -276,15 +274,16 @@ struct MacSolver {
       if (!(last > thr)) conv = true;
     }
     project_mean(x);
-    // 4. velocity back-substitution u_m = T_m^T [(T_m F_m + sigma C_m p) / Lambda_m]
+    // 4. velocity back-substitution u_m = T_m^T [(T_m F_m + sigma C_m p) / Lambda_m]: C_m p along
+    // z and y shared as in the matvec, then per component the fused x pass and the y, z inverses
+    HIPCHK(launch_zfwd_cg<T>(N, x, nullptr, A, B, nullptr, tb, s));  // A = DST_z p, B = DCT_z p
+    HIPCHK(launch_ypair<T>(N, false, A, A, A1, B2, tb, s));          // C_0, C_1 along y
+    pass(DST2, 1, B, B3);                                             // C_2 along y
     for (int m = 0; m < 3; ++m) {
-      pass(m == 0 ? DCT2 : DST2, 0, x, tmp);
-      pass(m == 1 ? DCT2 : DST2, 1, tmp, tmp);
-      pass(m == 2 ? DCT2 : DST2, 2, tmp, tmp);
-      HIPCHK(launch_backsub_combine<T>(N, m, Fh[m], tmp, A, mu, tb, s));
-      pass(m == 2 ? DST1 : DST3, 2, A, A);
-      pass(m == 1 ? DST1 : DST3, 1, A, A);
-      pass(m == 0 ? DST1 : DST3, 0, A, u + m * M);
+      T* um = u + m * M;
+      HIPCHK(launch_xfuse<T>(N, m, true, H[m], Fh[m], um, mu, tb, s));
+      pass(m == 1 ? DST1 : DST3, 1, um, um);
+      pass(m == 2 ? DST1 : DST3, 2, um, um);
     }
     if (p) HIPCHK(hipMemcpyAsync(p, x, M * sizeof(T), hipMemcpyDeviceToDevice, s));
     if (prof_used) {

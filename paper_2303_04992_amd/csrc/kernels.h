@@ -30,14 +30,11 @@ enum WeightKind { W_SCHUR = 0, W_RHS = 1 };
 template <typename T>
 hipError_t launch_pass(int N, int kind, int axis, const T* in, T* out, bool accumulate, const DevTables<T>& tb,
                        hipStream_t s);
-// z-pass: scale the (x, y, z)-spectral field by the weight of component m, then inverse z
-template <typename T>
-hipError_t launch_zscale_inv(int N, int m, int wkind, const T* in, T* out, double mu, const DevTables<T>& tb,
-                             hipStream_t s);
 // fused x-pass of the Schur operator for the three components (fwd x, weight, inverse x)
 template <typename T>
 hipError_t launch_xmid(int N, T* A0, T* A1, T* A2, double mu, const DevTables<T>& tb, hipStream_t s);
-// d = r + beta d_old (beta from scal[2]), A = DST-II_z(d), B = DCT-II_z(d)
+// d = r + beta d_old (beta from scal[2]), A = DST-II_z(d), B = DCT-II_z(d); with d = nullptr
+// only A = DST-II_z(r), B = DCT-II_z(r) (scal unused)
 template <typename T>
 hipError_t launch_zfwd_cg(int N, const T* r, T* d, T* A, T* B, const double* scal, const DevTables<T>& tb,
                           hipStream_t s);
@@ -45,6 +42,11 @@ hipError_t launch_zfwd_cg(int N, const T* r, T* d, T* A, T* B, const double* sca
 template <typename T>
 hipError_t launch_zinv_cg(int N, const T* A, const T* B, T* q, const T* d, double c, double* partials,
                           const DevTables<T>& tb, hipStream_t s);
+// fused x pass of component m: right-hand side (fh = T_m,x in; out = C_m,x^T (-sigma/(mu Lambda)) fh)
+// or back-substitution (out = T_m,x^T ((fh + sigma C_m,x in) / (mu Lambda)))
+template <typename T>
+hipError_t launch_xfuse(int N, int m, bool backsub, const T* in, T* fh, T* out, double mu, const DevTables<T>& tb,
+                        hipStream_t s);
 // y passes with two transforms per block: forward (out0 = DST-II_y(in0), out1 = DCT-II_y(in0)),
 // inverse (out0 = DST-III_y(in0) + DCT-III_y(in1))
 template <typename T>
@@ -55,10 +57,6 @@ int zinv_blocks(int N, int elem_size);
 template <typename T>
 hipError_t launch_cg_update(int64_t M, T* x, T* r, const T* d, const T* q, const double* scal, double* partials,
                             int nblocks, hipStream_t s);
-// back-substitution combine in spectral space: G = (F + sigma_{i_m} P) / Lambda_m
-template <typename T>
-hipError_t launch_backsub_combine(int N, int m, const T* F, const T* P, T* G, double mu, const DevTables<T>& tb,
-                                  hipStream_t s);
 
 // ---- reductions (float64, deterministic)
 // scal layout: [0] rr, [1] alpha, [2] beta, [3] mean q, [4] rr0, [5] scratch sum, [6] aux
@@ -77,13 +75,6 @@ template <typename T>
 hipError_t launch_fill(int64_t n, T* a, T v, hipStream_t s);
 template <typename T>
 hipError_t launch_axpby(int64_t n, T* y, double a, const T* x, double b, hipStream_t s);  // y = a x + b y
-template <typename TO, typename TI>
-hipError_t launch_convert(int64_t n, TO* out, const TI* in, hipStream_t s);
-template <typename TI>
-hipError_t launch_add_into_f64(int64_t n, double* out, const TI* in, hipStream_t s);  // out += in
-hipError_t launch_rhs_minus(int64_t M, double* b, const double* Fp, hipStream_t s);   // b = Fp - b
-template <typename T>
-hipError_t launch_rhs_minus_t(int64_t M, T* b, const T* Fp, hipStream_t s);
 
 // ---- full-system residual of the MAC scheme (float64)
 // r_u = F_u - (-mu lap u + G p), r_p = F_p - (D u + c p), internal layout
@@ -94,8 +85,6 @@ hipError_t launch_refine_prep(int64_t M, const double* F, float* r32, double* pa
 hipError_t launch_refine_residual(bool first, int N, double h, double mu, double c, const double* u, const double* p,
                                   const float* x32, const double* F, const double* shift, double* un, double* pn,
                                   float* r32, double* partials, int nparts, hipStream_t s);
-hipError_t launch_mac_residual(int N, double h, double mu, double c, const double* u, const double* p,
-                               const double* Fu, const double* Fp, double* ru, double* rp, hipStream_t s);
 
 // ---- surface stages (float64)
 hipError_t launch_fit_jump(int64_t T, const int64_t* nb_ptr, const int32_t* nb_idx, const double* fitw,

@@ -255,6 +255,104 @@ __device__ void xmid_body(T* lds, T* field, int mc, double mu, const double* sig
   }
 }
 
+template <typename T, int N, int KIND>
+__device__ __forceinline__ void store_xy_outputs(const T* lds, const Tab<T>& tb, T* out, long nstride) {
+  using O = OutItems<T, N, KIND>;
+  C2<T>* o = reinterpret_cast<C2<T>*>(out);
+  const long ns = nstride / 2;
+#pragma unroll 4
+  for (int u = 0; u < O::PER_XY; ++u) {
+    int j, k;
+    if (O::xy(u, j, k)) {
+      C2<T> v;
+      post_pair<T, N, KIND>(lds, tb, j, k, v.x, v.y);
+      o[k * ns + j] = v;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------------------
+// fused x pass of the right-hand side and of the velocity back-substitution, component m:
+//   RHS      (KF = T_m along x, KI = C_m^T along x): fh = KF(in) (the full T_m F_m, kept for
+//            the back-substitution), out = KI(-sigma_m / (mu Lambda_m) fh)
+//   BACKSUB  (KF = C_m along x, KI = T_m^T along x): out = KI((fh + sigma_m KF(in)) / (mu Lambda_m))
+// The forward outputs go to registers, are weighted (and fh read or written), and the tile
+// is restaged in LDS for the inverse.
+// ---------------------------------------------------------------------------------------
+template <typename T, int N, int KF, int KI, bool BACKSUB>
+__global__ __launch_bounds__(256) void k_xfuse(const T* __restrict__ in, T* __restrict__ fh, T* __restrict__ out,
+                                              int m, double mu, const double* __restrict__ sig,
+                                              const double* __restrict__ sig2s, Tab<T> tb) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* lds = reinterpret_cast<T*>(smem);
+  using SF = TileCfg<T, N, KF>;
+  using OF = OutItems<T, N, KF>;
+  static_assert(SF::W == TileCfg<T, N, KI>::W, "one tile for both transforms");
+  constexpr int W = SF::W, RS = N + 1;
+  const TileAddr a = tile_addr<W, N>(0, blockIdx.x);
+  const int yi = blockIdx.x / (N / W), z0 = (blockIdx.x % (N / W)) * W;
+  C2<T>* fp = reinterpret_cast<C2<T>*>(fh + a.base);
+  const long ns = a.nstride / 2;
+  C2<T> f[BACKSUB ? OF::PER_XY : 1];
+  if constexpr (BACKSUB) {
+#pragma unroll
+    for (int u = 0; u < OF::PER_XY; ++u) {
+      int j, k;
+      if (OF::xy(u, j, k)) f[u] = fp[k * ns + j];
+    }
+  }
+  fft_tile<T, N, KF>(lds, GlobSrc<T>{in, a.base, a.nstride}, tb);
+  C2<T> v[OF::PER_XY];
+#pragma unroll
+  for (int u = 0; u < OF::PER_XY; ++u) {
+    int j, k;
+    if (OF::xy(u, j, k)) {
+      post_pair<T, N, KF>(lds, tb, j, k, v[u].x, v[u].y);
+      // sigma_m and 1 / (mu Lambda_m) of the two pencils (z indices z0 + 2j, z0 + 2j + 1); the
+      // index along m is mode k of the DCT-II / DST-I, along the other axes mode k + 1 of DST-II
+      T sg[2], il[2];
+      const int id[3] = {k, yi, z0 + 2 * j};
+#pragma unroll
+      for (int w = 0; w < 2; ++w) {
+        T lam = T(0);
+#pragma unroll
+        for (int d = 0; d < 3; ++d) {
+          const int i = id[d] + (d == 2 ? w : 0);
+          lam += (d == m) ? tb.sg2[i] : tb.sg2s[i];
+        }
+        const int im = (m == 2) ? id[2] + w : id[m];
+        if constexpr (sizeof(T) == 4) {
+          sg[w] = __builtin_sqrtf(tb.sg2[im]);
+          il[w] = __builtin_amdgcn_rcpf(T(mu) * lam);  // 1 ulp: the float32 inner solve
+        } else {
+          sg[w] = sqrt(tb.sg2[im]);
+          il[w] = T(1) / (T(mu) * lam);
+        }
+      }
+      if constexpr (BACKSUB) {
+        v[u].x = (f[u].x + sg[0] * v[u].x) * il[0];
+        v[u].y = (f[u].y + sg[1] * v[u].y) * il[1];
+      } else {
+        fp[k * ns + j] = v[u];
+        v[u].x = -sg[0] * il[0] * v[u].x;
+        v[u].y = -sg[1] * il[1] * v[u].y;
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < OF::PER_XY; ++u) {
+    int j, k;
+    if (OF::xy(u, j, k)) {
+      lds[(2 * j) * RS + k] = v[u].x;
+      lds[(2 * j + 1) * RS + k] = v[u].y;
+    }
+  }
+  __syncthreads();
+  fft_tile<T, N, KI>(lds, LdsSrc<T, N>{lds}, tb);
+  store_xy_outputs<T, N, KI>(lds, tb, out + a.base, a.nstride);
+}
+
 template <typename T, int N>
 __global__ __launch_bounds__(256) void k_xmid(T* A0, T* A1, T* A2, double mu, const double* sig,
                                              const double* sig2s, Tab<T> tb) {
@@ -269,40 +367,6 @@ __global__ __launch_bounds__(256) void k_xmid(T* A0, T* A1, T* A2, double mu, co
     xmid_body<T, N, DST2, DST3>(lds, A2, 2, mu, sig, sig2s, tb);
 }
 
-// z-pass of the right-hand side: scale by sigma_m / Lambda_m, inverse z (KI)
-template <typename T, int N, int KI>
-__global__ __launch_bounds__(256) void k_zscale_inv(const T* __restrict__ in, T* __restrict__ out, int m, double mu,
-                                                   const double* sig, const double* sig2s, Tab<T> tb) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  T* lds = reinterpret_cast<T*>(smem);
-  using S = TileCfg<T, N, KI>;
-  using O = OutItems<T, N, KI>;
-  constexpr int W = S::W, RS = N + 1, NT = S::NT;
-  const TileAddr a = tile_addr<W, N>(2, blockIdx.x);
-  load_tile_z<T, N, NT>(lds, in + a.base);
-  for (int e = threadIdx.x; e < W * N; e += NT) {
-    const int p = e / N, k = e - p * N;
-    const int q = blockIdx.x * W + p;
-    const int xi = q / N, yi = q - xi * N;
-    double lam, sg;
-    lambda_of(m, xi, yi, k, sig, sig2s, lam, sg);
-    lds[p * RS + k] *= T(sg / (mu * lam));
-  }
-  __syncthreads();
-  fft_tile<T, N, KI>(lds, LdsSrc<T, N>{lds}, tb);
-  V16<T>* o = reinterpret_cast<V16<T>*>(out + a.base);
-  constexpr int RV = N / O::VEC;
-#pragma unroll
-  for (int u = 0; u < O::PER_Z; ++u) {
-    int j, k0;
-    if (O::z(u, j, k0)) {
-      V16<T> v0, v1;
-      O::z_values(lds, tb, j, k0, v0, v1);
-      o[(2 * j) * RV + k0 / O::VEC] = v0;
-      o[(2 * j + 1) * RV + k0 / O::VEC] = v1;
-    }
-  }
-}
 
 // ---------------------------------------------------------------------------------------
 // CG z-passes with fused vector updates
@@ -326,7 +390,7 @@ __device__ __forceinline__ void store_z_outputs(const T* lds, const Tab<T>& tb, 
   }
 }
 
-template <typename T, int N>
+template <typename T, int N, bool CG>
 __global__ __launch_bounds__(256) void k_zfwd_cg(const T* __restrict__ r, T* __restrict__ d, T* __restrict__ A,
                                                 T* __restrict__ B, const double* __restrict__ scal, Tab<T> tb) {
   extern __shared__ __align__(16) unsigned char smem[];
@@ -334,17 +398,17 @@ __global__ __launch_bounds__(256) void k_zfwd_cg(const T* __restrict__ r, T* __r
   using S = TileCfg<T, N, DST2>;
   constexpr int W = S::W, RS = N + 1, NT = S::NT, VEC = V16<T>::n;
   constexpr int NV = W * N / VEC, PER = (NV + NT - 1) / NT;
-  const T beta = T(scal[2]);
+  const T beta = CG ? T(scal[2]) : T(0);
   const TileAddr a = tile_addr<W, N>(2, blockIdx.x);
   const V16<T>* rv = reinterpret_cast<const V16<T>*>(r + a.base);
-  V16<T>* dv = reinterpret_cast<V16<T>*>(d + a.base);
+  V16<T>* dv = CG ? reinterpret_cast<V16<T>*>(d + a.base) : nullptr;
   V16<T> x[PER], y[PER];
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
     const int e = threadIdx.x + u * NT;
     if (NV % NT == 0 || e < NV) {
       x[u] = rv[e];
-      y[u] = dv[e];
+      if (CG) y[u] = dv[e];
     }
   }
   auto stage = [&]() {
@@ -359,13 +423,15 @@ __global__ __launch_bounds__(256) void k_zfwd_cg(const T* __restrict__ r, T* __r
     }
     __syncthreads();
   };
+  if constexpr (CG) {
 #pragma unroll
-  for (int u = 0; u < PER; ++u) {
-    const int e = threadIdx.x + u * NT;
-    if (NV % NT == 0 || e < NV) {
+    for (int u = 0; u < PER; ++u) {
+      const int e = threadIdx.x + u * NT;
+      if (NV % NT == 0 || e < NV) {
 #pragma unroll
-      for (int q = 0; q < VEC; ++q) x[u].a[q] += beta * y[u].a[q];
-      dv[e] = x[u];
+        for (int q = 0; q < VEC; ++q) x[u].a[q] += beta * y[u].a[q];
+        dv[e] = x[u];
+      }
     }
   }
   stage();
@@ -465,22 +531,6 @@ __global__ __launch_bounds__(256) void k_zinv_cg(const T* __restrict__ A, const 
 // y passes of the Schur matvec with two transforms per block.
 // forward: A1 = DST-II_y(A), B2 = DCT-II_y(A) (the tile of A is read twice, the second time
 // from L2); inverse: A = DST-III_y(A1) + DCT-III_y(B2)
-template <typename T, int N, int KIND>
-__device__ __forceinline__ void store_xy_outputs(const T* lds, const Tab<T>& tb, T* out, long nstride) {
-  using O = OutItems<T, N, KIND>;
-  C2<T>* o = reinterpret_cast<C2<T>*>(out);
-  const long ns = nstride / 2;
-#pragma unroll 4
-  for (int u = 0; u < O::PER_XY; ++u) {
-    int j, k;
-    if (O::xy(u, j, k)) {
-      C2<T> v;
-      post_pair<T, N, KIND>(lds, tb, j, k, v.x, v.y);
-      o[k * ns + j] = v;
-    }
-  }
-}
-
 template <typename T, int N>
 __global__ __launch_bounds__(256) void k_ypair_fwd(const T* __restrict__ A, T* __restrict__ A1, T* __restrict__ B2,
                                                   Tab<T> tb) {
@@ -605,17 +655,6 @@ __global__ void k_add_scalar(int64_t M, T* a, const double* scal, int idx, doubl
     a[i] += v;
 }
 
-template <typename T, int N>
-__global__ void k_backsub_combine(int m, const T* __restrict__ F, const T* __restrict__ P, T* __restrict__ G,
-                                  double mu, const double* sig, const double* sig2s) {
-  const int64_t M = (int64_t)N * N * N;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (int64_t)gridDim.x * blockDim.x) {
-    const int k = (int)(i % N), j = (int)((i / N) % N), xi = (int)(i / ((int64_t)N * N));
-    double lam, sg;
-    lambda_of(m, xi, j, k, sig, sig2s, lam, sg);
-    G[i] = T(((double)F[i] + sg * (double)P[i]) / (mu * lam));
-  }
-}
 
 // ---------------------------------------------------------------------------------------
 // elementwise
@@ -630,70 +669,11 @@ __global__ void k_axpby(int64_t n, T* y, double a, const T* x, double b) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     y[i] = T(a * (double)x[i] + b * (double)y[i]);
 }
-template <typename TO, typename TI>
-__global__ void k_convert(int64_t n, TO* out, const TI* in) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    out[i] = TO(in[i]);
-}
-template <typename TI>
-__global__ void k_add_into_f64(int64_t n, double* out, const TI* in) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    out[i] += (double)in[i];
-}
-template <typename T>
-__global__ void k_rhs_minus(int64_t n, T* b, const T* Fp) {
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    b[i] = Fp[i] - b[i];
-}
 
 // ---------------------------------------------------------------------------------------
 // full-system MAC residual (float64, internal layout)
 // ---------------------------------------------------------------------------------------
-__global__ void k_res_u(int N, int m, double h, double mu, const double* __restrict__ u, const double* __restrict__ p,
-                        const double* __restrict__ F, double* __restrict__ r) {
-  const int64_t M = (int64_t)N * N * N;
-  const double ih2 = 1.0 / (h * h), ih = 1.0 / h;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (int64_t)gridDim.x * blockDim.x) {
-    const int id[3] = {(int)(i / ((int64_t)N * N)), (int)((i / N) % N), (int)(i % N)};
-    const int64_t st[3] = {(int64_t)N * N, N, 1};
-    if (id[m] == 0) {
-      r[i] = 0.0;
-      continue;
-    }
-    const double c = u[i];
-    double lap = 0;
-    for (int d = 0; d < 3; ++d) {
-      double lo, hi;
-      if (d == m) {
-        lo = u[i - st[d]];                               // face a-1 (face 0 holds zero)
-        hi = (id[d] + 1 < N) ? u[i + st[d]] : 0.0;       // face N is the box face
-      } else {
-        lo = (id[d] > 0) ? u[i - st[d]] : -c;            // ghost reflection
-        hi = (id[d] + 1 < N) ? u[i + st[d]] : -c;
-      }
-      lap += (lo - 2.0 * c + hi) * ih2;
-    }
-    const double gp = (p[i] - p[i - st[m]]) * ih;        // cells a-1, a
-    r[i] = F[i] - (-mu * lap + gp);
-  }
-}
 
-__global__ void k_res_p(int N, double h, double cc, const double* __restrict__ u, const double* __restrict__ p,
-                        const double* __restrict__ F, double* __restrict__ r) {
-  const int64_t M = (int64_t)N * N * N;
-  const double ih = 1.0 / h;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (int64_t)gridDim.x * blockDim.x) {
-    const int id[3] = {(int)(i / ((int64_t)N * N)), (int)((i / N) % N), (int)(i % N)};
-    const int64_t st[3] = {(int64_t)N * N, N, 1};
-    double div = 0;
-    for (int m = 0; m < 3; ++m) {
-      const double* um = u + (int64_t)m * M;
-      const double hi = (id[m] + 1 < N) ? um[i + st[m]] : 0.0;
-      div += (hi - um[i]) * ih;
-    }
-    r[i] = F[i] - (div + cc * p[i]);
-  }
-}
 
 // ---------------------------------------------------------------------------------------
 // mixed-precision refinement (float64 residual of the full MAC system, float32 correction)
@@ -1085,29 +1065,6 @@ hipError_t launch_pass(int N, int kind, int axis, const T* in, T* out, bool accu
   return hipErrorInvalidValue;
 }
 
-template <typename T>
-hipError_t launch_zscale_inv(int N, int m, int wkind, const T* in, T* out, double mu, const DevTables<T>& tb,
-                             hipStream_t s) {
-  (void)wkind;
-  const Tab<T> t = tab_of(tb);
-#define KFBI_M(NN)                                                                                          \
-  {                                                                                                         \
-    using S = TileCfg<T, NN, DCT3>;                                                                         \
-    const int blocks = NN * NN / S::W;                                                                      \
-    const size_t lds = S::BYTES;                                                                            \
-    ensure_lds(k_zscale_inv<T, NN, DCT3>, lds);                                                             \
-    ensure_lds(k_zscale_inv<T, NN, DST3>, lds);                                                             \
-    if (m == 2)                                                                                             \
-      hipLaunchKernelGGL((k_zscale_inv<T, NN, DCT3>), dim3(blocks), dim3(S::NT), lds, s, in, out, m, mu, tb.sig, \
-                         tb.sig2s, t);                                                                      \
-    else                                                                                                    \
-      hipLaunchKernelGGL((k_zscale_inv<T, NN, DST3>), dim3(blocks), dim3(S::NT), lds, s, in, out, m, mu, tb.sig, \
-                         tb.sig2s, t);                                                                      \
-  }
-  KFBI_DISPATCH_N(N, KFBI_M)
-#undef KFBI_M
-  return hipGetLastError();
-}
 
 template <typename T>
 hipError_t launch_xmid(int N, T* A0, T* A1, T* A2, double mu, const DevTables<T>& tb, hipStream_t s) {
@@ -1134,8 +1091,13 @@ hipError_t launch_zfwd_cg(int N, const T* r, T* d, T* A, T* B, const double* sca
     using S = TileCfg<T, NN, DST2>;                                                                  \
     const int blocks = NN * NN / S::W;                                                               \
     const size_t lds = S::BYTES;                                                                     \
-    ensure_lds(k_zfwd_cg<T, NN>, lds);                                                               \
-    hipLaunchKernelGGL((k_zfwd_cg<T, NN>), dim3(blocks), dim3(S::NT), lds, s, r, d, A, B, scal, t);  \
+    if (d) {                                                                                         \
+      ensure_lds(k_zfwd_cg<T, NN, true>, lds);                                                       \
+      hipLaunchKernelGGL((k_zfwd_cg<T, NN, true>), dim3(blocks), dim3(S::NT), lds, s, r, d, A, B, scal, t); \
+    } else {                                                                                         \
+      ensure_lds(k_zfwd_cg<T, NN, false>, lds);                                                      \
+      hipLaunchKernelGGL((k_zfwd_cg<T, NN, false>), dim3(blocks), dim3(S::NT), lds, s, r, d, A, B, scal, t); \
+    }                                                                                                \
   }
   KFBI_DISPATCH_N(N, KFBI_M)
 #undef KFBI_M
@@ -1159,6 +1121,34 @@ hipError_t launch_zinv_cg(int N, const T* A, const T* B, T* q, const T* d, doubl
   KFBI_DISPATCH_N(N, KFBI_M)
 #undef KFBI_M
   return hipGetLastError();
+}
+
+template <typename T, int N, int KF, int KI, bool BS>
+static hipError_t xfuse_n(int m, const T* in, T* fh, T* out, double mu, const DevTables<T>& tb, hipStream_t s) {
+  using SF = TileCfg<T, N, KF>;
+  using SI = TileCfg<T, N, KI>;
+  const size_t lds = SF::BYTES > SI::BYTES ? SF::BYTES : SI::BYTES;
+  const int nt = SF::NT > SI::NT ? SF::NT : SI::NT;
+  const int blocks = N * N / SF::W;
+  ensure_lds(k_xfuse<T, N, KF, KI, BS>, lds);
+  hipLaunchKernelGGL((k_xfuse<T, N, KF, KI, BS>), dim3(blocks), dim3(nt), lds, s, in, fh, out, m, mu, tb.sig,
+                     tb.sig2s, tab_of(tb));
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_xfuse(int N, int m, bool backsub, const T* in, T* fh, T* out, double mu, const DevTables<T>& tb,
+                        hipStream_t s) {
+  if (m < 0 || m > 2) return hipErrorInvalidValue;
+#define KFBI_M(NN)                                                                            \
+  if (backsub)                                                                                \
+    return m == 0 ? xfuse_n<T, NN, DCT2, DST1, true>(m, in, fh, out, mu, tb, s)               \
+                  : xfuse_n<T, NN, DST2, DST3, true>(m, in, fh, out, mu, tb, s);              \
+  return m == 0 ? xfuse_n<T, NN, DST1, DCT3, false>(m, in, fh, out, mu, tb, s)                \
+                : xfuse_n<T, NN, DST2, DST3, false>(m, in, fh, out, mu, tb, s);
+  KFBI_DISPATCH_N(N, KFBI_M)
+#undef KFBI_M
+  return hipErrorInvalidValue;
 }
 
 template <typename T>
@@ -1190,16 +1180,6 @@ hipError_t launch_cg_update(int64_t M, T* x, T* r, const T* d, const T* q, const
   return hipGetLastError();
 }
 
-template <typename T>
-hipError_t launch_backsub_combine(int N, int m, const T* F, const T* P, T* G, double mu, const DevTables<T>& tb,
-                                  hipStream_t s) {
-#define KFBI_M(NN)                                                                                           \
-  hipLaunchKernelGGL((k_backsub_combine<T, NN>), dim3(ew_blocks((int64_t)NN * NN * NN)), dim3(256), 0, s, m, F, P, \
-                     G, mu, tb.sig, tb.sig2s);
-  KFBI_DISPATCH_N(N, KFBI_M)
-#undef KFBI_M
-  return hipGetLastError();
-}
 
 hipError_t launch_reduce(const double* partials, int nparts, int nper, double* scal, int op, int stokes, int64_t M,
                          hipStream_t s, double* out) {
@@ -1232,35 +1212,7 @@ hipError_t launch_axpby(int64_t n, T* y, double a, const T* x, double b, hipStre
   hipLaunchKernelGGL((k_axpby<T>), dim3(ew_blocks(n)), dim3(256), 0, s, n, y, a, x, b);
   return hipGetLastError();
 }
-template <typename TO, typename TI>
-hipError_t launch_convert(int64_t n, TO* out, const TI* in, hipStream_t s) {
-  hipLaunchKernelGGL((k_convert<TO, TI>), dim3(ew_blocks(n)), dim3(256), 0, s, n, out, in);
-  return hipGetLastError();
-}
-template <typename TI>
-hipError_t launch_add_into_f64(int64_t n, double* out, const TI* in, hipStream_t s) {
-  hipLaunchKernelGGL((k_add_into_f64<TI>), dim3(ew_blocks(n)), dim3(256), 0, s, n, out, in);
-  return hipGetLastError();
-}
-hipError_t launch_rhs_minus(int64_t M, double* b, const double* Fp, hipStream_t s) {
-  hipLaunchKernelGGL((k_rhs_minus<double>), dim3(ew_blocks(M)), dim3(256), 0, s, M, b, Fp);
-  return hipGetLastError();
-}
-template <typename T>
-hipError_t launch_rhs_minus_t(int64_t M, T* b, const T* Fp, hipStream_t s) {
-  hipLaunchKernelGGL((k_rhs_minus<T>), dim3(ew_blocks(M)), dim3(256), 0, s, M, b, Fp);
-  return hipGetLastError();
-}
 
-hipError_t launch_mac_residual(int N, double h, double mu, double c, const double* u, const double* p,
-                               const double* Fu, const double* Fp, double* ru, double* rp, hipStream_t s) {
-  const int64_t M = (int64_t)N * N * N;
-  for (int m = 0; m < 3; ++m)
-    hipLaunchKernelGGL(k_res_u, dim3(ew_blocks(M)), dim3(256), 0, s, N, m, h, mu, u + m * M, p, Fu + m * M,
-                       ru + m * M);
-  hipLaunchKernelGGL(k_res_p, dim3(ew_blocks(M)), dim3(256), 0, s, N, h, c, u, p, Fp, rp);
-  return hipGetLastError();
-}
 
 hipError_t launch_refine_prep(int64_t M, const double* F, float* r32, double* partials, int nparts, hipStream_t s) {
   hipLaunchKernelGGL(k_refine_prep, dim3(nparts), dim3(EW_NT), 0, s, M, F, r32, partials);
@@ -1358,27 +1310,20 @@ hipError_t launch_check_finite(int64_t n, const double* a, int* flag, hipStream_
 // explicit instantiations
 #define KFBI_INST(T)                                                                                                 \
   template hipError_t launch_pass<T>(int, int, int, const T*, T*, bool, const DevTables<T>&, hipStream_t);           \
-  template hipError_t launch_zscale_inv<T>(int, int, int, const T*, T*, double, const DevTables<T>&, hipStream_t);   \
   template hipError_t launch_xmid<T>(int, T*, T*, T*, double, const DevTables<T>&, hipStream_t);                     \
   template hipError_t launch_zfwd_cg<T>(int, const T*, T*, T*, T*, const double*, const DevTables<T>&, hipStream_t); \
   template hipError_t launch_ypair<T>(int, bool, const T*, const T*, T*, T*, const DevTables<T>&, hipStream_t);      \
+  template hipError_t launch_xfuse<T>(int, int, bool, const T*, T*, T*, double, const DevTables<T>&, hipStream_t);   \
   template hipError_t launch_zinv_cg<T>(int, const T*, const T*, T*, const T*, double, double*, const DevTables<T>&, \
                                         hipStream_t);                                                                \
   template hipError_t launch_cg_update<T>(int64_t, T*, T*, const T*, const T*, const double*, double*, int,          \
                                           hipStream_t);                                                              \
-  template hipError_t launch_backsub_combine<T>(int, int, const T*, const T*, T*, double, const DevTables<T>&,       \
-                                                hipStream_t);                                                        \
   template hipError_t launch_dot_partials<T>(int64_t, const T*, const T*, double*, int, hipStream_t);                \
   template hipError_t launch_sum_partials<T>(int64_t, const T*, double*, int, hipStream_t);                          \
   template hipError_t launch_add_scalar<T>(int64_t, T*, const double*, int, double, hipStream_t);                    \
   template hipError_t launch_fill<T>(int64_t, T*, T, hipStream_t);                                                   \
-  template hipError_t launch_axpby<T>(int64_t, T*, double, const T*, double, hipStream_t);                           \
-  template hipError_t launch_rhs_minus_t<T>(int64_t, T*, const T*, hipStream_t);                                     \
-  template hipError_t launch_add_into_f64<T>(int64_t, double*, const T*, hipStream_t);
+  template hipError_t launch_axpby<T>(int64_t, T*, double, const T*, double, hipStream_t);
 KFBI_INST(float)
 KFBI_INST(double)
-template hipError_t launch_convert<float, double>(int64_t, float*, const double*, hipStream_t);
-template hipError_t launch_convert<double, float>(int64_t, double*, const float*, hipStream_t);
-template hipError_t launch_convert<double, double>(int64_t, double*, const double*, hipStream_t);
 
 }  // namespace kfbi

@@ -203,7 +203,8 @@ __device__ __forceinline__ C2<T> pre_sample(const Src& src, const Tab<T>& tb, in
 
 // Complex FFTs of the W/2 jobs of the tile; on return the spectra are in LDS at
 // cb[j * ZS + k] (natural order, length L).  LDS may alias the source (pass-1 samples are
-// staged in registers).  Every thread of the block (Cfg::NT) must call it.
+// staged in registers).  Every thread of the block must call it; a block may have more
+// threads than Cfg::NT (the extra ones only take part in the barriers).
 template <typename T, int N, int KIND, int WQ = 0, class Sampler>
 __device__ void fft_core(T* lds, Sampler&& sample, const Tab<T>& tb);
 
@@ -229,7 +230,7 @@ __device__ void fft_core(T* lds, Sampler&& sample, const Tab<T>& tb) {
 #pragma unroll
     for (int u = 0; u < PT; ++u) {
       const int task = tid + u * NT;
-      if (TASKS % NT == 0 || task < TASKS) {
+      if ((TASKS % NT == 0 || task < TASKS) && tid < NT) {
         const int j = task % NJ, n2 = task / NJ;
 #pragma unroll
         for (int n1 = 0; n1 < R1; ++n1) z[u][n1] = sample(j, R2 * n1 + n2);
@@ -246,7 +247,7 @@ __device__ void fft_core(T* lds, Sampler&& sample, const Tab<T>& tb) {
 #pragma unroll
     for (int u = 0; u < PT; ++u) {
       const int task = tid + u * NT;
-      if (TASKS % NT == 0 || task < TASKS) {
+      if ((TASKS % NT == 0 || task < TASKS) && tid < NT) {
         const int j = task % NJ, n2 = task / NJ;
 #pragma unroll
         for (int k1 = 0; k1 < R1; ++k1) cb[j * YS + k1 * P2 + n2] = z[u][k1];
@@ -262,7 +263,7 @@ __device__ void fft_core(T* lds, Sampler&& sample, const Tab<T>& tb) {
 #pragma unroll
     for (int u = 0; u < PT; ++u) {
       const int task = tid + u * NT;
-      if (TASKS % NT == 0 || task < TASKS) {
+      if ((TASKS % NT == 0 || task < TASKS) && tid < NT) {
         const int j = task % NJ, k1 = task / NJ;
 #pragma unroll
         for (int n2 = 0; n2 < R2; ++n2) z[u][n2] = cb[j * YS + k1 * P2 + n2];
@@ -273,41 +274,13 @@ __device__ void fft_core(T* lds, Sampler&& sample, const Tab<T>& tb) {
 #pragma unroll
     for (int u = 0; u < PT; ++u) {
       const int task = tid + u * NT;
-      if (TASKS % NT == 0 || task < TASKS) {
+      if ((TASKS % NT == 0 || task < TASKS) && tid < NT) {
         const int j = task % NJ, k1 = task / NJ;
 #pragma unroll
         for (int k2 = 0; k2 < R2; ++k2) cb[j * ZS + k1 + R1 * k2] = z[u][k2];
       }
     }
     __syncthreads();
-  }
-}
-
-// Post-processing value of output element (p, k) from the spectra in LDS.
-template <typename T, int N, int KIND>
-__device__ __forceinline__ T post_value(const T* lds, const Tab<T>& tb, int p, int k) {
-  constexpr int ZS = TileCfg<T, N, KIND>::ZS;
-  const C2<T>* Z = reinterpret_cast<const C2<T>*>(lds) + (p >> 1) * ZS;
-  const int which = p & 1;
-  if constexpr (KIND == DCT2 || KIND == DST2) {
-    const int kk = (KIND == DST2) ? N - 1 - k : k;
-    const C2<T> a = Z[kk], b = Z[(N - kk) & (N - 1)];
-    C2<T> V;
-    if (which == 0)
-      V = {(a.x + b.x) * T(0.5), (a.y - b.y) * T(0.5)};
-    else
-      V = {(a.y + b.y) * T(0.5), (b.x - a.x) * T(0.5)};
-    const C2<T> m = tb.mk[kk];
-    return tb.sc[kk] * (m.x * V.x - m.y * V.y);
-  } else if constexpr (KIND == DCT3 || KIND == DST3) {
-    const C2<T> z = Z[perm_dst(k, N)];
-    T val = (which ? z.y : z.x) * (T(1) / T(N));
-    if (KIND == DST3 && (k & 1)) val = -val;
-    return val;
-  } else {
-    const C2<T> z = Z[k];
-    const T y = which ? z.x * T(0.5) : -z.y * T(0.5);
-    return (k == 0) ? T(0) : y * tb.sc[1];  // sqrt(2/N)
   }
 }
 
@@ -360,51 +333,19 @@ struct OutItems {
     const int e = threadIdx.x + u * NT;
     j = e / NKV;
     k0 = (e - j * NKV) * VEC;
-    return COUNT_Z % NT == 0 || e < COUNT_Z;
+    return (COUNT_Z % NT == 0 || e < COUNT_Z) && (int)threadIdx.x < NT;
   }
   __device__ static bool xy(int u, int& j, int& k) {
     const int e = threadIdx.x + u * NT;
     k = e / NJ;
     j = e - k * NJ;
-    return COUNT_XY % NT == 0 || e < COUNT_XY;
+    return (COUNT_XY % NT == 0 || e < COUNT_XY) && (int)threadIdx.x < NT;
   }
   __device__ static void z_values(const T* lds, const Tab<T>& tb, int j, int k0, V16<T>& a, V16<T>& b) {
 #pragma unroll
     for (int q = 0; q < VEC; ++q) post_pair<T, N, KIND>(lds, tb, j, k0 + q, a.a[q], b.a[q]);
   }
 };
-
-// Transform from the source and hand the outputs to the stores in the coalescing order of
-// the axis: axis 2: store_z(p, k0, V16 values of k0..k0+VEC-1) for rows p = 2j, 2j+1;
-// axes 0, 1: store_xy(j, k, v0, v1) for pencils 2j, 2j+1 (the stores must not write LDS).
-template <typename T, int N, int KIND, class Src, class StoreZ, class StoreXY>
-__device__ __forceinline__ void transform_store(T* lds, const Src& src, const Tab<T>& tb, int axis, StoreZ&& store_z,
-                                                StoreXY&& store_xy) {
-  using O = OutItems<T, N, KIND>;
-  fft_tile<T, N, KIND>(lds, src, tb);
-  if (axis == 2) {
-#pragma unroll
-    for (int u = 0; u < O::PER_Z; ++u) {
-      int j, k0;
-      if (O::z(u, j, k0)) {
-        V16<T> a, b;
-        O::z_values(lds, tb, j, k0, a, b);
-        store_z(2 * j, k0, a);
-        store_z(2 * j + 1, k0, b);
-      }
-    }
-  } else {
-#pragma unroll 4
-    for (int u = 0; u < O::PER_XY; ++u) {
-      int j, k;
-      if (O::xy(u, j, k)) {
-        T v0, v1;
-        post_pair<T, N, KIND>(lds, tb, j, k, v0, v1);
-        store_xy(j, k, v0, v1);
-      }
-    }
-  }
-}
 
 // Tile addressing.  Field layout [x][y][z], z contiguous, N^3 elements.
 //  axis 2: tile = W consecutive z-pencils (pencil q = blk*W + p, (x, y) = (q / N, q % N))
