@@ -416,7 +416,12 @@ kfbi_status kfbi_create(const kfbi_config* cfg_in, kfbi_ctx** out) {
     C->nb_ptr = dupload(S.nb_ptr, o, s);
     C->nb_idx = dupload(S.nb_idx, o, s);
     C->fitw = dupload(S.fitw, o, s);
-    C->jmap = dupload(S.jmap, o, s);
+    {  // component-major on the device: consecutive crossings are adjacent for every (r, c)
+      std::vector<double> jt(S.jmap.size());
+      for (int64_t t = 0; t < S.T; ++t)
+        for (int rc = 0; rc < 90; ++rc) jt[(int64_t)rc * S.T + t] = S.jmap[t * 90 + rc];
+      C->jmap = dupload(jt, o, s);
+    }
     C->jfmap = dupload(S.jfmap, o, s);
     std::vector<double> em(S.emap.begin(), S.emap.begin() + S.n * 54);
     std::vector<double> efm(S.emap.begin() + S.n * 54, S.emap.end());
@@ -450,7 +455,7 @@ kfbi_status kfbi_create(const kfbi_config* cfg_in, kfbi_ctx** out) {
     C->svT_row = dupload(S.svT_row, o, s);
     C->svT_w = dupload(S.svT_w, o, s);
     C->jumps = dalloc<double>(5 * S.T, o);
-    C->fitvals = dalloc<double>(18 * S.T, o);
+    C->fitvals = dalloc<double>(18 * S.n, o);
     C->ejump = dalloc<double>(3 * S.n, o);
     C->jbar = dalloc<double>(5 * S.T, o);
     C->fitbar = dalloc<double>(18 * S.T, o);
@@ -466,7 +471,7 @@ kfbi_status kfbi_create(const kfbi_config* cfg_in, kfbi_ctx** out) {
       C->r32 = dalloc<float>(4 * S.M, o);
       C->x32 = dalloc<float>(4 * S.M, o);
       C->rscal = dalloc<double>(16, o);
-      C->rpart = dalloc<double>(4096, o);
+      C->rpart = dalloc<double>(3 * 2048, o);
     } else {
       C->s64.init(S.N, S.h, S.pde, S.mu, c, s, o);
     }
@@ -533,7 +538,8 @@ void assemble_rhs(kfbi_ctx* C, const double* phi, bool vol) {
   const Setup& S = C->S;
   hipStream_t s = C->s;
   const double* Fj = (vol && C->Fj) ? C->Fj : nullptr;
-  HIPCHK(launch_fit_jump(S.T, C->nb_ptr, C->nb_idx, C->fitw, C->jmap, C->jfmap, Fj, phi, C->jumps, C->fitvals, s));
+  HIPCHK(launch_fit_jump(S.T, C->nb_ptr, C->nb_idx, C->fitw, C->jmap, C->jfmap, Fj, phi, C->cp_of, C->jumps,
+                         C->fitvals, s));
   HIPCHK(launch_interp_jump(S.n, C->cp_target, C->fitvals, C->emap, C->efmap, Fj, C->ejump, s));
   HIPCHK(launch_fill<double>(4 * S.M, C->F, 0.0, s));
   HIPCHK(launch_correct((int64_t)S.irr_node.size(), C->irr_node, C->irr_ptr, C->arm_t, C->arm_o, C->arm_a, C->jumps,
@@ -561,7 +567,7 @@ int mac_solve(kfbi_ctx* C, const double* F, double* u, double* p, kfbi_info* inf
   // modulo constants, which the inner solve projects out).
   const bool stokes = S.pde == KFBI_STOKES;
   const double c = stokes ? 0.0 : 1.0 / (S.lam + S.mu);
-  constexpr int NP = 1024;  // blocks of the fused passes (3 partial sums each)
+  constexpr int NP = 2048;  // blocks of the fused passes (3 partial sums each; 8 per CU)
   auto norm = [&](int op) {
     HIPCHK(launch_reduce(C->rpart, NP, 3, C->rscal, op, stokes, M, s));
     double h2 = 0;
@@ -730,7 +736,7 @@ int gmres(kfbi_ctx* C, const double* rhs, double* phi, double tol, int maxit, do
     C->H = dalloc<double>((size_t)(maxit + 2) * (maxit + 1) + 16, C->owned);
     C->gm_max = maxit;
   }
-  if (!C->rpart) C->rpart = dalloc<double>(4096, C->owned);
+  if (!C->rpart) C->rpart = dalloc<double>(3 * 2048, C->owned);
   if (!C->rscal) C->rscal = dalloc<double>(16, C->owned);
   const int LD = maxit + 2;  // column stride of H
   double* scratch = C->rscal;  // scratch[5] = norm^2

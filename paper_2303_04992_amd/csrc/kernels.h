@@ -87,9 +87,11 @@ hipError_t launch_refine_residual(bool first, int N, double h, double mu, double
                                   float* r32, double* partials, int nparts, hipStream_t s);
 
 // ---- surface stages (float64)
+// jumps of every crossing (jmap component-major: jmap[(r * 18 + c) * T + t]) and the fit
+// values of the control points (fitvals[18 cp + c])
 hipError_t launch_fit_jump(int64_t T, const int64_t* nb_ptr, const int32_t* nb_idx, const double* fitw,
                            const double* jmap, const double* jfmap, const double* Fj, const double* phi,
-                           double* jumps, double* fitvals, hipStream_t s);
+                           const int64_t* cp_of, double* jumps, double* fitvals, hipStream_t s);
 hipError_t launch_interp_jump(int64_t n, const int64_t* cp_target, const double* fitvals, const double* emap,
                               const double* efmap, const double* Fj, double* ejump, hipStream_t s);
 hipError_t launch_correct(int64_t nirr, const int64_t* irr_node, const int64_t* irr_ptr, const int32_t* arm_t,

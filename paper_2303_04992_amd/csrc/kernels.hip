@@ -792,10 +792,14 @@ __global__ __launch_bounds__(EW_NT) void k_refine_residual(int N, double h, doub
 // ---------------------------------------------------------------------------------------
 // surface stages (float64)
 // ---------------------------------------------------------------------------------------
+// jmap is stored component-major on the device, jmap[(r * 18 + c) * T + t], so that the
+// threads of a wavefront (consecutive crossings t) read consecutive addresses; fit values are
+// kept only for the control points (fitvals[18 cp + c]), which the interpolation jump needs.
 __global__ void k_fit_jump(int64_t T, const int64_t* __restrict__ nb_ptr, const int32_t* __restrict__ nb_idx,
                            const double* __restrict__ fitw, const double* __restrict__ jmap,
                            const double* __restrict__ jfmap, const double* __restrict__ Fj,
-                           const double* __restrict__ phi, double* __restrict__ jumps, double* __restrict__ fitvals) {
+                           const double* __restrict__ phi, const int64_t* __restrict__ cp_of,
+                           double* __restrict__ jumps, double* __restrict__ fitvals) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= T) return;
   double fv[18];
@@ -812,13 +816,15 @@ __global__ void k_fit_jump(int64_t T, const int64_t* __restrict__ nb_ptr, const 
       fv[3 * q + 2] += w * p2;
     }
   }
+  const int64_t cp = cp_of[t];
+  if (cp >= 0) {
 #pragma unroll
-  for (int c = 0; c < 18; ++c) fitvals[18 * t + c] = fv[c];
+    for (int c = 0; c < 18; ++c) fitvals[18 * cp + c] = fv[c];
+  }
   for (int r = 0; r < 5; ++r) {
-    const double* Jr = jmap + (t * 5 + r) * 18;
     double s = 0;
 #pragma unroll
-    for (int c = 0; c < 18; ++c) s += Jr[c] * fv[c];
+    for (int c = 0; c < 18; ++c) s += jmap[(r * 18 + c) * T + t] * fv[c];
     if (Fj) {
       const double* Fr = jfmap + (t * 5 + r) * 3;
       s += Fr[0] * Fj[3 * t] + Fr[1] * Fj[3 * t + 1] + Fr[2] * Fj[3 * t + 2];
@@ -835,7 +841,7 @@ __global__ void k_interp_jump(int64_t n, const int64_t* __restrict__ cp_target, 
   const int64_t c = r / 3;
   const int64_t t = cp_target[c];
   double s = 0;
-  for (int q = 0; q < 18; ++q) s += emap[18 * r + q] * fitvals[18 * t + q];
+  for (int q = 0; q < 18; ++q) s += emap[18 * r + q] * fitvals[18 * c + q];
   if (Fj)
     for (int i = 0; i < 3; ++i) s += efmap[3 * r + i] * Fj[3 * t + i];
   ejump[r] = s;
@@ -935,7 +941,7 @@ __global__ void k_jump_T(int64_t T, const int64_t* __restrict__ cp_of, const dou
   const int64_t cp = cp_of[t];
   for (int c = 0; c < 18; ++c) {
     double s = 0;
-    for (int r = 0; r < 5; ++r) s += jmap[(t * 5 + r) * 18 + c] * jbar[5 * t + r];
+    for (int r = 0; r < 5; ++r) s += jmap[(r * 18 + c) * T + t] * jbar[5 * t + r];
     if (cp >= 0 && wbar)
       for (int m = 0; m < 3; ++m) s += emap[(cp * 3 + m) * 18 + c] * wbar[3 * cp + m];
     fitbar[18 * t + c] = s;
@@ -1235,9 +1241,9 @@ static inline int gb(int64_t n) { return (int)((n + 255) / 256 > 0 ? (n + 255) /
 
 hipError_t launch_fit_jump(int64_t T, const int64_t* nb_ptr, const int32_t* nb_idx, const double* fitw,
                            const double* jmap, const double* jfmap, const double* Fj, const double* phi,
-                           double* jumps, double* fitvals, hipStream_t s) {
-  hipLaunchKernelGGL(k_fit_jump, dim3(gb(T)), dim3(256), 0, s, T, nb_ptr, nb_idx, fitw, jmap, jfmap, Fj, phi, jumps,
-                     fitvals);
+                           const int64_t* cp_of, double* jumps, double* fitvals, hipStream_t s) {
+  hipLaunchKernelGGL(k_fit_jump, dim3(gb(T)), dim3(256), 0, s, T, nb_ptr, nb_idx, fitw, jmap, jfmap, Fj, phi, cp_of,
+                     jumps, fitvals);
   return hipGetLastError();
 }
 hipError_t launch_interp_jump(int64_t n, const int64_t* cp_target, const double* fitvals, const double* emap,

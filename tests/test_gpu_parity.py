@@ -185,3 +185,27 @@ def test_512_navier_matches_stored_oracle_sample(K):
     r = _rel(kt, z["KTw"])
     _say(f"   K^T w: rel l2 over the sample {r:.3e}  info {op.last_info}")
     assert r < 1e-6
+    del op
+    # the float64 path at the largest supported size, to its own 1e-10
+    op = K.Operator(cfg, K.FP64, cg_rtol=1e-12, trace=meta.get("form", "interior"))
+    kg = op.eval(phi).cpu().numpy()[idx]
+    r = _rel(kg, z["Kphi"])
+    _say(f"   K phi float64: rel l2 over the sample {r:.3e}  info {op.last_info}")
+    assert r < 1e-10
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+@pytest.mark.parametrize("trace", ["average", "interior"])
+def test_degenerate_inputs(K, prec, trace):
+    """Zero density, zero cotangent and zero Dirichlet data give exact zeros (the mixed
+    refinement and GMRES take their zero-norm exits), on a ragged control-point count."""
+    import torch
+    cfg = KI.WORKLOADS["ellip128"].with_N(32)
+    op = K.Operator(cfg, prec, trace=trace)
+    z = torch.zeros((op.n, 3), dtype=torch.float64, device="cuda")
+    assert op.n % 256 != 0
+    assert torch.count_nonzero(op.eval(z)).item() == 0
+    assert torch.count_nonzero(op.eval_adjoint(z)).item() == 0
+    phi, u, p = op.solve_bvp(z)
+    assert torch.count_nonzero(phi).item() == 0 and op.last_info["gmres_iters"] == 0
+    assert torch.count_nonzero(u).item() == 0
