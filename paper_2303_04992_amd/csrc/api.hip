@@ -567,7 +567,7 @@ int mac_solve(kfbi_ctx* C, const double* F, double* u, double* p, kfbi_info* inf
   // modulo constants, which the inner solve projects out).
   const bool stokes = S.pde == KFBI_STOKES;
   const double c = stokes ? 0.0 : 1.0 / (S.lam + S.mu);
-  constexpr int NP = 2048;  // blocks of the fused passes (3 partial sums each; 8 per CU)
+  constexpr int NP = 1024;  // blocks of the fused passes (3 partial sums each; 2048 measured slower)
   auto norm = [&](int op) {
     HIPCHK(launch_reduce(C->rpart, NP, 3, C->rscal, op, stokes, M, s));
     double h2 = 0;
