@@ -34,18 +34,19 @@ KIND_NAMES = {DCT2: "k_pass DCT2", DST2: "k_pass DST2", DCT3: "k_pass DCT3", DST
 
 
 def cpu_baseline(cfg, n_cg):
-    """The oracle as it stands, on the host cores, on a bounded sample: two Schur-complement
+    """The oracle as it stands, on the host cores, on a bounded sample: Schur-complement
     applications (each three sine-transform Poisson solves plus the MAC gradient and
-    divergence) at the full 256^3 size; one K phi costs about (n_cg + 2) of them (right-hand
-    side and velocity back-substitution add the equivalent of two), the surface stages are
-    below 1%."""
+    divergence) at the full 256^3 size, as many as fit in about 10 s (2 to 40); one K phi
+    costs about (n_cg + 2) of them (right-hand side and velocity back-substitution add the
+    equivalent of two), the surface stages are below 1%."""
     from oracle.mac import MAC
     workers = os.cpu_count()
     mac = MAC(cfg.N, cfg.lo, cfg.hi, cfg.pde, cfg.mu, cfg.lam, workers=workers)
     p = np.random.default_rng(0).standard_normal((cfg.N,) * 3)
-    mac.schur(p)  # warm-up
     t0 = time.perf_counter()
-    reps = 2
+    mac.schur(p)  # warm-up, also sizes the sample to about 10 s of host work
+    reps = int(min(40, max(2, 10.0 / max(time.perf_counter() - t0, 1e-3))))
+    t0 = time.perf_counter()
     for _ in range(reps):
         mac.schur(p)
     t = (time.perf_counter() - t0) / reps
