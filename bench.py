@@ -98,6 +98,49 @@ def run_form(K, KI, cfg, prec, rtol, inner, steps, warmup, ref, prof=None):
     return res
 
 
+def all_configs(K, KI, say):
+    """Timings of every configuration (not part of the one-line result): K phi and K^T w in
+    float64 and mixed form, and the Dirichlet BVP (volume trace, GMRES, unified solve)."""
+    import torch
+    rows = []
+    for name, N, bvp in (("sphere32", 32, True), ("star128", 128, True), ("ellip128", 128, True),
+                         ("star256", 256, True), ("star512n", 512, True)):
+        cfg = KI.WORKLOADS[name].with_N(N)
+        for prec, pname, rt in ((K.FP64, "fp64", 1e-12), (K.MIXED_FP32, "mixed", 1e-9)):
+            t0 = time.perf_counter()
+            op = K.Operator(cfg, prec, cg_rtol=rt, gmres_rtol=1e-8)
+            setup = time.perf_counter() - t0
+            xyz, _ = op.points()
+            g = torch.as_tensor(KI.exact_u(cfg.solution, xyz[:, 0], xyz[:, 1], xyz[:, 2]), device="cuda")
+            op.eval(g)
+            reps = 5 if N >= 512 else 20
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                op.eval(g)
+            torch.cuda.synchronize()
+            te = (time.perf_counter() - t0) / reps
+            t0 = time.perf_counter()
+            for _ in range(reps):
+                op.eval_adjoint(g)
+            torch.cuda.synchronize()
+            ta = (time.perf_counter() - t0) / reps
+            row = {"config": name, "N": N, "form": pname, "setup_s": round(setup, 2), "eval_ms": round(te * 1e3, 2),
+                   "adjoint_ms": round(ta * 1e3, 2)}
+            if bvp:
+                f = lambda x, y, z, c=cfg: KI.body_force(c.solution, x, y, z, c.mu, c.lam)
+                torch.cuda.synchronize()
+                t0 = time.perf_counter()
+                op.solve_bvp(g, f)
+                torch.cuda.synchronize()
+                row.update({"bvp_s": round(time.perf_counter() - t0, 3), "gmres_iters": op.last_info["gmres_iters"]})
+            say(json.dumps(row))
+            rows.append(row)
+            del op
+            torch.cuda.empty_cache()
+    return rows
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -109,6 +152,7 @@ def main():
     ap.add_argument("--refine-rtol", type=float, default=1e-5, help="mixed: float64 residual tolerance")
     ap.add_argument("--inner-rtol", type=float, default=1e-5, help="mixed: float32 inner CG tolerance")
     ap.add_argument("--fp64-equal-rtol", type=float, default=1e-6, help="float64 CG tolerance at equal accuracy")
+    ap.add_argument("--all-configs", action="store_true", help="time every configuration instead (one line each)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only (there is no multi-GPU path; the sharding design is "
@@ -118,6 +162,9 @@ def main():
     import kfbi_inputs as KI
     import paper_2303_04992_amd as K
 
+    if args.all_configs:
+        all_configs(K, KI, lambda m: print(m, flush=True))
+        return
     cfg = KI.WORKLOADS[args.workload]
     ref_path = os.path.join(ROOT, "tests", "golden", f"{args.workload}_Kphi_uexact.npy")
     meta_path = ref_path.replace(".npy", ".json")

@@ -792,44 +792,55 @@ __global__ __launch_bounds__(EW_NT) void k_refine_residual(int N, double h, doub
 // ---------------------------------------------------------------------------------------
 // surface stages (float64)
 // ---------------------------------------------------------------------------------------
-// jmap is stored component-major on the device, jmap[(r * 18 + c) * T + t], so that the
-// threads of a wavefront (consecutive crossings t) read consecutive addresses; fit values are
-// kept only for the control points (fitvals[18 cp + c]), which the interpolation jump needs.
-__global__ void k_fit_jump(int64_t T, const int64_t* __restrict__ nb_ptr, const int32_t* __restrict__ nb_idx,
-                           const double* __restrict__ fitw, const double* __restrict__ jmap,
-                           const double* __restrict__ jfmap, const double* __restrict__ Fj,
-                           const double* __restrict__ phi, const int64_t* __restrict__ cp_of,
-                           double* __restrict__ jumps, double* __restrict__ fitvals) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= T) return;
-  double fv[18];
-#pragma unroll
-  for (int c = 0; c < 18; ++c) fv[c] = 0.0;
-  for (int64_t e = nb_ptr[t]; e < nb_ptr[t + 1]; ++e) {
-    const int64_t cp = nb_idx[e];
-    const double p0 = phi[3 * cp], p1 = phi[3 * cp + 1], p2 = phi[3 * cp + 2];
-#pragma unroll
-    for (int q = 0; q < 6; ++q) {
+// Eight lanes per crossing t (lane q < 6 owns fit quantity q: value, two first and three second
+// tangential derivatives, for the three components), so that the fit weights of one
+// neighbour entry (6 doubles) are read as one contiguous segment; the 5 jumps of the crossing
+// are then reduced over the lanes of the group.  jmap is component-major on the device,
+// jmap[(r * 18 + c) * T + t]; fit values are kept only for the control points
+// (fitvals[18 cp + c]), which the interpolation jump needs.
+constexpr int FJ_LANES = 8;
+__global__ __launch_bounds__(256) void k_fit_jump(int64_t T, const int64_t* __restrict__ nb_ptr,
+                                                 const int32_t* __restrict__ nb_idx, const double* __restrict__ fitw,
+                                                 const double* __restrict__ jmap, const double* __restrict__ jfmap,
+                                                 const double* __restrict__ Fj, const double* __restrict__ phi,
+                                                 const int64_t* __restrict__ cp_of, double* __restrict__ jumps,
+                                                 double* __restrict__ fitvals) {
+  const int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / FJ_LANES;
+  const int q = threadIdx.x % FJ_LANES;
+  const bool live = t < T;  // all lanes stay for the shuffles
+  double fv[3] = {0.0, 0.0, 0.0};
+  if (live && q < 6) {
+    for (int64_t e = nb_ptr[t]; e < nb_ptr[t + 1]; ++e) {
+      const int64_t cp = nb_idx[e];
       const double w = fitw[6 * e + q];
-      fv[3 * q] += w * p0;
-      fv[3 * q + 1] += w * p1;
-      fv[3 * q + 2] += w * p2;
+      fv[0] += w * phi[3 * cp];
+      fv[1] += w * phi[3 * cp + 1];
+      fv[2] += w * phi[3 * cp + 2];
     }
+    const int64_t cp = cp_of[t];
+    if (cp >= 0)
+      for (int i = 0; i < 3; ++i) fitvals[18 * cp + 3 * q + i] = fv[i];
   }
-  const int64_t cp = cp_of[t];
-  if (cp >= 0) {
+  double part[5];
 #pragma unroll
-    for (int c = 0; c < 18; ++c) fitvals[18 * cp + c] = fv[c];
-  }
   for (int r = 0; r < 5; ++r) {
-    double s = 0;
+    double s = 0.0;
+    if (live && q < 6)
+      for (int i = 0; i < 3; ++i) s += jmap[(int64_t)(r * 18 + 3 * q + i) * T + t] * fv[i];
 #pragma unroll
-    for (int c = 0; c < 18; ++c) s += jmap[(r * 18 + c) * T + t] * fv[c];
+    for (int o = 1; o < FJ_LANES; o <<= 1) s += __shfl_xor(s, o, FJ_LANES);
+    part[r] = s;
+  }
+  if (live && q < 5) {
+    double s = part[0];
+#pragma unroll
+    for (int r = 1; r < 5; ++r)
+      if (q == r) s = part[r];
     if (Fj) {
-      const double* Fr = jfmap + (t * 5 + r) * 3;
+      const double* Fr = jfmap + (t * 5 + q) * 3;
       s += Fr[0] * Fj[3 * t] + Fr[1] * Fj[3 * t + 1] + Fr[2] * Fj[3 * t + 2];
     }
-    jumps[5 * t + r] = s;
+    jumps[5 * t + q] = s;
   }
 }
 
@@ -1242,8 +1253,8 @@ static inline int gb(int64_t n) { return (int)((n + 255) / 256 > 0 ? (n + 255) /
 hipError_t launch_fit_jump(int64_t T, const int64_t* nb_ptr, const int32_t* nb_idx, const double* fitw,
                            const double* jmap, const double* jfmap, const double* Fj, const double* phi,
                            const int64_t* cp_of, double* jumps, double* fitvals, hipStream_t s) {
-  hipLaunchKernelGGL(k_fit_jump, dim3(gb(T)), dim3(256), 0, s, T, nb_ptr, nb_idx, fitw, jmap, jfmap, Fj, phi, cp_of,
-                     jumps, fitvals);
+  hipLaunchKernelGGL(k_fit_jump, dim3(gb(T * FJ_LANES)), dim3(256), 0, s, T, nb_ptr, nb_idx, fitw, jmap, jfmap, Fj,
+                     phi, cp_of, jumps, fitvals);
   return hipGetLastError();
 }
 hipError_t launch_interp_jump(int64_t n, const int64_t* cp_target, const double* fitvals, const double* emap,
