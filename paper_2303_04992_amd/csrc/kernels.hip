@@ -79,17 +79,6 @@ __device__ __forceinline__ void load_tile_z(T* lds, const T* __restrict__ g) {
   __syncthreads();
 }
 
-// spectral weight of component m at spectral index (i, j, k) (internal index mapping: along
-// axis m index i is mode i of DCT-II/DST-I; along the other axes index i is mode i+1 of
-// DST-II); returns Lambda_m / mu and sigma_{i_m}
-__device__ __forceinline__ void lambda_of(int m, int i, int j, int k, const double* sig, const double* sig2s,
-                                          double& lam, double& sg) {
-  const int id[3] = {i, j, k};
-  lam = 0;
-#pragma unroll
-  for (int d = 0; d < 3; ++d) lam += (d == m) ? sig[id[d]] * sig[id[d]] : sig2s[id[d]];
-  sg = sig[id[m]];
-}
 
 // ---------------------------------------------------------------------------------------
 // generic transform pass: out (+)= transform_KIND(in) along axis
@@ -174,22 +163,14 @@ __global__ __launch_bounds__(256) void k_pass(const T* in, T* out, int axis, Tab
 // orthonormal scale factors cancelling; V'_q = e^{+i pi q/2N}(Y_q - i Y_{N-q}), Y_N = 0,
 // Z'_q = V'^a_q + i V'^b_q.
 // ---------------------------------------------------------------------------------------
-// Pencils per tile of the fused x kernel: one 128-byte row (half-row tiles, with twice the
-// resident blocks, measured slower: 149 vs 115 us at 256^3 float32).
-template <typename T, int N>
-constexpr int xmid_w() {
-  return TileCfg<T, N, DCT2>::W;
-}
-
 template <typename T, int N, int KF, int KI>
 __device__ void xmid_body(T* lds, T* field, int mc, double mu, const double* sig, const double* sig2s,
                           const Tab<T>& tb) {
-  constexpr int XW = xmid_w<T, N>();
-  using S = TileCfg<T, N, KF, XW>;
+  using S = TileCfg<T, N, KF>;
   constexpr int W = S::W, NJ = S::NJ, ZS = S::ZS, NT = S::NT;
   const TileAddr a = tile_addr<W, N>(0, blockIdx.x);
   const int yi = blockIdx.x / (N / W), z0 = (blockIdx.x % (N / W)) * W;
-  fft_tile<T, N, KF, XW>(lds, GlobSrc<T>{field, a.base, a.nstride}, tb);
+  fft_tile<T, N, KF>(lds, GlobSrc<T>{field, a.base, a.nstride}, tb);
   C2<T>* cb = reinterpret_cast<C2<T>*>(lds);
   constexpr int PAIRS = N / 2 + 1;
   static_assert(NT % NJ == 0, "the job of a thread is fixed across the loop");
@@ -240,8 +221,8 @@ __device__ void xmid_body(T* lds, T* field, int mc, double mu, const double* sig
     }
   }
   __syncthreads();
-  fft_core<T, N, KI, XW>(lds, [&](int j, int n) { return cb[j * ZS + n]; }, tb);
-  using O = OutItems<T, N, KI, XW>;
+  fft_core<T, N, KI>(lds, [&](int j, int n) { return cb[j * ZS + n]; }, tb);
+  using O = OutItems<T, N, KI>;
   C2<T>* o = reinterpret_cast<C2<T>*>(field + a.base);
   const long ns = a.nstride / 2;
 #pragma unroll 4
@@ -281,8 +262,7 @@ __device__ __forceinline__ void store_xy_outputs(const T* lds, const Tab<T>& tb,
 // ---------------------------------------------------------------------------------------
 template <typename T, int N, int KF, int KI, bool BACKSUB>
 __global__ __launch_bounds__(256) void k_xfuse(const T* __restrict__ in, T* __restrict__ fh, T* __restrict__ out,
-                                              int m, double mu, const double* __restrict__ sig,
-                                              const double* __restrict__ sig2s, Tab<T> tb) {
+                                              int m, double mu, Tab<T> tb) {
   extern __shared__ __align__(16) unsigned char smem[];
   T* lds = reinterpret_cast<T*>(smem);
   using SF = TileCfg<T, N, KF>;
@@ -1088,7 +1068,7 @@ hipError_t launch_xmid(int N, T* A0, T* A1, T* A2, double mu, const DevTables<T>
   const Tab<T> t = tab_of(tb);
 #define KFBI_M(NN)                                                                                              \
   {                                                                                                             \
-    using S = TileCfg<T, NN, DCT2, xmid_w<T, NN>()>;                                                            \
+    using S = TileCfg<T, NN, DCT2>;                                                                             \
     const int blocks = NN * NN / S::W;                                                                          \
     const size_t lds = S::BYTES;                                                                                \
     ensure_lds(k_xmid<T, NN>, lds);                                                                             \
@@ -1148,8 +1128,7 @@ static hipError_t xfuse_n(int m, const T* in, T* fh, T* out, double mu, const De
   const int nt = SF::NT > SI::NT ? SF::NT : SI::NT;
   const int blocks = N * N / SF::W;
   ensure_lds(k_xfuse<T, N, KF, KI, BS>, lds);
-  hipLaunchKernelGGL((k_xfuse<T, N, KF, KI, BS>), dim3(blocks), dim3(nt), lds, s, in, fh, out, m, mu, tb.sig,
-                     tb.sig2s, tab_of(tb));
+  hipLaunchKernelGGL((k_xfuse<T, N, KF, KI, BS>), dim3(blocks), dim3(nt), lds, s, in, fh, out, m, mu, tab_of(tb));
   return hipGetLastError();
 }
 

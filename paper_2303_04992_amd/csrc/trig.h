@@ -48,11 +48,10 @@ __host__ __device__ __forceinline__ C2<T> cmul(C2<T> a, C2<T> b) {
 
 __host__ __device__ constexpr int ilog2(int v) { return v <= 1 ? 0 : 1 + ilog2(v / 2); }
 
-// Tile configuration of one transform kind at grid size N (WQ > 0: W pencils per tile instead
-// of one 128-byte row's worth).
-template <typename T, int N, int KIND, int WQ = 0>
+// Tile configuration of one transform kind at grid size N.
+template <typename T, int N, int KIND>
 struct TileCfg {
-  static constexpr int W = WQ > 0 ? WQ : ((int)(128 / sizeof(T)) < N ? (int)(128 / sizeof(T)) : N);  // pencils
+  static constexpr int W = (int)(128 / sizeof(T)) < N ? (int)(128 / sizeof(T)) : N;  // pencils
   static constexpr int RS = N + 1;                                                  // row stride
   static constexpr int L = (KIND == DST1) ? 2 * N : N;                              // FFT length
   static constexpr int NJ = W / 2;                                                  // complex jobs
@@ -205,18 +204,18 @@ __device__ __forceinline__ C2<T> pre_sample(const Src& src, const Tab<T>& tb, in
 // cb[j * ZS + k] (natural order, length L).  LDS may alias the source (pass-1 samples are
 // staged in registers).  Every thread of the block must call it; a block may have more
 // threads than Cfg::NT (the extra ones only take part in the barriers).
-template <typename T, int N, int KIND, int WQ = 0, class Sampler>
+template <typename T, int N, int KIND, class Sampler>
 __device__ void fft_core(T* lds, Sampler&& sample, const Tab<T>& tb);
 
-template <typename T, int N, int KIND, int WQ = 0, class Src>
+template <typename T, int N, int KIND, class Src>
 __device__ __forceinline__ void fft_tile(T* lds, const Src& src, const Tab<T>& tb) {
-  fft_core<T, N, KIND, WQ>(lds, [&](int j, int n) { return pre_sample<T, N, KIND>(src, tb, j, n); }, tb);
+  fft_core<T, N, KIND>(lds, [&](int j, int n) { return pre_sample<T, N, KIND>(src, tb, j, n); }, tb);
 }
 
 // Same, with the complex FFT input given directly by sample(j, n) (it may read LDS).
-template <typename T, int N, int KIND, int WQ, class Sampler>
+template <typename T, int N, int KIND, class Sampler>
 __device__ void fft_core(T* lds, Sampler&& sample, const Tab<T>& tb) {
-  using S = TileCfg<T, N, KIND, WQ>;
+  using S = TileCfg<T, N, KIND>;
   constexpr int L = S::L, NJ = S::NJ, R1 = S::R1, R2 = S::R2, P2 = S::P2, YS = S::YS, ZS = S::ZS, NT = S::NT;
   constexpr bool INV = (KIND == DCT3 || KIND == DST3);
   C2<T>* cb = reinterpret_cast<C2<T>*>(lds);
@@ -322,9 +321,9 @@ struct alignas(16) V16 {
 // wavefront writes whole pencils).  Axes 0, 1 (pencils adjacent in memory): item (j, k) covers
 // output k of pencils 2j and 2j+1 (one 2-element store, a wavefront writes whole 128-byte rows
 // of the tile).  Thread t handles items t + u*NT, u < PER.
-template <typename T, int N, int KIND, int WQ = 0>
+template <typename T, int N, int KIND>
 struct OutItems {
-  using S = TileCfg<T, N, KIND, WQ>;
+  using S = TileCfg<T, N, KIND>;
   static constexpr int NT = S::NT, NJ = S::NJ, VEC = V16<T>::n;
   static constexpr int NKV = N / VEC;
   static constexpr int COUNT_Z = NJ * NKV, PER_Z = (COUNT_Z + NT - 1) / NT;
