@@ -163,14 +163,15 @@ __global__ __launch_bounds__(256) void k_pass(const T* in, T* out, int axis, Tab
 // orthonormal scale factors cancelling; V'_q = e^{+i pi q/2N}(Y_q - i Y_{N-q}), Y_N = 0,
 // Z'_q = V'^a_q + i V'^b_q.
 // ---------------------------------------------------------------------------------------
+// one tile: forward x from the pass-1 samples already in registers, weight, inverse x, store
 template <typename T, int N, int KF, int KI>
-__device__ void xmid_body(T* lds, T* field, int mc, double mu, const double* sig, const double* sig2s,
-                          const Tab<T>& tb) {
+__device__ void xmid_tile(T* lds, T* field, int tile, int mc, double mu, const Tab<T>& tb,
+                          C2<T> (&zs)[TileCfg<T, N, KF>::PT1][TileCfg<T, N, KF>::R1]) {
   using S = TileCfg<T, N, KF>;
   constexpr int W = S::W, NJ = S::NJ, ZS = S::ZS, NT = S::NT;
-  const TileAddr a = tile_addr<W, N>(0, blockIdx.x);
-  const int yi = blockIdx.x / (N / W), z0 = (blockIdx.x % (N / W)) * W;
-  fft_tile<T, N, KF>(lds, GlobSrc<T>{field, a.base, a.nstride}, tb);
+  const TileAddr a = tile_addr<W, N>(0, tile);
+  const int yi = tile / (N / W), z0 = (tile % (N / W)) * W;
+  fft_core_from<T, N, KF>(lds, zs, tb);
   C2<T>* cb = reinterpret_cast<C2<T>*>(lds);
   constexpr int PAIRS = N / 2 + 1;
   static_assert(NT % NJ == 0, "the job of a thread is fixed across the loop");
@@ -333,18 +334,30 @@ __global__ __launch_bounds__(256) void k_xfuse(const T* __restrict__ in, T* __re
   store_xy_outputs<T, N, KI>(lds, tb, out + a.base, a.nstride);
 }
 
+// one tile per block (two tiles per block, with the second tile's samples requested before the
+// first is transformed, measured slower: 125 vs 118 us at 256^3 float32)
+template <typename T, int N, int KF, int KI>
+__device__ void xmid_body(T* lds, T* field, int mc, double mu, const Tab<T>& tb) {
+  using S = TileCfg<T, N, KF>;
+  const int tile = blockIdx.x;
+  const TileAddr a = tile_addr<S::W, N>(0, tile);
+  const GlobSrc<T> src{field, a.base, a.nstride};
+  C2<T> zs[S::PT1][S::R1];
+  fft_gather<T, N, KF>([&](int j, int n) { return pre_sample<T, N, KF>(src, tb, j, n); }, zs);
+  xmid_tile<T, N, KF, KI>(lds, field, tile, mc, mu, tb, zs);
+}
+
 template <typename T, int N>
-__global__ __launch_bounds__(256) void k_xmid(T* A0, T* A1, T* A2, double mu, const double* sig,
-                                             const double* sig2s, Tab<T> tb) {
+__global__ __launch_bounds__(256) void k_xmid(T* A0, T* A1, T* A2, double mu, Tab<T> tb) {
   extern __shared__ __align__(16) unsigned char smem[];
   T* lds = reinterpret_cast<T*>(smem);
   const int mc = blockIdx.y;
   if (mc == 0)
-    xmid_body<T, N, DCT2, DCT3>(lds, A0, 0, mu, sig, sig2s, tb);
+    xmid_body<T, N, DCT2, DCT3>(lds, A0, 0, mu, tb);
   else if (mc == 1)
-    xmid_body<T, N, DST2, DST3>(lds, A1, 1, mu, sig, sig2s, tb);
+    xmid_body<T, N, DST2, DST3>(lds, A1, 1, mu, tb);
   else
-    xmid_body<T, N, DST2, DST3>(lds, A2, 2, mu, sig, sig2s, tb);
+    xmid_body<T, N, DST2, DST3>(lds, A2, 2, mu, tb);
 }
 
 
@@ -1072,7 +1085,7 @@ hipError_t launch_xmid(int N, T* A0, T* A1, T* A2, double mu, const DevTables<T>
     const int blocks = NN * NN / S::W;                                                                          \
     const size_t lds = S::BYTES;                                                                                \
     ensure_lds(k_xmid<T, NN>, lds);                                                                             \
-    hipLaunchKernelGGL((k_xmid<T, NN>), dim3(blocks, 3), dim3(S::NT), lds, s, A0, A1, A2, mu, tb.sig, tb.sig2s, t); \
+    hipLaunchKernelGGL((k_xmid<T, NN>), dim3(blocks, 3), dim3(S::NT), lds, s, A0, A1, A2, mu, t);               \
   }
   KFBI_DISPATCH_N(N, KFBI_M)
 #undef KFBI_M

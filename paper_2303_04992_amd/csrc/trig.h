@@ -65,6 +65,7 @@ struct TileCfg {
   static constexpr int YS = R1 * P2 + PAD[1];                // job stride of the transpose buffer
   static constexpr int ZS = L + PAD[2];                      // job stride of the spectra
   static constexpr int NT = (NJ * R2 > 256) ? 256 : (NJ * R2 > 64) ? NJ * R2 : 64;  // threads
+  static constexpr int PT1 = (NJ * R2 + NT - 1) / NT;  // pass-1 tasks per thread
   static constexpr int REALS_TILE = W * RS;
   static constexpr int REALS_Y = NJ * YS * 2;
   static constexpr int REALS_Z = NJ * ZS * 2;
@@ -212,9 +213,41 @@ __device__ __forceinline__ void fft_tile(T* lds, const Src& src, const Tab<T>& t
   fft_core<T, N, KIND>(lds, [&](int j, int n) { return pre_sample<T, N, KIND>(src, tb, j, n); }, tb);
 }
 
+// Pass-1 samples of the thread: z[u][n1] = sample(j, R2 n1 + n2) for its task u = (j, n2).
+template <typename T, int N, int KIND, class Sampler>
+__device__ __forceinline__ void fft_gather(Sampler&& sample,
+                                           C2<T> (&z)[TileCfg<T, N, KIND>::PT1][TileCfg<T, N, KIND>::R1]) {
+  using S = TileCfg<T, N, KIND>;
+  constexpr int NJ = S::NJ, R1 = S::R1, R2 = S::R2, NT = S::NT, TASKS = NJ * R2;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < S::PT1; ++u) {
+    const int task = tid + u * NT;
+    if ((TASKS % NT == 0 || task < TASKS) && tid < NT) {
+      const int j = task % NJ, n2 = task / NJ;
+#pragma unroll
+      for (int n1 = 0; n1 < R1; ++n1) z[u][n1] = sample(j, R2 * n1 + n2);
+    }
+  }
+}
+
+template <typename T, int N, int KIND>
+__device__ void fft_core_from(T* lds, C2<T> (&z)[TileCfg<T, N, KIND>::PT1][TileCfg<T, N, KIND>::R1],
+                              const Tab<T>& tb);
+
 // Same, with the complex FFT input given directly by sample(j, n) (it may read LDS).
 template <typename T, int N, int KIND, class Sampler>
 __device__ void fft_core(T* lds, Sampler&& sample, const Tab<T>& tb) {
+  using S = TileCfg<T, N, KIND>;
+  C2<T> z[S::PT1][S::R1];
+  fft_gather<T, N, KIND>(sample, z);
+  fft_core_from<T, N, KIND>(lds, z, tb);
+}
+
+// The FFTs from the pass-1 samples already in registers (z is overwritten).
+template <typename T, int N, int KIND>
+__device__ void fft_core_from(T* lds, C2<T> (&z)[TileCfg<T, N, KIND>::PT1][TileCfg<T, N, KIND>::R1],
+                              const Tab<T>& tb) {
   using S = TileCfg<T, N, KIND>;
   constexpr int L = S::L, NJ = S::NJ, R1 = S::R1, R2 = S::R2, P2 = S::P2, YS = S::YS, ZS = S::ZS, NT = S::NT;
   constexpr bool INV = (KIND == DCT3 || KIND == DST3);
@@ -224,15 +257,12 @@ __device__ void fft_core(T* lds, Sampler&& sample, const Tab<T>& tb) {
   // ---------------- pass 1: R1-point DFTs over stride-R2 samples, twiddle, transpose
   {
     constexpr int TASKS = NJ * R2;
-    constexpr int PT = (TASKS + NT - 1) / NT;
-    C2<T> z[PT][R1];
+    constexpr int PT = S::PT1;
 #pragma unroll
     for (int u = 0; u < PT; ++u) {
       const int task = tid + u * NT;
       if ((TASKS % NT == 0 || task < TASKS) && tid < NT) {
-        const int j = task % NJ, n2 = task / NJ;
-#pragma unroll
-        for (int n1 = 0; n1 < R1; ++n1) z[u][n1] = sample(j, R2 * n1 + n2);
+        const int n2 = task / NJ;
         dftR<T, R1, INV>(z[u]);
 #pragma unroll
         for (int k1 = 1; k1 < R1; ++k1) {
