@@ -70,10 +70,11 @@ struct MacSolver {
   T *Fh[3] = {nullptr, nullptr, nullptr}, *b = nullptr, *x = nullptr, *r = nullptr, *d = nullptr, *q = nullptr;
   T *A = nullptr, *B = nullptr, *A1 = nullptr, *B2 = nullptr, *B3 = nullptr, *tmp = nullptr;
   double* partials = nullptr;
+  double* rpart = nullptr;  // partial r.r of the forward z pass
   double* scal = nullptr;
   double* host_rr = nullptr;  // pinned, 2 slots
   hipEvent_t ev[2] = {nullptr, nullptr};
-  int nparts_x = 0, nparts_u = 1024;
+  int nparts_x = 0, nparts_z = 0, nparts_u = 1024;
   // live timing of one transform-pass kind with HIP events on the solver stream
   int prof_kind = -1, prof_axis = -1;
   std::vector<std::pair<hipEvent_t, hipEvent_t>> prof_ev;
@@ -136,7 +137,9 @@ struct MacSolver {
     B3 = dalloc<T>(M, owned);
     tmp = dalloc<T>(M, owned);
     nparts_x = zinv_blocks(N, sizeof(T));
-    partials = dalloc<double>(std::max(3 * nparts_x, nparts_u), owned);
+    nparts_z = zfwd_blocks(N, sizeof(T));
+    partials = dalloc<double>(std::max(4 * nparts_x, nparts_u), owned);
+    rpart = dalloc<double>(nparts_z, owned);
     scal = dalloc<double>(16, owned);
     HIPCHK(hipHostMalloc((void**)&host_rr, 2 * sizeof(double), hipHostMallocDefault));
     HIPCHK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
@@ -179,7 +182,7 @@ struct MacSolver {
     const double f = (double)M * sizeof(T);
     switch (id) {
       case KFBI_K_XMID: return 6 * f;  // three fields read and written
-      case KFBI_K_ZFWD: return 5 * f;  // r, d read; d, A, B written
+      case KFBI_K_ZFWD: return 9 * f;  // x, r, d, q read; x, r, d, A, B written
       case KFBI_K_ZINV: return 4 * f;  // A, B, d read; q written
       case KFBI_K_YFWD: return 3 * f;  // A read; A1, B2 written
       case KFBI_K_YINV: return 3 * f;  // A1, B2 read; A written
@@ -203,27 +206,29 @@ struct MacSolver {
     HIPCHK(launch_add_scalar<T>(M, v, scal, 5, -1.0 / (double)M, s));
   }
 
-  // S p for the CG direction d (q = S d); d = r + beta d_old is formed in the first pass
+  // S p for the CG direction d (q = S d); the updates of x, r (previous iteration) and of
+  // d = r + beta d_old are formed in the first pass
   // C_0 = DCT_x DST_y DST_z, C_1 = DST_x DCT_y DST_z, C_2 = DST_x DST_y DCT_z (orthonormal);
   // order z, y, [x fused with the weights], y, z
-  void zfwd() { timed(prof_kind == KFBI_K_ZFWD, [&] { return launch_zfwd_cg<T>(N, r, d, A, B, scal, tb, s); }); }
+  void zfwd(int mode = ZF_FUSED) {
+    timed(prof_kind == KFBI_K_ZFWD && mode == ZF_FUSED,
+          [&] { return launch_zfwd_cg<T>(N, mode, x, r, d, q, A, B, scal, rpart, tb, s); });
+  }
   void yfwd() { timed(prof_kind == KFBI_K_YFWD, [&] { return launch_ypair<T>(N, false, A, A, A1, B2, tb, s); }); }
   void xmid() { timed(prof_kind == KFBI_K_XMID, [&] { return launch_xmid<T>(N, A1, B2, B3, mu, tb, s); }); }
   void yinv() { timed(prof_kind == KFBI_K_YINV, [&] { return launch_ypair<T>(N, true, A1, B2, A, A, tb, s); }); }
   void zinv() {
     timed(prof_kind == KFBI_K_ZINV, [&] { return launch_zinv_cg<T>(N, A, B, q, d, c, partials, tb, s); });
   }
-  void cg_iteration() {
-    zfwd();                // d = r + beta d; A = DST_z d; B = DCT_z d
+  void cg_iteration(bool first) {
+    zfwd(first ? ZF_FIRST : ZF_FUSED);  // x, r of the last step; d = r + beta d; A = DST_z d; B = DCT_z d
     yfwd();                // components 0, 1: A1 = DST_y A, B2 = DCT_y A
     pass(DST2, 1, B, B3);  // component 2
     xmid();                // x: forward, weight sigma^2 / Lambda, inverse (all components)
     yinv();                // A = DST_y^T A1 + DCT_y^T B2 (components 0 and 1 share DST_z)
     pass(DST3, 1, B3, B);
     zinv();                // q = DST_z^T A + DCT_z^T B + c d, partial dots
-    HIPCHK(launch_reduce(partials, nparts_x, 3, scal, R_ALPHA, pde == KFBI_STOKES, M, s));
-    HIPCHK(launch_cg_update<T>(M, x, r, d, q, scal, partials, nparts_u, s));
-    HIPCHK(launch_reduce(partials, nparts_u, 1, scal, R_BETA, 0, M, s));
+    HIPCHK(launch_cg_coef(rpart, nparts_z, partials, nparts_x, scal, pde == KFBI_STOKES, M, s));
   }
 
   // Solve A_u u + G p = F_u, D u + c p = F_p (Stokes: D u = F_p - mean F_p, mean p = 0).
@@ -243,9 +248,9 @@ struct MacSolver {
     pass(DST3, 1, B3, B);                                        // B = DST_y^T H2
     HIPCHK(launch_zinv_cg<T>(N, A, B, b, Fp, 1.0, partials, tb, s));  // b = DST_z^T A + DCT_z^T B + F_p
     project_mean(b);
-    // 3. CG on S x = b
+    // 3. CG on S x = b.  Iteration k forms x_k, r_k (with alpha_{k-1}) and d_k in its first
+    // pass, so x lags one step until the final x += alpha d.
     HIPCHK(launch_fill<T>(M, x, T(0), s));
-    HIPCHK(launch_fill<T>(M, d, T(0), s));
     HIPCHK(hipMemcpyAsync(r, b, M * sizeof(T), hipMemcpyDeviceToDevice, s));
     HIPCHK(launch_dot_partials<T>(M, r, r, partials, nparts_u, s));
     HIPCHK(launch_reduce(partials, nparts_u, 1, scal, R_INIT_RR, 0, M, s));
@@ -258,7 +263,7 @@ struct MacSolver {
     const double thr = rtol * rtol * rr0;
     // one iteration of look-ahead: iteration k+1 is queued before the residual of k is read
     while (!conv && it < maxit) {
-      cg_iteration();
+      cg_iteration(it == 0);
       HIPCHK(hipMemcpyAsync(&host_rr[it & 1], scal, sizeof(double), hipMemcpyDeviceToHost, s));
       HIPCHK(hipEventRecord(ev[it & 1], s));
       ++it;
@@ -268,6 +273,7 @@ struct MacSolver {
         if (std::isnan(host_rr[(it - 2) & 1])) throw DevErr{"NaN in the Schur CG residual"};
       }
     }
+    if (it > 0) HIPCHK(launch_axpy_scal<T>(M, x, d, scal, 1, s));  // the pending x += alpha d
     HIPCHK(hipStreamSynchronize(s));
     if (!conv && it > 0) {
       double last = host_rr[(it - 1) & 1];
@@ -276,7 +282,8 @@ struct MacSolver {
     project_mean(x);
     // 4. velocity back-substitution u_m = T_m^T [(T_m F_m + sigma C_m p) / Lambda_m]: C_m p along
     // z and y shared as in the matvec, then per component the fused x pass and the y, z inverses
-    HIPCHK(launch_zfwd_cg<T>(N, x, nullptr, A, B, nullptr, tb, s));  // A = DST_z p, B = DCT_z p
+    // A = DST_z p, B = DCT_z p
+    HIPCHK(launch_zfwd_cg<T>(N, ZF_PLAIN, nullptr, x, nullptr, nullptr, A, B, nullptr, nullptr, tb, s));
     HIPCHK(launch_ypair<T>(N, false, A, A, A1, B2, tb, s));          // C_0, C_1 along y
     pass(DST2, 1, B, B3);                                             // C_2 along y
     for (int m = 0; m < 3; ++m) {
@@ -950,7 +957,8 @@ kfbi_status kfbi_time_pass(kfbi_ctx* C, int32_t kind, int32_t axis, int32_t reps
     HIPCHK(hipEventCreate(&e1));
     auto run = [&](auto& sv) {
       using T = std::remove_reference_t<decltype(*sv.A)>;
-      for (T* f : {sv.A, sv.B, sv.A1, sv.B2, sv.B3, sv.r, sv.d}) HIPCHK(launch_fill<T>(sv.M, f, T(1), C->s));
+      for (T* f : {sv.A, sv.B, sv.A1, sv.B2, sv.B3, sv.r, sv.d, sv.q, sv.x})
+        HIPCHK(launch_fill<T>(sv.M, f, T(1), C->s));
       HIPCHK(hipMemsetAsync(sv.scal, 0, 16 * sizeof(double), C->s));
       auto once = [&] {
         switch (kind) {

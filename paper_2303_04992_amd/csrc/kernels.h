@@ -33,12 +33,18 @@ hipError_t launch_pass(int N, int kind, int axis, const T* in, T* out, bool accu
 // fused x-pass of the Schur operator for the three components (fwd x, weight, inverse x)
 template <typename T>
 hipError_t launch_xmid(int N, T* A0, T* A1, T* A2, double mu, const DevTables<T>& tb, hipStream_t s);
-// d = r + beta d_old (beta from scal[2]), A = DST-II_z(d), B = DCT-II_z(d); with d = nullptr
-// only A = DST-II_z(r), B = DCT-II_z(r) (scal unused)
+// Forward z pass of the Schur matvec (A = DST-II_z v, B = DCT-II_z v) with the CG updates folded in:
+//   ZF_PLAIN  v = r (x, d, q, scal, rpart unused)
+//   ZF_FIRST  d = r, v = d; rpart[block] = partial r.r
+//   ZF_FUSED  x += alpha d; r -= alpha (q - mean q); d = r + beta d (scal[1], scal[2], scal[3]);
+//             v = d; rpart[block] = partial r.r of the updated r
+// rpart holds zfwd_blocks(N, sizeof(T)) doubles.
+enum ZfwdMode { ZF_PLAIN = 0, ZF_FIRST = 1, ZF_FUSED = 2 };
 template <typename T>
-hipError_t launch_zfwd_cg(int N, const T* r, T* d, T* A, T* B, const double* scal, const DevTables<T>& tb,
-                          hipStream_t s);
-// q = DST-III_z(A) + DCT-III_z(B) + c d; per-block partial sums of d.q, q, d
+hipError_t launch_zfwd_cg(int N, int mode, T* x, T* r, T* d, const T* q, T* A, T* B, const double* scal,
+                          double* rpart, const DevTables<T>& tb, hipStream_t s);
+int zfwd_blocks(int N, int elem_size);
+// q = DST-III_z(A) + DCT-III_z(B) + c d; per-block partial sums (d.q, q, d, q.q), 4 per block
 template <typename T>
 hipError_t launch_zinv_cg(int N, const T* A, const T* B, T* q, const T* d, double c, double* partials,
                           const DevTables<T>& tb, hipStream_t s);
@@ -53,14 +59,18 @@ template <typename T>
 hipError_t launch_ypair(int N, bool inverse, const T* in0, const T* in1, T* out0, T* out1, const DevTables<T>& tb,
                         hipStream_t s);
 int zinv_blocks(int N, int elem_size);
-// x += alpha d; r -= alpha (q - mq); partial sums of r.r
+// x += scal[idx] d
 template <typename T>
-hipError_t launch_cg_update(int64_t M, T* x, T* r, const T* d, const T* q, const double* scal, double* partials,
-                            int nblocks, hipStream_t s);
+hipError_t launch_axpy_scal(int64_t M, T* x, const T* d, const double* scal, int idx, hipStream_t s);
+// CG coefficients from the partial sums of the forward z pass (r.r, nr blocks) and of the
+// inverse z pass (nz blocks of 4): scal[0] = |r_next|^2 (recurrence), [1] alpha, [2] beta,
+// [3] mean q (Stokes), [7] r.r
+hipError_t launch_cg_coef(const double* rpart, int nr, const double* zpart, int nz, double* scal, int stokes,
+                          int64_t M, hipStream_t s);
 
 // ---- reductions (float64, deterministic)
-// scal layout: [0] rr, [1] alpha, [2] beta, [3] mean q, [4] rr0, [5] scratch sum, [6] aux
-enum ReduceOp { R_ALPHA = 0, R_BETA = 1, R_SUM = 2, R_INIT_RR = 3, R_RESNORM = 4, R_RESNORM0 = 5 };
+// scal layout: [0] rr, [1] alpha, [2] beta, [3] mean q, [4] rr0, [5] scratch sum, [6] aux, [7] r.r
+enum ReduceOp { R_SUM = 2, R_INIT_RR = 3, R_RESNORM = 4, R_RESNORM0 = 5 };
 hipError_t launch_reduce(const double* partials, int nparts, int nper, double* scal, int op, int stokes,
                          int64_t M, hipStream_t s, double* out = nullptr);  // R_SUM: *out (or scal[5])
 template <typename T>

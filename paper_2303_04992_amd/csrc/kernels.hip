@@ -181,7 +181,13 @@ __device__ void xmid_tile(T* lds, T* field, int tile, int mc, double mu, const T
   T lz[2];
 #pragma unroll
   for (int w = 0; w < 2; ++w) lz[w] = (mc == 2) ? tb.sg2[z0 + 2 * jt + w] : tb.sg2s[z0 + 2 * jt + w];
-  for (int t = threadIdx.x; t < NJ * PAIRS; t += NT) {
+  // the factor 1/2 of V below is folded into the weight denominators
+  const T mu2 = T(2 * mu);
+  constexpr int PER = (NJ * PAIRS + NT - 1) / NT;
+#pragma unroll
+  for (int u = 0; u < PER; ++u) {
+    const int t = threadIdx.x + u * NT;
+    if (t >= NJ * PAIRS) break;
     const int j = jt, k = t / NJ;
     const int kr = (N - k) & (N - 1);
     const C2<T> Zk = cb[j * ZS + k], Zr = cb[j * ZS + kr];
@@ -196,7 +202,7 @@ __device__ void xmid_tile(T* lds, T* field, int tile, int mc, double mu, const T
 #pragma unroll
       for (int w = 0; w < 2; ++w) {
         const T num = (mc == 0) ? lx : (mc == 1) ? ly : lz[w];
-        const T den = T(mu) * (lx + ly + lz[w]);
+        const T den = mu2 * (lx + ly + lz[w]);
         if constexpr (sizeof(T) == 4)
           om[w][h] = num * __builtin_amdgcn_rcpf(den);  // 1 ulp: the float32 inner solve
         else
@@ -204,10 +210,10 @@ __device__ void xmid_tile(T* lds, T* field, int tile, int mc, double mu, const T
       }
     }
     const C2<T> mkk = tb.mk[k], mkr = tb.mk[kr];
-    const C2<T> Vak = {(Zk.x + Zr.x) * T(0.5), (Zk.y - Zr.y) * T(0.5)};
-    const C2<T> Vbk = {(Zk.y + Zr.y) * T(0.5), (Zr.x - Zk.x) * T(0.5)};
-    const C2<T> Var = {(Zr.x + Zk.x) * T(0.5), (Zr.y - Zk.y) * T(0.5)};
-    const C2<T> Vbr = {(Zr.y + Zk.y) * T(0.5), (Zk.x - Zr.x) * T(0.5)};
+    const C2<T> Vak = {Zk.x + Zr.x, Zk.y - Zr.y};  // 2 V^a_k
+    const C2<T> Vbk = {Zk.y + Zr.y, Zr.x - Zk.x};  // 2 V^b_k
+    const C2<T> Var = {Zr.x + Zk.x, Zr.y - Zk.y};
+    const C2<T> Vbr = {Zr.y + Zk.y, Zk.x - Zr.x};
     const T Yak = om[0][0] * (mkk.x * Vak.x - mkk.y * Vak.y);
     const T Ybk = om[1][0] * (mkk.x * Vbk.x - mkk.y * Vbk.y);
     const T Yar = (k == 0) ? T(0) : om[0][1] * (mkr.x * Var.x - mkr.y * Var.y);
@@ -383,26 +389,62 @@ __device__ __forceinline__ void store_z_outputs(const T* lds, const Tab<T>& tb, 
   }
 }
 
-template <typename T, int N, bool CG>
-__global__ __launch_bounds__(256) void k_zfwd_cg(const T* __restrict__ r, T* __restrict__ d, T* __restrict__ A,
-                                                T* __restrict__ B, const double* __restrict__ scal, Tab<T> tb) {
+// Forward z pass of the Schur matvec with the CG vector updates folded in.
+//   ZF_PLAIN  A = DST-II_z r, B = DCT-II_z r (velocity back-substitution; r is only read)
+//   ZF_FIRST  d = r, then the transforms of d; partial sums of r.r
+//   ZF_FUSED  x += alpha d, r -= alpha (q - mean q), d = r + beta d (alpha, beta, mean q of the
+//             previous iteration in scal[1..3]), then the transforms of d; partial sums of r.r
+// Every thread streams its vectors once; d stays in registers for the second transform.
+template <typename T, int N, int MODE>
+__global__ __launch_bounds__(256) void k_zfwd_cg(T* __restrict__ x, T* __restrict__ r, T* __restrict__ d,
+                                                const T* __restrict__ q, T* __restrict__ A, T* __restrict__ B,
+                                                const double* __restrict__ scal, double* __restrict__ rpart,
+                                                Tab<T> tb) {
   extern __shared__ __align__(16) unsigned char smem[];
+  __shared__ double red[4];
   T* lds = reinterpret_cast<T*>(smem);
   using S = TileCfg<T, N, DST2>;
   constexpr int W = S::W, RS = N + 1, NT = S::NT, VEC = V16<T>::n;
   constexpr int NV = W * N / VEC, PER = (NV + NT - 1) / NT;
-  const T beta = CG ? T(scal[2]) : T(0);
   const TileAddr a = tile_addr<W, N>(2, blockIdx.x);
   const V16<T>* rv = reinterpret_cast<const V16<T>*>(r + a.base);
-  V16<T>* dv = CG ? reinterpret_cast<V16<T>*>(d + a.base) : nullptr;
-  V16<T> x[PER], y[PER];
+  V16<T> v[PER];
+  double rr = 0;
 #pragma unroll
   for (int u = 0; u < PER; ++u) {
     const int e = threadIdx.x + u * NT;
     if (NV % NT == 0 || e < NV) {
-      x[u] = rv[e];
-      if (CG) y[u] = dv[e];
+      v[u] = rv[e];
+      if constexpr (MODE == ZF_FUSED) {
+        const T alpha = T(scal[1]), beta = T(scal[2]), mq = T(scal[3]);
+        V16<T>* xv = reinterpret_cast<V16<T>*>(x + a.base);
+        V16<T>* wv = reinterpret_cast<V16<T>*>(r + a.base);
+        V16<T>* dv = reinterpret_cast<V16<T>*>(d + a.base);
+        const V16<T> dold = dv[e], qv = reinterpret_cast<const V16<T>*>(q + a.base)[e];
+        V16<T> xn = xv[e];
+#pragma unroll
+        for (int c = 0; c < VEC; ++c) {
+          xn.a[c] += alpha * dold.a[c];
+          v[u].a[c] -= alpha * (qv.a[c] - mq);
+        }
+        xv[e] = xn;
+        wv[e] = v[u];
+#pragma unroll
+        for (int c = 0; c < VEC; ++c) {
+          rr += (double)v[u].a[c] * (double)v[u].a[c];
+          v[u].a[c] += beta * dold.a[c];
+        }
+        dv[e] = v[u];
+      } else if constexpr (MODE == ZF_FIRST) {
+#pragma unroll
+        for (int c = 0; c < VEC; ++c) rr += (double)v[u].a[c] * (double)v[u].a[c];
+        reinterpret_cast<V16<T>*>(d + a.base)[e] = v[u];
+      }
     }
+  }
+  if constexpr (MODE != ZF_PLAIN) {
+    const double t = block_sum(rr, red);
+    if (threadIdx.x == 0) rpart[blockIdx.x] = t;
   }
   auto stage = [&]() {
 #pragma unroll
@@ -411,22 +453,11 @@ __global__ __launch_bounds__(256) void k_zfwd_cg(const T* __restrict__ r, T* __r
       if (NV % NT == 0 || e < NV) {
         const int p = (e * VEC) / N, n = (e * VEC) - p * N;
 #pragma unroll
-        for (int q = 0; q < VEC; ++q) lds[p * RS + n + q] = x[u].a[q];
+        for (int c = 0; c < VEC; ++c) lds[p * RS + n + c] = v[u].a[c];
       }
     }
     __syncthreads();
   };
-  if constexpr (CG) {
-#pragma unroll
-    for (int u = 0; u < PER; ++u) {
-      const int e = threadIdx.x + u * NT;
-      if (NV % NT == 0 || e < NV) {
-#pragma unroll
-        for (int q = 0; q < VEC; ++q) x[u].a[q] += beta * y[u].a[q];
-        dv[e] = x[u];
-      }
-    }
-  }
   stage();
   fft_tile<T, N, DST2>(lds, LdsSrc<T, N>{lds}, tb);
   store_z_outputs<T, N, DST2>(lds, tb, A + a.base);
@@ -436,7 +467,7 @@ __global__ __launch_bounds__(256) void k_zfwd_cg(const T* __restrict__ r, T* __r
   store_z_outputs<T, N, DCT2>(lds, tb, B + a.base);
 }
 
-// q = DST-III_z(A) + DCT-III_z(B) + c d; per-block partial sums of d.q, q, d
+// q = DST-III_z(A) + DCT-III_z(B) + c d; per-block partial sums of d.q, q, d, q.q
 template <typename T, int N>
 __global__ __launch_bounds__(256) void k_zinv_cg(const T* __restrict__ A, const T* __restrict__ B,
                                                 T* __restrict__ q, const T* __restrict__ d, double c,
@@ -488,7 +519,7 @@ __global__ __launch_bounds__(256) void k_zinv_cg(const T* __restrict__ A, const 
   }
   fft_tile<T, N, DCT3>(lds, LdsSrc<T, N>{lds}, tb);
   V16<T>* qv = reinterpret_cast<V16<T>*>(q + a.base);
-  double sdq = 0, sq = 0, sd = 0;
+  double sdq = 0, sq = 0, sd = 0, sqq = 0;
   const T cc = T(c);
 #pragma unroll
   for (int u = 0; u < O::PER_Z; ++u) {
@@ -504,6 +535,7 @@ __global__ __launch_bounds__(256) void k_zinv_cg(const T* __restrict__ A, const 
           const T qn = acc[2 * u + h].a[e] + v[h].a[e] + cc * dvv;
           v[h].a[e] = qn;
           sdq += (double)dvv * (double)qn;
+          sqq += (double)qn * (double)qn;
           sq += (double)qn;
           sd += (double)dvv;
         }
@@ -514,10 +546,12 @@ __global__ __launch_bounds__(256) void k_zinv_cg(const T* __restrict__ A, const 
   double t0 = block_sum(sdq, red);
   double t1 = block_sum(sq, red);
   double t2 = block_sum(sd, red);
+  double t3 = block_sum(sqq, red);
   if (threadIdx.x == 0) {
-    partials[3 * blockIdx.x + 0] = t0;
-    partials[3 * blockIdx.x + 1] = t1;
-    partials[3 * blockIdx.x + 2] = t2;
+    partials[4 * blockIdx.x + 0] = t0;
+    partials[4 * blockIdx.x + 1] = t1;
+    partials[4 * blockIdx.x + 2] = t2;
+    partials[4 * blockIdx.x + 3] = t3;
   }
 }
 
@@ -568,21 +602,45 @@ __global__ __launch_bounds__(256) void k_ypair_inv(const T* __restrict__ A1, con
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(EW_NT) void k_cg_update(int64_t M, T* __restrict__ x, T* __restrict__ r,
-                                                  const T* __restrict__ d, const T* __restrict__ q,
-                                                  const double* __restrict__ scal, double* __restrict__ partials) {
+// CG coefficients after the matvec of iteration k, one block.  rpart: partial sums of r_k.r_k
+// (nr blocks); zpart: partial sums (d.q, q, d, q.q) of q = S d_k (nz blocks).  With q' = q - mean q
+// (Stokes) or q: alpha = r.r / d.q', and, by the conjugacy of d_k and d_{k-1},
+// |r_{k+1}|^2 = alpha^2 q'.q' - r_k.r_k, so beta = |r_{k+1}|^2 / r_k.r_k is known before r_{k+1}
+// is formed (the next forward z pass forms it together with x and d).
+// scal: [0] |r_{k+1}|^2 (recurrence), [1] alpha, [2] beta, [3] mean q, [7] r_k.r_k
+__global__ __launch_bounds__(EW_NT) void k_cg_coef(const double* __restrict__ rpart, int nr,
+                                                const double* __restrict__ zpart, int nz, double* __restrict__ scal,
+                                                int stokes, int64_t M) {
   __shared__ double red[EW_NT / 64];
-  const T alpha = T(scal[1]), mq = T(scal[3]);
-  double s = 0;
-  for (int64_t i = (int64_t)blockIdx.x * EW_NT + threadIdx.x; i < M; i += (int64_t)gridDim.x * EW_NT) {
-    x[i] += alpha * d[i];
-    const T rv = r[i] - alpha * (q[i] - mq);
-    r[i] = rv;
-    s += (double)rv * (double)rv;
+  double acc[5] = {0, 0, 0, 0, 0};
+  for (int i = threadIdx.x; i < nr; i += EW_NT) acc[0] += rpart[i];
+  for (int i = threadIdx.x; i < nz; i += EW_NT)
+    for (int c = 0; c < 4; ++c) acc[1 + c] += zpart[(int64_t)i * 4 + c];
+  double tot[5];
+  for (int c = 0; c < 5; ++c) tot[c] = block_sum(acc[c], red);
+  if (threadIdx.x == 0) {
+    const double rr = tot[0];
+    const double mq = stokes ? tot[2] / (double)M : 0.0;
+    const double dq = tot[1] - mq * tot[3];
+    const double qq = tot[4] - (stokes ? mq * mq * (double)M : 0.0);
+    const double alpha = (dq != 0.0) ? rr / dq : 0.0;
+    double rn = alpha * alpha * qq - rr;
+    if (!(rn > 0.0)) rn = (rn == rn) ? 0.0 : rn;  // a rounding-level negative value means converged
+    scal[0] = rn;
+    scal[1] = alpha;
+    scal[2] = (rr > 0.0) ? rn / rr : 0.0;
+    scal[3] = mq;
+    scal[7] = rr;
   }
-  double t = block_sum(s, red);
-  if (threadIdx.x == 0) partials[blockIdx.x] = t;
+}
+
+// x += scal[idx] d
+template <typename T>
+__global__ __launch_bounds__(EW_NT) void k_axpy_scal(int64_t M, T* __restrict__ x, const T* __restrict__ d,
+                                                  const double* __restrict__ scal, int idx) {
+  const T a = T(scal[idx]);
+  for (int64_t i = (int64_t)blockIdx.x * EW_NT + threadIdx.x; i < M; i += (int64_t)gridDim.x * EW_NT)
+    x[i] += a * d[i];
 }
 
 template <typename T>
@@ -615,15 +673,7 @@ __global__ __launch_bounds__(EW_NT) void k_reduce(const double* __restrict__ par
   double tot[3];
   for (int c = 0; c < 3; ++c) tot[c] = block_sum(c < nper ? acc[c] : 0.0, red);
   if (threadIdx.x == 0) {
-    if (op == R_ALPHA) {
-      const double mq = stokes ? tot[1] / (double)M : 0.0;
-      const double dq = tot[0] - mq * tot[2];
-      scal[1] = (dq != 0.0) ? scal[0] / dq : 0.0;
-      scal[3] = mq;
-    } else if (op == R_BETA) {
-      scal[2] = (scal[0] > 0.0) ? tot[0] / scal[0] : 0.0;
-      scal[0] = tot[0];
-    } else if (op == R_RESNORM || op == R_RESNORM0) {
+    if (op == R_RESNORM || op == R_RESNORM0) {
       // |r_u|^2 + |r_p - mean r_p|^2 (Stokes: the pressure equation is taken modulo constants);
       // R_RESNORM0 also keeps the mean of the pressure part in scal[6]
       scal[5] = tot[0] + tot[2] - (stokes ? tot[1] * tot[1] / (double)M : 0.0);
@@ -1093,27 +1143,34 @@ hipError_t launch_xmid(int N, T* A0, T* A1, T* A2, double mu, const DevTables<T>
 }
 
 template <typename T>
-hipError_t launch_zfwd_cg(int N, const T* r, T* d, T* A, T* B, const double* scal, const DevTables<T>& tb,
-                          hipStream_t s) {
+hipError_t launch_zfwd_cg(int N, int mode, T* x, T* r, T* d, const T* q, T* A, T* B, const double* scal,
+                          double* rpart, const DevTables<T>& tb, hipStream_t s) {
   const Tab<T> t = tab_of(tb);
-#define KFBI_M(NN)                                                                                   \
-  {                                                                                                  \
-    using S = TileCfg<T, NN, DST2>;                                                                  \
-    const int blocks = NN * NN / S::W;                                                               \
-    const size_t lds = S::BYTES;                                                                     \
-    if (d) {                                                                                         \
-      ensure_lds(k_zfwd_cg<T, NN, true>, lds);                                                       \
-      hipLaunchKernelGGL((k_zfwd_cg<T, NN, true>), dim3(blocks), dim3(S::NT), lds, s, r, d, A, B, scal, t); \
-    } else {                                                                                         \
-      ensure_lds(k_zfwd_cg<T, NN, false>, lds);                                                      \
-      hipLaunchKernelGGL((k_zfwd_cg<T, NN, false>), dim3(blocks), dim3(S::NT), lds, s, r, d, A, B, scal, t); \
-    }                                                                                                \
+#define KFBI_ZF(NN, MODE)                                                                                  \
+  {                                                                                                        \
+    using S = TileCfg<T, NN, DST2>;                                                                        \
+    const int blocks = NN * NN / S::W;                                                                     \
+    const size_t lds = S::BYTES;                                                                           \
+    ensure_lds(k_zfwd_cg<T, NN, MODE>, lds);                                                               \
+    hipLaunchKernelGGL((k_zfwd_cg<T, NN, MODE>), dim3(blocks), dim3(S::NT), lds, s, x, r, d, q, A, B, scal, \
+                       rpart, t);                                                                          \
+  }
+#define KFBI_M(NN)            \
+  {                           \
+    if (mode == ZF_FUSED)     \
+      KFBI_ZF(NN, ZF_FUSED)   \
+    else if (mode == ZF_FIRST) \
+      KFBI_ZF(NN, ZF_FIRST)   \
+    else                      \
+      KFBI_ZF(NN, ZF_PLAIN)   \
   }
   KFBI_DISPATCH_N(N, KFBI_M)
 #undef KFBI_M
+#undef KFBI_ZF
   return hipGetLastError();
 }
 
+int zfwd_blocks(int N, int elem_size) { return N * N / std::min(128 / elem_size, N); }
 int zinv_blocks(int N, int elem_size) { return N * N / std::min(128 / elem_size, N); }
 
 template <typename T>
@@ -1183,12 +1240,16 @@ hipError_t launch_ypair(int N, bool inverse, const T* in0, const T* in1, T* out0
 }
 
 template <typename T>
-hipError_t launch_cg_update(int64_t M, T* x, T* r, const T* d, const T* q, const double* scal, double* partials,
-                            int nblocks, hipStream_t s) {
-  hipLaunchKernelGGL((k_cg_update<T>), dim3(nblocks), dim3(EW_NT), 0, s, M, x, r, d, q, scal, partials);
+hipError_t launch_axpy_scal(int64_t M, T* x, const T* d, const double* scal, int idx, hipStream_t s) {
+  hipLaunchKernelGGL((k_axpy_scal<T>), dim3(1024), dim3(EW_NT), 0, s, M, x, d, scal, idx);
   return hipGetLastError();
 }
 
+hipError_t launch_cg_coef(const double* rpart, int nr, const double* zpart, int nz, double* scal, int stokes,
+                          int64_t M, hipStream_t s) {
+  hipLaunchKernelGGL(k_cg_coef, dim3(1), dim3(EW_NT), 0, s, rpart, nr, zpart, nz, scal, stokes, M);
+  return hipGetLastError();
+}
 
 hipError_t launch_reduce(const double* partials, int nparts, int nper, double* scal, int op, int stokes, int64_t M,
                          hipStream_t s, double* out) {
@@ -1320,13 +1381,13 @@ hipError_t launch_check_finite(int64_t n, const double* a, int* flag, hipStream_
 #define KFBI_INST(T)                                                                                                 \
   template hipError_t launch_pass<T>(int, int, int, const T*, T*, bool, const DevTables<T>&, hipStream_t);           \
   template hipError_t launch_xmid<T>(int, T*, T*, T*, double, const DevTables<T>&, hipStream_t);                     \
-  template hipError_t launch_zfwd_cg<T>(int, const T*, T*, T*, T*, const double*, const DevTables<T>&, hipStream_t); \
+  template hipError_t launch_zfwd_cg<T>(int, int, T*, T*, T*, const T*, T*, T*, const double*, double*,               \
+                                        const DevTables<T>&, hipStream_t);                                           \
   template hipError_t launch_ypair<T>(int, bool, const T*, const T*, T*, T*, const DevTables<T>&, hipStream_t);      \
   template hipError_t launch_xfuse<T>(int, int, bool, const T*, T*, T*, double, const DevTables<T>&, hipStream_t);   \
   template hipError_t launch_zinv_cg<T>(int, const T*, const T*, T*, const T*, double, double*, const DevTables<T>&, \
                                         hipStream_t);                                                                \
-  template hipError_t launch_cg_update<T>(int64_t, T*, T*, const T*, const T*, const double*, double*, int,          \
-                                          hipStream_t);                                                              \
+  template hipError_t launch_axpy_scal<T>(int64_t, T*, const T*, const double*, int, hipStream_t);                   \
   template hipError_t launch_dot_partials<T>(int64_t, const T*, const T*, double*, int, hipStream_t);                \
   template hipError_t launch_sum_partials<T>(int64_t, const T*, double*, int, hipStream_t);                          \
   template hipError_t launch_add_scalar<T>(int64_t, T*, const double*, int, double, hipStream_t);                    \
