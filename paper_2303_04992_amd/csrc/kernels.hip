@@ -81,6 +81,119 @@ __device__ __forceinline__ void load_tile_z(T* lds, const T* __restrict__ g) {
 
 
 // ---------------------------------------------------------------------------------------
+// Persistent, software-pipelined transform passes.  A block owns tiles blockIdx.x,
+// blockIdx.x + gridDim.x, ...; the raw rows of its next tile are requested into registers
+// right after the current tile has been staged in LDS, so they arrive while the current tile
+// is transformed.  The transform tables are copied to LDS once per block, so that the
+// transform phase waits on LDS only (a table read from global memory would also wait for the
+// outstanding prefetch, the vector-memory counter being in order).
+// ---------------------------------------------------------------------------------------
+template <typename T, int N, int KIND>
+struct PipeCfg {
+  using S = TileCfg<T, N, KIND>;
+  static constexpr size_t TAB_OFF = (S::BYTES + 15) / 16 * 16;
+  static constexpr size_t BYTES = TAB_OFF + (size_t)(S::L + N) * sizeof(C2<T>) + (size_t)N * sizeof(T);
+  static constexpr int NPAIR = S::NJ * N;                  // element pairs of a tile
+  static constexpr int PER = (NPAIR + S::NT - 1) / S::NT;  // per thread
+};
+
+// twiddles (tw or tw2), mk and the scale table of the kind (sc, or isc for the inverses) in LDS
+template <typename T, int N, int KIND>
+__device__ __forceinline__ Tab<T> tables_to_lds(unsigned char* smem, const Tab<T>& g) {
+  using S = TileCfg<T, N, KIND>;
+  C2<T>* ltw = reinterpret_cast<C2<T>*>(smem + PipeCfg<T, N, KIND>::TAB_OFF);
+  C2<T>* lmk = ltw + S::L;
+  T* lsc = reinterpret_cast<T*>(lmk + N);
+  const C2<T>* gtw = (S::L == N) ? g.tw : g.tw2;
+  const T* gsc = (KIND == DCT3 || KIND == DST3) ? g.isc : g.sc;
+  for (int i = threadIdx.x; i < S::L; i += blockDim.x) ltw[i] = gtw[i];
+  for (int i = threadIdx.x; i < N; i += blockDim.x) {
+    lmk[i] = g.mk[i];
+    lsc[i] = gsc[i];
+  }
+  Tab<T> t = g;
+  t.tw = ltw;
+  t.tw2 = ltw;
+  t.mk = lmk;
+  t.sc = lsc;
+  t.isc = lsc;
+  return t;
+}
+
+// raw element pairs (pencils 2j, 2j+1 at sample n) of an x or y tile: pair e -> (n, j) = (e / NJ, e % NJ)
+template <typename T, int N, int KIND>
+__device__ __forceinline__ void fetch_xy(const T* g, const TileAddr& a, C2<T> (&raw)[PipeCfg<T, N, KIND>::PER]) {
+  using S = TileCfg<T, N, KIND>;
+  using P = PipeCfg<T, N, KIND>;
+#pragma unroll
+  for (int u = 0; u < P::PER; ++u) {
+    const int e = threadIdx.x + u * S::NT;
+    if ((P::NPAIR % S::NT == 0 || e < P::NPAIR) && (int)threadIdx.x < S::NT) {
+      const int n = e / S::NJ, j = e - n * S::NJ;
+      raw[u] = *reinterpret_cast<const C2<T>*>(g + a.base + (long)n * a.nstride + 2 * j);
+    }
+  }
+}
+template <typename T, int N, int KIND>
+__device__ __forceinline__ void stage_xy(T* lds, const C2<T> (&raw)[PipeCfg<T, N, KIND>::PER]) {
+  using S = TileCfg<T, N, KIND>;
+  using P = PipeCfg<T, N, KIND>;
+#pragma unroll
+  for (int u = 0; u < P::PER; ++u) {
+    const int e = threadIdx.x + u * S::NT;
+    if ((P::NPAIR % S::NT == 0 || e < P::NPAIR) && (int)threadIdx.x < S::NT) {
+      const int n = e / S::NJ, j = e - n * S::NJ;
+      lds[(2 * j) * (N + 1) + n] = raw[u].x;
+      lds[(2 * j + 1) * (N + 1) + n] = raw[u].y;
+    }
+  }
+}
+
+template <typename T, int N, int KIND>
+__global__ __launch_bounds__(256) void k_pass_pipe(const T* in, T* out, int axis, int ntiles, Tab<T> tg) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* lds = reinterpret_cast<T*>(smem);
+  using S = TileCfg<T, N, KIND>;
+  constexpr int W = S::W;
+  const Tab<T> tb = tables_to_lds<T, N, KIND>(smem, tg);
+  C2<T> raw[PipeCfg<T, N, KIND>::PER];
+  int tile = blockIdx.x;
+  if (tile < ntiles) fetch_xy<T, N, KIND>(in, tile_addr<W, N>(axis, tile), raw);
+  for (; tile < ntiles; tile += gridDim.x) {
+    __syncthreads();  // the previous tile's outputs have been read from LDS
+    stage_xy<T, N, KIND>(lds, raw);
+    __syncthreads();
+    if (tile + (int)gridDim.x < ntiles) fetch_xy<T, N, KIND>(in, tile_addr<W, N>(axis, tile + gridDim.x), raw);
+    fft_tile<T, N, KIND>(lds, LdsSrc<T, N>{lds}, tb);
+    const TileAddr a = tile_addr<W, N>(axis, tile);
+    store_xy_outputs<T, N, KIND>(lds, tb, out + a.base, a.nstride);
+  }
+}
+
+// resident blocks of a persistent launch: compute units x blocks per unit (occupancy query)
+static int cu_count() {
+  static int n[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (n[dev] == 0) {
+    int v = 0;
+    if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
+    n[dev] = v;
+  }
+  return n[dev];
+}
+// (per_cu caches the occupancy query of one kernel; the caller keeps it in a static)
+template <typename K>
+static int persistent_blocks(K kernel, int threads, size_t lds_bytes, int ntiles, int& per_cu) {
+  if (per_cu < 1) {
+    int v = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, kernel, threads, lds_bytes) != hipSuccess || v < 1) v = 1;
+    per_cu = v;
+  }
+  return std::max(1, std::min(ntiles, cu_count() * per_cu));
+}
+
+// ---------------------------------------------------------------------------------------
 // generic transform pass: out (+)= transform_KIND(in) along axis
 // ---------------------------------------------------------------------------------------
 // (in may equal out: a block reads its whole tile before it writes any output)
@@ -243,6 +356,138 @@ __device__ void xmid_tile(T* lds, T* field, int tile, int mc, double mu, const T
   }
 }
 
+// Register path of the same x pass, for R1 == R2 with one pass-2 task per thread.  The last
+// forward radix pass leaves spectrum values k1 + R1 k2 (k2 < R2) of a job in the registers of
+// the thread that owns k1, which is exactly the input set of the first inverse radix pass of
+// stride R2 with n2 = k1: the weight is applied in registers and the transposes before and
+// after it disappear.  The partner values at N - k are in the thread owning -k1 (mod R1); the
+// pass-2 slots are ordered so that this thread is lane + 32 of the same wavefront (k1 = 0 and
+// k1 = R1/2 hold their own partners), and the values are exchanged by lane shuffles.
+template <int R1, int SW>
+__device__ __forceinline__ int xmid_k1_of_slot(int slot) {
+  constexpr int H = SW / 2;
+  const int w = slot / SW, p = slot % SW;
+  if (p < H) return w * H + p;
+  const int kp = w * H + (p - H);
+  return kp == 0 ? R1 / 2 : R1 - kp;
+}
+
+template <typename T, int N, int KF>
+struct XmidRegs {
+  using S = TileCfg<T, N, KF>;
+  static constexpr int SW = 64 / S::NJ;  // pass-2 slots per wavefront
+  static constexpr bool ok = S::R1 == S::R2 && S::NJ * S::R1 == S::NT && S::NJ * S::R2 == S::NT &&
+                             S::NT % 64 == 0 && 64 % S::NJ == 0 && SW % 2 == 0 && S::R1 % SW == 0;
+};
+
+template <typename T, int N, int KF, int KI>
+__device__ void xmid_tile_regs(T* lds, T* field, int tile, int mc, double mu, const Tab<T>& tb,
+                               C2<T> (&zs)[TileCfg<T, N, KF>::PT1][TileCfg<T, N, KF>::R1]) {
+  using S = TileCfg<T, N, KF>;
+  constexpr int W = S::W, NJ = S::NJ, R1 = S::R1, R2 = S::R2, SW = XmidRegs<T, N, KF>::SW;
+  static_assert(XmidRegs<T, N, KF>::ok, "register path needs R1 == R2 and one task per thread");
+  const TileAddr a = tile_addr<W, N>(0, tile);
+  const int yi = tile / (N / W), z0 = (tile % (N / W)) * W;
+  C2<T>* cb = reinterpret_cast<C2<T>*>(lds);
+  const int tid = threadIdx.x, j = tid % NJ;
+  // forward: pass 1 of task (j, tid / NJ), then pass 2 of task (j, k1) in the paired slot order
+  fft_pass1_dft<T, N, KF>(tid / NJ, zs[0], tb);
+  fft_pass1_store<T, N, KF>(cb, zs[0], j, tid / NJ);
+  __syncthreads();
+  const int k1 = xmid_k1_of_slot<R1, SW>(tid / NJ);
+  C2<T> z[R2];
+  fft_pass2_dft<T, N, KF>(cb, z, j, k1);  // z[k2] = Z_k, k = k1 + R1 k2
+  // Z_{N-k} is register R2 - 1 - k2 of the partner (k1 != 0) or of the thread itself
+  // (k1 = R1/2), and register (R2 - k2) mod R2 of the thread itself for k1 = 0
+  const int lane = tid & 63;
+  const bool own = (k1 == 0) || (2 * k1 == R1);
+  const int src = own ? lane : (lane ^ 32);
+  const bool zero_k1 = (k1 == 0);
+  const bool wave_has_zero = (tid / 64) == 0;  // slot 0 (k1 = 0) is in the first wavefront
+  C2<T> zr[R2];
+#pragma unroll
+  for (int k2 = 0; k2 < R2; ++k2) {
+    zr[k2].x = __shfl(z[R2 - 1 - k2].x, src, 64);
+    zr[k2].y = __shfl(z[R2 - 1 - k2].y, src, 64);
+  }
+  if (wave_has_zero) {
+#pragma unroll
+    for (int k2 = 0; k2 < R2; ++k2)
+      if (zero_k1) zr[k2] = z[(R2 - k2) & (R2 - 1)];
+  }
+  // y and z eigenvalues of the thread's two pencils
+  const T ly = (mc == 1) ? tb.sg2[yi] : tb.sg2s[yi];
+  T lz[2];
+#pragma unroll
+  for (int w = 0; w < 2; ++w) lz[w] = (mc == 2) ? tb.sg2[z0 + 2 * j + w] : tb.sg2s[z0 + 2 * j + w];
+  const T mu2 = T(2 * mu);  // the factor 1/2 of V is folded into the weight denominators
+  T ya[R2], yb[R2];
+#pragma unroll
+  for (int k2 = 0; k2 < R2; ++k2) {
+    const int k = k1 + R1 * k2;
+    const int mode = (KF == DST2) ? N - 1 - k : k;
+    const T lx = (mc == 0) ? tb.sg2[mode] : tb.sg2s[mode];
+    T om[2];
+#pragma unroll
+    for (int w = 0; w < 2; ++w) {
+      const T num = (mc == 0) ? lx : (mc == 1) ? ly : lz[w];
+      const T den = mu2 * (lx + ly + lz[w]);
+      if constexpr (sizeof(T) == 4)
+        om[w] = num * __builtin_amdgcn_rcpf(den);  // 1 ulp: the float32 inner solve
+      else
+        om[w] = num / den;
+    }
+    const C2<T> Zk = z[k2], Zr = zr[k2], mkk = tb.mk[k];
+    const C2<T> Va = {Zk.x + Zr.x, Zk.y - Zr.y};  // 2 V^a_k
+    const C2<T> Vb = {Zk.y + Zr.y, Zr.x - Zk.x};  // 2 V^b_k
+    ya[k2] = om[0] * (mkk.x * Va.x - mkk.y * Va.y);
+    yb[k2] = om[1] * (mkk.x * Vb.x - mkk.y * Vb.y);
+  }
+  // Y_{N-k} from the same place as Z_{N-k} (Y_N = 0)
+  T yar[R2], ybr[R2];
+#pragma unroll
+  for (int k2 = 0; k2 < R2; ++k2) {
+    yar[k2] = __shfl(ya[R2 - 1 - k2], src, 64);
+    ybr[k2] = __shfl(yb[R2 - 1 - k2], src, 64);
+  }
+  if (wave_has_zero) {
+#pragma unroll
+    for (int k2 = 0; k2 < R2; ++k2)
+      if (zero_k1) {
+        yar[k2] = (k2 == 0) ? T(0) : ya[(R2 - k2) & (R2 - 1)];
+        ybr[k2] = (k2 == 0) ? T(0) : yb[(R2 - k2) & (R2 - 1)];
+      }
+  }
+  // inverse input Z'_k = V'^a_k + i V'^b_k, V'_k = conj(mk_k)(Y_k - i Y_{N-k})
+#pragma unroll
+  for (int k2 = 0; k2 < R2; ++k2) {
+    const C2<T> mk = tb.mk[k1 + R1 * k2], ck = {mk.x, -mk.y};
+    const C2<T> Wa = cmul(ck, C2<T>{ya[k2], -yar[k2]}), Wb = cmul(ck, C2<T>{yb[k2], -ybr[k2]});
+    z[k2] = {Wa.x - Wb.y, Wa.y + Wb.x};
+  }
+  // inverse: pass 1 of task (j, n2 = k1) from registers, pass 2 in the natural order
+  fft_pass1_dft<T, N, KI>(k1, z, tb);
+  __syncthreads();  // the forward pass-2 reads of the transpose buffer are done
+  fft_pass1_store<T, N, KI>(cb, z, j, k1);
+  __syncthreads();
+  fft_pass2_dft<T, N, KI>(cb, z, j, tid / NJ);
+  __syncthreads();
+  fft_pass2_store<T, N, KI>(cb, z, j, tid / NJ);
+  __syncthreads();
+  using O = OutItems<T, N, KI>;
+  C2<T>* o = reinterpret_cast<C2<T>*>(field + a.base);
+  const long ns = a.nstride / 2;
+#pragma unroll 4
+  for (int u = 0; u < O::PER_XY; ++u) {
+    int jj, k;
+    if (O::xy(u, jj, k)) {
+      C2<T> v;
+      post_pair<T, N, KI>(lds, tb, jj, k, v.x, v.y);
+      o[k * ns + jj] = v;
+    }
+  }
+}
+
 template <typename T, int N, int KIND>
 __device__ __forceinline__ void store_xy_outputs(const T* lds, const Tab<T>& tb, T* out, long nstride) {
   using O = OutItems<T, N, KIND>;
@@ -350,7 +595,10 @@ __device__ void xmid_body(T* lds, T* field, int mc, double mu, const Tab<T>& tb)
   const GlobSrc<T> src{field, a.base, a.nstride};
   C2<T> zs[S::PT1][S::R1];
   fft_gather<T, N, KF>([&](int j, int n) { return pre_sample<T, N, KF>(src, tb, j, n); }, zs);
-  xmid_tile<T, N, KF, KI>(lds, field, tile, mc, mu, tb, zs);
+  if constexpr (XmidRegs<T, N, KF>::ok)
+    xmid_tile_regs<T, N, KF, KI>(lds, field, tile, mc, mu, tb, zs);
+  else
+    xmid_tile<T, N, KF, KI>(lds, field, tile, mc, mu, tb, zs);
 }
 
 template <typename T, int N>
@@ -608,14 +856,23 @@ __global__ __launch_bounds__(256) void k_ypair_inv(const T* __restrict__ A1, con
 // |r_{k+1}|^2 = alpha^2 q'.q' - r_k.r_k, so beta = |r_{k+1}|^2 / r_k.r_k is known before r_{k+1}
 // is formed (the next forward z pass forms it together with x and d).
 // scal: [0] |r_{k+1}|^2 (recurrence), [1] alpha, [2] beta, [3] mean q, [7] r_k.r_k
-__global__ __launch_bounds__(EW_NT) void k_cg_coef(const double* __restrict__ rpart, int nr,
+constexpr int CG_NT = 1024;  // threads of the coefficient kernel (its loads are latency-bound)
+__global__ __launch_bounds__(CG_NT) void k_cg_coef(const double* __restrict__ rpart, int nr,
                                                 const double* __restrict__ zpart, int nz, double* __restrict__ scal,
                                                 int stokes, int64_t M) {
-  __shared__ double red[EW_NT / 64];
+  __shared__ double red[CG_NT / 64];
   double acc[5] = {0, 0, 0, 0, 0};
-  for (int i = threadIdx.x; i < nr; i += EW_NT) acc[0] += rpart[i];
-  for (int i = threadIdx.x; i < nz; i += EW_NT)
-    for (int c = 0; c < 4; ++c) acc[1 + c] += zpart[(int64_t)i * 4 + c];
+#pragma unroll 2
+  for (int i = threadIdx.x; i < nr; i += CG_NT) acc[0] += rpart[i];
+  const double4* z4 = reinterpret_cast<const double4*>(zpart);
+#pragma unroll 4
+  for (int i = threadIdx.x; i < nz; i += CG_NT) {
+    const double4 v = z4[i];
+    acc[1] += v.x;
+    acc[2] += v.y;
+    acc[3] += v.z;
+    acc[4] += v.w;
+  }
   double tot[5];
   for (int c = 0; c < 5; ++c) tot[c] = block_sum(acc[c], red);
   if (threadIdx.x == 0) {
@@ -1094,6 +1351,18 @@ static hipError_t pass_n(int axis, const T* in, T* out, const Tab<T>& tb, hipStr
   using S = TileCfg<T, N, KIND>;
   const size_t lds = S::BYTES;
   const int blocks = N * N / S::W;
+  // the inverse kinds read two samples per FFT input, which the staged tile serves from LDS;
+  // for the forward kinds the direct gather measured faster
+  if constexpr (PipeCfg<T, N, KIND>::BYTES <= 163840 && !ACC && (KIND == DCT3 || KIND == DST3)) {
+    if (axis != 2) {
+      using P = PipeCfg<T, N, KIND>;
+      ensure_lds(k_pass_pipe<T, N, KIND>, P::BYTES);
+      static int per_cu = 0;
+      const int pb = persistent_blocks(k_pass_pipe<T, N, KIND>, S::NT, P::BYTES, blocks, per_cu);
+      hipLaunchKernelGGL((k_pass_pipe<T, N, KIND>), dim3(pb), dim3(S::NT), P::BYTES, s, in, out, axis, blocks, tb);
+      return hipGetLastError();
+    }
+  }
   ensure_lds(k_pass<T, N, KIND, ACC>, lds);
   hipLaunchKernelGGL((k_pass<T, N, KIND, ACC>), dim3(blocks), dim3(S::NT), lds, s, in, out, axis, tb);
   return hipGetLastError();
@@ -1247,7 +1516,7 @@ hipError_t launch_axpy_scal(int64_t M, T* x, const T* d, const double* scal, int
 
 hipError_t launch_cg_coef(const double* rpart, int nr, const double* zpart, int nz, double* scal, int stokes,
                           int64_t M, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_coef, dim3(1), dim3(EW_NT), 0, s, rpart, nr, zpart, nz, scal, stokes, M);
+  hipLaunchKernelGGL(k_cg_coef, dim3(1), dim3(CG_NT), 0, s, rpart, nr, zpart, nz, scal, stokes, M);
   return hipGetLastError();
 }
 

@@ -244,15 +244,52 @@ __device__ void fft_core(T* lds, Sampler&& sample, const Tab<T>& tb) {
   fft_core_from<T, N, KIND>(lds, z, tb);
 }
 
+// Pass 1 of one task (j, n2): R1-point DFT of its samples and the L-point twiddles
+template <typename T, int N, int KIND>
+__device__ __forceinline__ void fft_pass1_dft(int n2, C2<T> (&z)[TileCfg<T, N, KIND>::R1], const Tab<T>& tb) {
+  using S = TileCfg<T, N, KIND>;
+  constexpr bool INV = (KIND == DCT3 || KIND == DST3);
+  const C2<T>* tw = (S::L == N) ? tb.tw : tb.tw2;
+  dftR<T, S::R1, INV>(z);
+#pragma unroll
+  for (int k1 = 1; k1 < S::R1; ++k1) {
+    C2<T> w = tw[n2 * k1];
+    if (INV) w.y = -w.y;
+    z[k1] = cmul(z[k1], w);
+  }
+}
+// ... and its transposed store
+template <typename T, int N, int KIND>
+__device__ __forceinline__ void fft_pass1_store(C2<T>* cb, const C2<T> (&z)[TileCfg<T, N, KIND>::R1], int j,
+                                                int n2) {
+  using S = TileCfg<T, N, KIND>;
+#pragma unroll
+  for (int k1 = 0; k1 < S::R1; ++k1) cb[j * S::YS + k1 * S::P2 + n2] = z[k1];
+}
+// Pass 2 of one task (j, k1): z[k2] = spectrum value k1 + R1 k2 of job j
+template <typename T, int N, int KIND>
+__device__ __forceinline__ void fft_pass2_dft(const C2<T>* cb, C2<T> (&z)[TileCfg<T, N, KIND>::R2], int j, int k1) {
+  using S = TileCfg<T, N, KIND>;
+  constexpr bool INV = (KIND == DCT3 || KIND == DST3);
+#pragma unroll
+  for (int n2 = 0; n2 < S::R2; ++n2) z[n2] = cb[j * S::YS + k1 * S::P2 + n2];
+  dftR<T, S::R2, INV>(z);
+}
+template <typename T, int N, int KIND>
+__device__ __forceinline__ void fft_pass2_store(C2<T>* cb, const C2<T> (&z)[TileCfg<T, N, KIND>::R2], int j,
+                                                int k1) {
+  using S = TileCfg<T, N, KIND>;
+#pragma unroll
+  for (int k2 = 0; k2 < S::R2; ++k2) cb[j * S::ZS + k1 + S::R1 * k2] = z[k2];
+}
+
 // The FFTs from the pass-1 samples already in registers (z is overwritten).
 template <typename T, int N, int KIND>
 __device__ void fft_core_from(T* lds, C2<T> (&z)[TileCfg<T, N, KIND>::PT1][TileCfg<T, N, KIND>::R1],
                               const Tab<T>& tb) {
   using S = TileCfg<T, N, KIND>;
-  constexpr int L = S::L, NJ = S::NJ, R1 = S::R1, R2 = S::R2, P2 = S::P2, YS = S::YS, ZS = S::ZS, NT = S::NT;
-  constexpr bool INV = (KIND == DCT3 || KIND == DST3);
+  constexpr int NJ = S::NJ, R1 = S::R1, R2 = S::R2, NT = S::NT;
   C2<T>* cb = reinterpret_cast<C2<T>*>(lds);
-  const C2<T>* tw = (L == N) ? tb.tw : tb.tw2;
   const int tid = threadIdx.x;
   // ---------------- pass 1: R1-point DFTs over stride-R2 samples, twiddle, transpose
   {
@@ -261,26 +298,13 @@ __device__ void fft_core_from(T* lds, C2<T> (&z)[TileCfg<T, N, KIND>::PT1][TileC
 #pragma unroll
     for (int u = 0; u < PT; ++u) {
       const int task = tid + u * NT;
-      if ((TASKS % NT == 0 || task < TASKS) && tid < NT) {
-        const int n2 = task / NJ;
-        dftR<T, R1, INV>(z[u]);
-#pragma unroll
-        for (int k1 = 1; k1 < R1; ++k1) {
-          C2<T> w = tw[n2 * k1];
-          if (INV) w.y = -w.y;
-          z[u][k1] = cmul(z[u][k1], w);
-        }
-      }
+      if ((TASKS % NT == 0 || task < TASKS) && tid < NT) fft_pass1_dft<T, N, KIND>(task / NJ, z[u], tb);
     }
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < PT; ++u) {
       const int task = tid + u * NT;
-      if ((TASKS % NT == 0 || task < TASKS) && tid < NT) {
-        const int j = task % NJ, n2 = task / NJ;
-#pragma unroll
-        for (int k1 = 0; k1 < R1; ++k1) cb[j * YS + k1 * P2 + n2] = z[u][k1];
-      }
+      if ((TASKS % NT == 0 || task < TASKS) && tid < NT) fft_pass1_store<T, N, KIND>(cb, z[u], task % NJ, task / NJ);
     }
     __syncthreads();
   }
@@ -288,26 +312,17 @@ __device__ void fft_core_from(T* lds, C2<T> (&z)[TileCfg<T, N, KIND>::PT1][TileC
   {
     constexpr int TASKS = NJ * R1;
     constexpr int PT = (TASKS + NT - 1) / NT;
-    C2<T> z[PT][R2];
+    C2<T> z2[PT][R2];
 #pragma unroll
     for (int u = 0; u < PT; ++u) {
       const int task = tid + u * NT;
-      if ((TASKS % NT == 0 || task < TASKS) && tid < NT) {
-        const int j = task % NJ, k1 = task / NJ;
-#pragma unroll
-        for (int n2 = 0; n2 < R2; ++n2) z[u][n2] = cb[j * YS + k1 * P2 + n2];
-        dftR<T, R2, INV>(z[u]);
-      }
+      if ((TASKS % NT == 0 || task < TASKS) && tid < NT) fft_pass2_dft<T, N, KIND>(cb, z2[u], task % NJ, task / NJ);
     }
     __syncthreads();
 #pragma unroll
     for (int u = 0; u < PT; ++u) {
       const int task = tid + u * NT;
-      if ((TASKS % NT == 0 || task < TASKS) && tid < NT) {
-        const int j = task % NJ, k1 = task / NJ;
-#pragma unroll
-        for (int k2 = 0; k2 < R2; ++k2) cb[j * ZS + k1 + R1 * k2] = z[u][k2];
-      }
+      if ((TASKS % NT == 0 || task < TASKS) && tid < NT) fft_pass2_store<T, N, KIND>(cb, z2[u], task % NJ, task / NJ);
     }
     __syncthreads();
   }
