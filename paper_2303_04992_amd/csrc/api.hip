@@ -72,7 +72,7 @@ struct MacSolver {
   double* partials = nullptr;
   double* rpart = nullptr;  // partial r.r of the forward z pass
   double* scal = nullptr;
-  double* host_rr = nullptr;  // pinned, 2 slots
+  double* host_rr = nullptr;  // pinned: [0], [1] look-ahead slots, [2] r.r of the start
   hipEvent_t ev[2] = {nullptr, nullptr};
   int nparts_x = 0, nparts_z = 0, nparts_u = 1024;
   // live timing of one transform-pass kind with HIP events on the solver stream
@@ -141,7 +141,7 @@ struct MacSolver {
     partials = dalloc<double>(std::max(4 * nparts_x, nparts_u), owned);
     rpart = dalloc<double>(nparts_z, owned);
     scal = dalloc<double>(16, owned);
-    HIPCHK(hipHostMalloc((void**)&host_rr, 2 * sizeof(double), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&host_rr, 4 * sizeof(double), hipHostMallocDefault));
     HIPCHK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
   }
@@ -254,13 +254,11 @@ struct MacSolver {
     HIPCHK(hipMemcpyAsync(r, b, M * sizeof(T), hipMemcpyDeviceToDevice, s));
     HIPCHK(launch_dot_partials<T>(M, r, r, partials, nparts_u, s));
     HIPCHK(launch_reduce(partials, nparts_u, 1, scal, R_INIT_RR, 0, M, s));
-    double rr0 = 0;
-    HIPCHK(hipMemcpyAsync(&host_rr[0], scal, sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    rr0 = host_rr[0];
+    // r.r of the start is read at the first check (no synchronisation before the first
+    // iterations are queued; b = 0 converges at that check with x = 0)
+    HIPCHK(hipMemcpyAsync(&host_rr[2], scal, sizeof(double), hipMemcpyDeviceToHost, s));
     int it = 0;
-    bool conv = (rr0 == 0.0);
-    const double thr = rtol * rtol * rr0;
+    bool conv = false;
     // one iteration of look-ahead: iteration k+1 is queued before the residual of k is read
     while (!conv && it < maxit) {
       cg_iteration(it == 0);
@@ -269,15 +267,16 @@ struct MacSolver {
       ++it;
       if (it >= 2) {
         HIPCHK(hipEventSynchronize(ev[(it - 2) & 1]));
-        if (!(host_rr[(it - 2) & 1] > thr)) conv = true;
+        if (!(host_rr[(it - 2) & 1] > rtol * rtol * host_rr[2])) conv = true;
         if (std::isnan(host_rr[(it - 2) & 1])) throw DevErr{"NaN in the Schur CG residual"};
       }
     }
     if (it > 0) HIPCHK(launch_axpy_scal<T>(M, x, d, scal, 1, s));  // the pending x += alpha d
-    HIPCHK(hipStreamSynchronize(s));
     if (!conv && it > 0) {
-      double last = host_rr[(it - 1) & 1];
-      if (!(last > thr)) conv = true;
+      HIPCHK(hipEventSynchronize(ev[(it - 1) & 1]));
+      const double last = host_rr[(it - 1) & 1];
+      if (std::isnan(last)) throw DevErr{"NaN in the Schur CG residual"};
+      if (!(last > rtol * rtol * host_rr[2])) conv = true;
     }
     project_mean(x);
     // 4. velocity back-substitution u_m = T_m^T [(T_m F_m + sigma C_m p) / Lambda_m]: C_m p along
@@ -351,7 +350,13 @@ struct kfbi_ctx {
   double *pr_w = nullptr, *prT_w = nullptr;
   int gm_max = 0;
   kfbi_info last;
+  // pinned host scalars read after a later synchronisation, and the stage events of an evaluation
+  double* hpin = nullptr;
+  hipEvent_t sev[4] = {nullptr, nullptr, nullptr, nullptr};
   ~kfbi_ctx() {
+    if (hpin) (void)hipHostFree(hpin);
+    for (auto& e : sev)
+      if (e) (void)hipEventDestroy(e);
     s64.release();
     s32.release();
     for (void* q : owned) (void)hipFree(q);
@@ -419,6 +424,8 @@ kfbi_status kfbi_create(const kfbi_config* cfg_in, kfbi_ctx** out) {
       HIPCHK(hipStreamCreate(&C->s));
     hipStream_t s = C->s;
     auto& o = C->owned;
+    HIPCHK(hipHostMalloc((void**)&C->hpin, 16 * sizeof(double), hipHostMallocDefault));
+    for (auto& e : C->sev) HIPCHK(hipEventCreate(&e));
     C->M = S.M;
     C->nb_ptr = dupload(S.nb_ptr, o, s);
     C->nb_idx = dupload(S.nb_idx, o, s);
@@ -575,29 +582,19 @@ int mac_solve(kfbi_ctx* C, const double* F, double* u, double* p, kfbi_info* inf
   const bool stokes = S.pde == KFBI_STOKES;
   const double c = stokes ? 0.0 : 1.0 / (S.lam + S.mu);
   constexpr int NP = 1024;  // blocks of the fused passes (3 partial sums each; 2048 measured slower)
-  auto norm = [&](int op) {
-    HIPCHK(launch_reduce(C->rpart, NP, 3, C->rscal, op, stokes, M, s));
-    double h2 = 0;
-    HIPCHK(hipMemcpyAsync(&h2, C->rscal + 5, sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(hipStreamSynchronize(s));
-    return std::sqrt(std::max(h2, 0.0));
-  };
+  // |F| is copied to pinned memory and read with the first residual norm: the first inner
+  // solve is queued without a synchronisation (F = 0 gives x32 = 0 and a zero residual)
   HIPCHK(launch_refine_prep(M, F, C->r32, C->rpart, NP, s));
-  const double f0 = norm(R_RESNORM0);
+  HIPCHK(launch_reduce(C->rpart, NP, 3, C->rscal, R_RESNORM0, stokes, M, s));
+  HIPCHK(hipMemcpyAsync(C->hpin + 1, C->rscal + 5, sizeof(double), hipMemcpyDeviceToHost, s));
   const double* shift = stokes ? C->rscal + 6 : nullptr;  // mean of F_p (Stokes)
-  if (!(f0 > 0)) {
-    HIPCHK(launch_fill<double>(3 * M, u, 0.0, s));
-    HIPCHK(launch_fill<double>(M, p, 0.0, s));
-    if (info) info->refine_rounds = 0;
-    return 0;
-  }
   // the iterate alternates between (u, p) and the spare float64 fields (neighbour values of
   // the old iterate are read while the new one is written)
   double* cu = u;
   double* cp = p;
   int total = 0, rounds = 0;
-  double rn = f0;
-  while (rn > C->cfg.cg_rtol * f0) {
+  double rn = 1.0, f0 = 0.0;
+  while (rounds == 0 || rn > C->cfg.cg_rtol * f0) {
     if (rounds >= 30) throw std::runtime_error("ENOCONV: mixed refinement did not converge");
     int it = C->s32.solve(C->r32, C->r32 + 3 * M, C->x32, C->x32 + 3 * M, C->cfg.inner_rtol, C->cfg.cg_maxit);
     if (it < 0) throw std::runtime_error("ENOCONV: inner float32 CG reached cg_maxit");
@@ -608,7 +605,12 @@ int mac_solve(kfbi_ctx* C, const double* F, double* u, double* p, kfbi_info* inf
                                   NP, s));
     cu = nu;
     cp = np;
-    rn = norm(R_RESNORM);
+    HIPCHK(launch_reduce(C->rpart, NP, 3, C->rscal, R_RESNORM, stokes, M, s));
+    HIPCHK(hipMemcpyAsync(C->hpin, C->rscal + 5, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    rn = std::sqrt(std::max(C->hpin[0], 0.0));
+    f0 = std::sqrt(std::max(C->hpin[1], 0.0));
+    if (std::isnan(rn) || std::isnan(f0)) throw DevErr{"NaN in the refinement residual"};
     ++rounds;
   }
   if (cu != u) {
@@ -630,23 +632,23 @@ int mac_solve(kfbi_ctx* C, const double* F, double* u, double* p, kfbi_info* inf
 void eval_impl(kfbi_ctx* C, const double* phi, double* out, bool vol, kfbi_info* info) {
   const Setup& S = C->S;
   hipStream_t s = C->s;
-  double t0 = now_ms();
+  // stage times from events on the stream (no synchronisation between the stages)
+  HIPCHK(hipEventRecord(C->sev[0], s));
   assemble_rhs(C, phi, vol);
-  HIPCHK(hipStreamSynchronize(s));
-  double t1 = now_ms();
+  HIPCHK(hipEventRecord(C->sev[1], s));
   mac_solve(C, C->F, C->u, C->p, info);
-  HIPCHK(hipStreamSynchronize(s));
-  double t2 = now_ms();
+  HIPCHK(hipEventRecord(C->sev[2], s));
   HIPCHK(launch_interp(S.n, C->itp_idx, C->itp_w, C->u, C->ejump, out, s));
   if (C->cfg.trace == KFBI_TRACE_AVERAGE)
     HIPCHK(launch_stab(S.n, C->sv_ptr, C->sv_idx, C->sv_w, C->stab_a, phi, out, s));
-  HIPCHK(hipStreamSynchronize(s));
-  double t3 = now_ms();
+  HIPCHK(hipEventRecord(C->sev[3], s));
+  HIPCHK(hipEventSynchronize(C->sev[3]));
   if (info) {
-    info->ms_stage[0] += t1 - t0;
-    info->ms_stage[1] += t2 - t1;
-    info->ms_stage[2] += t3 - t2;
-    info->ms_total += t3 - t0;
+    float ms[4] = {0, 0, 0, 0};
+    for (int k = 0; k < 3; ++k) HIPCHK(hipEventElapsedTime(&ms[k], C->sev[k], C->sev[k + 1]));
+    HIPCHK(hipEventElapsedTime(&ms[3], C->sev[0], C->sev[3]));
+    for (int k = 0; k < 3; ++k) info->ms_stage[k] += ms[k];
+    info->ms_total += ms[3];
   }
 }
 
