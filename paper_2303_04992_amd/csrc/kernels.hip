@@ -806,16 +806,32 @@ __global__ __launch_bounds__(256) void k_zinv_cg(const T* __restrict__ A, const 
 // y passes of the Schur matvec with two transforms per block.
 // forward: A1 = DST-II_y(A), B2 = DCT-II_y(A) (the tile of A is read twice, the second time
 // from L2); inverse: A = DST-III_y(A1) + DCT-III_y(B2)
+// The DST-II input is the DCT-II input (Makhoul order) with the samples from the second half of
+// the reordered pencil negated: one gather serves both transforms, A is read once.
 template <typename T, int N>
 __global__ __launch_bounds__(256) void k_ypair_fwd(const T* __restrict__ A, T* __restrict__ A1, T* __restrict__ B2,
                                                   Tab<T> tb) {
   extern __shared__ __align__(16) unsigned char smem[];
   T* lds = reinterpret_cast<T*>(smem);
-  constexpr int W = TileCfg<T, N, DST2>::W;
+  using S = TileCfg<T, N, DCT2>;
+  static_assert(S::R1 == TileCfg<T, N, DST2>::R1 && S::R2 == TileCfg<T, N, DST2>::R2, "one gather for both kinds");
+  constexpr int W = S::W, R1 = S::R1, R2 = S::R2;
   const TileAddr a = tile_addr<W, N>(1, blockIdx.x);
-  fft_tile<T, N, DST2>(lds, GlobSrc<T>{A, a.base, a.nstride}, tb);
+  const GlobSrc<T> src{A, a.base, a.nstride};
+  C2<T> zc[S::PT1][R1], zs[S::PT1][R1];
+  fft_gather<T, N, DCT2>([&](int j, int n) { return pre_sample<T, N, DCT2>(src, tb, j, n); }, zc);
+#pragma unroll
+  for (int u = 0; u < S::PT1; ++u)
+#pragma unroll
+    for (int n1 = 0; n1 < R1; ++n1) {
+      // sample R2 n1 + n2 (n2 < R2) comes from an odd source index iff R2 n1 + n2 >= N/2
+      static_assert((N / 2) % R2 == 0, "the sign of a sample depends on n1 only");
+      const bool odd = R2 * n1 >= N / 2;
+      zs[u][n1] = odd ? C2<T>{-zc[u][n1].x, -zc[u][n1].y} : zc[u][n1];
+    }
+  fft_core_from<T, N, DST2>(lds, zs, tb);
   store_xy_outputs<T, N, DST2>(lds, tb, A1 + a.base, a.nstride);
-  fft_tile<T, N, DCT2>(lds, GlobSrc<T>{A, a.base, a.nstride}, tb);
+  fft_core_from<T, N, DCT2>(lds, zc, tb);
   store_xy_outputs<T, N, DCT2>(lds, tb, B2 + a.base, a.nstride);
 }
 
