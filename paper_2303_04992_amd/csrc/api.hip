@@ -199,11 +199,11 @@ struct MacSolver {
     }
     prof_used = 0;
   }
-  void project_mean(T* v) {
-    if (pde != KFBI_STOKES) return;
+  // v -= mean v; the sum of v is left in scal[keep] when keep >= 0
+  void project_mean(T* v, int keep = -1) {
     HIPCHK(launch_sum_partials<T>(M, v, partials, nparts_u, s));
-    HIPCHK(launch_reduce(partials, nparts_u, 1, scal, R_SUM, 1, M, s));
-    HIPCHK(launch_add_scalar<T>(M, v, scal, 5, -1.0 / (double)M, s));
+    HIPCHK(launch_reduce(partials, nparts_u, 1, scal, R_SUM, 1, M, s, keep >= 0 ? scal + keep : nullptr));
+    HIPCHK(launch_add_scalar<T>(M, v, scal, keep >= 0 ? keep : 5, -1.0 / (double)M, s));
   }
 
   // S p for the CG direction d (q = S d); the updates of x, r (previous iteration) and of
@@ -228,7 +228,7 @@ struct MacSolver {
     yinv();                // A = DST_y^T A1 + DCT_y^T B2 (components 0 and 1 share DST_z)
     pass(DST3, 1, B3, B);
     zinv();                // q = DST_z^T A + DCT_z^T B + c d, partial dots
-    HIPCHK(launch_cg_coef(rpart, nparts_z, partials, nparts_x, scal, pde == KFBI_STOKES, M, s));
+    HIPCHK(launch_cg_coef(rpart, nparts_z, partials, nparts_x, scal, 1, M, s));  // mean-zero iterates
   }
 
   // Solve A_u u + G p = F_u, D u + c p = F_p (Stokes: D u = F_p - mean F_p, mean p = 0).
@@ -247,7 +247,12 @@ struct MacSolver {
     HIPCHK(launch_ypair<T>(N, true, A1, B2, A, A, tb, s));       // A = DST_y^T H0 + DCT_y^T H1
     pass(DST3, 1, B3, B);                                        // B = DST_y^T H2
     HIPCHK(launch_zinv_cg<T>(N, A, B, b, Fp, 1.0, partials, tb, s));  // b = DST_z^T A + DCT_z^T B + F_p
-    project_mean(b);
+    // Both PDEs iterate on mean-zero pressures.  S = S_0 + cI with S_0 1 = 0 (G annihilates
+    // constants, sigma_0 = 0) and S_0 symmetric, so the mean of S p is c mean(p): for Navier
+    // (c > 0) the constant mode, whose eigenvalue c = 1/(lambda + mu) is the smallest of S and
+    // grows the iteration count as nu -> 1/2, is solved exactly, mean(p) = mean(b) / c, and CG
+    // runs on the mean-zero part.  Stokes (c = 0): P b, mean(p) = 0.
+    project_mean(b, 9);
     // 3. CG on S x = b.  Iteration k forms x_k, r_k (with alpha_{k-1}) and d_k in its first
     // pass, so x lags one step until the final x += alpha d.
     HIPCHK(launch_fill<T>(M, x, T(0), s));
@@ -279,6 +284,7 @@ struct MacSolver {
       if (!(last > rtol * rtol * host_rr[2])) conv = true;
     }
     project_mean(x);
+    if (c > 0) HIPCHK(launch_add_scalar<T>(M, x, scal, 9, 1.0 / ((double)M * c), s));  // + mean(b) / c
     // 4. velocity back-substitution u_m = T_m^T [(T_m F_m + sigma C_m p) / Lambda_m]: C_m p along
     // z and y shared as in the matvec, then per component the fused x pass and the y, z inverses
     // A = DST_z p, B = DCT_z p
