@@ -255,18 +255,18 @@ struct MacSolver {
     project_mean(b, 9);
     // 3. CG on S x = b.  Iteration k forms x_k, r_k (with alpha_{k-1}) and d_k in its first
     // pass, so x lags one step until the final x += alpha d.
+    // The residual starts as b itself (b is not needed afterwards: the buffers swap roles), and
+    // the first iteration's coefficient kernel leaves r.r of the start in scal[7], read at the
+    // first check (no synchronisation before the first iterations are queued; b = 0 converges
+    // at that check with x = 0).
     HIPCHK(launch_fill<T>(M, x, T(0), s));
-    HIPCHK(hipMemcpyAsync(r, b, M * sizeof(T), hipMemcpyDeviceToDevice, s));
-    HIPCHK(launch_dot_partials<T>(M, r, r, partials, nparts_u, s));
-    HIPCHK(launch_reduce(partials, nparts_u, 1, scal, R_INIT_RR, 0, M, s));
-    // r.r of the start is read at the first check (no synchronisation before the first
-    // iterations are queued; b = 0 converges at that check with x = 0)
-    HIPCHK(hipMemcpyAsync(&host_rr[2], scal, sizeof(double), hipMemcpyDeviceToHost, s));
+    std::swap(r, b);
     int it = 0;
     bool conv = false;
     // one iteration of look-ahead: iteration k+1 is queued before the residual of k is read
     while (!conv && it < maxit) {
       cg_iteration(it == 0);
+      if (it == 0) HIPCHK(hipMemcpyAsync(&host_rr[2], scal + 7, sizeof(double), hipMemcpyDeviceToHost, s));
       HIPCHK(hipMemcpyAsync(&host_rr[it & 1], scal, sizeof(double), hipMemcpyDeviceToHost, s));
       HIPCHK(hipEventRecord(ev[it & 1], s));
       ++it;
