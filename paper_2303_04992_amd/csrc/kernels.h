@@ -69,8 +69,9 @@ hipError_t launch_cg_coef(const double* rpart, int nr, const double* zpart, int 
                           int64_t M, hipStream_t s);
 
 // ---- reductions (float64, deterministic)
-// scal layout: [0] rr, [1] alpha, [2] beta, [3] mean q, [4] rr0, [5] scratch sum, [6] aux, [7] r.r
-enum ReduceOp { R_SUM = 2, R_INIT_RR = 3, R_RESNORM = 4, R_RESNORM0 = 5 };
+// scal layout: [0] |r_next|^2, [1] alpha, [2] beta, [3] mean q, [5] scratch sum, [6] aux, [7] r.r,
+// [9] sum of the right-hand side
+enum ReduceOp { R_SUM = 2, R_RESNORM = 4, R_RESNORM0 = 5 };
 hipError_t launch_reduce(const double* partials, int nparts, int nper, double* scal, int op, int stokes,
                          int64_t M, hipStream_t s, double* out = nullptr);  // R_SUM: *out (or scal[5])
 template <typename T>

@@ -12,6 +12,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 
 #include "kernels.h"
 #include "trig.h"
@@ -51,6 +52,26 @@ __device__ __forceinline__ double block_sum(double v, double* sh) {
   if (threadIdx.x == 0)
     for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r += sh[w];
   return r;
+}
+
+// four block sums with one exchange through LDS (sh holds 4 * waves doubles); the totals are
+// valid in thread 0
+__device__ __forceinline__ void block_sum4(double (&v)[4], double* sh) {
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < 4; ++c) v[c] = wave_sum(v[c]);
+  __syncthreads();
+  if (lane == 0)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) sh[4 * wid + c] = v[c];
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      double r = 0;
+      for (int w = 0; w < (int)(blockDim.x >> 6); ++w) r += sh[4 * w + c];
+      v[c] = r;
+    }
 }
 
 constexpr int EW_NT = 256;  // threads per block of the elementwise and reduction kernels
@@ -172,25 +193,26 @@ __global__ __launch_bounds__(256) void k_pass_pipe(const T* in, T* out, int axis
 
 // resident blocks of a persistent launch: compute units x blocks per unit (occupancy query)
 static int cu_count() {
-  static int n[64] = {0};
+  static std::atomic<int> n[64];  // per device; 0 = not queried yet (racing threads store the same value)
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
-  if (n[dev] == 0) {
-    int v = 0;
+  int v = n[dev].load(std::memory_order_relaxed);
+  if (v == 0) {
     if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || v <= 0) v = 256;
-    n[dev] = v;
+    n[dev].store(v, std::memory_order_relaxed);
   }
-  return n[dev];
+  return v;
 }
-// (per_cu caches the occupancy query of one kernel; the caller keeps it in a static)
+// (per_cu caches the occupancy query of one kernel; the caller keeps it in a static, and
+// racing threads store the same value)
 template <typename K>
-static int persistent_blocks(K kernel, int threads, size_t lds_bytes, int ntiles, int& per_cu) {
-  if (per_cu < 1) {
-    int v = 0;
+static int persistent_blocks(K kernel, int threads, size_t lds_bytes, int ntiles, std::atomic<int>& per_cu) {
+  int v = per_cu.load(std::memory_order_relaxed);
+  if (v < 1) {
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&v, kernel, threads, lds_bytes) != hipSuccess || v < 1) v = 1;
-    per_cu = v;
+    per_cu.store(v, std::memory_order_relaxed);
   }
-  return std::max(1, std::min(ntiles, cu_count() * per_cu));
+  return std::max(1, std::min(ntiles, cu_count() * v));
 }
 
 // ---------------------------------------------------------------------------------------
@@ -721,7 +743,7 @@ __global__ __launch_bounds__(256) void k_zinv_cg(const T* __restrict__ A, const 
                                                 T* __restrict__ q, const T* __restrict__ d, double c,
                                                 double* __restrict__ partials, Tab<T> tb) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ double red[4];
+  __shared__ double red[16];  // 4 sums x up to 4 wavefronts
   T* lds = reinterpret_cast<T*>(smem);
   using S = TileCfg<T, N, DCT3>;
   using O = OutItems<T, N, DCT3>;
@@ -791,16 +813,11 @@ __global__ __launch_bounds__(256) void k_zinv_cg(const T* __restrict__ A, const 
       }
     }
   }
-  double t0 = block_sum(sdq, red);
-  double t1 = block_sum(sq, red);
-  double t2 = block_sum(sd, red);
-  double t3 = block_sum(sqq, red);
-  if (threadIdx.x == 0) {
-    partials[4 * blockIdx.x + 0] = t0;
-    partials[4 * blockIdx.x + 1] = t1;
-    partials[4 * blockIdx.x + 2] = t2;
-    partials[4 * blockIdx.x + 3] = t3;
-  }
+  double t[4] = {sdq, sq, sd, sqq};
+  block_sum4(t, red);
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int c = 0; c < 4; ++c) partials[4 * blockIdx.x + c] = t[c];
 }
 
 // y passes of the Schur matvec with two transforms per block.
@@ -951,10 +968,6 @@ __global__ __launch_bounds__(EW_NT) void k_reduce(const double* __restrict__ par
       // R_RESNORM0 also keeps the mean of the pressure part in scal[6]
       scal[5] = tot[0] + tot[2] - (stokes ? tot[1] * tot[1] / (double)M : 0.0);
       if (op == R_RESNORM0) scal[6] = tot[1] / (double)M;
-    } else if (op == R_INIT_RR) {
-      scal[0] = tot[0];
-      scal[4] = tot[0];
-      scal[2] = 0.0;
     } else {
       if (out)
         *out = tot[0];
@@ -1376,7 +1389,7 @@ static hipError_t pass_n(int axis, const T* in, T* out, const Tab<T>& tb, hipStr
     if (axis != 2) {
       using P = PipeCfg<T, N, KIND>;
       ensure_lds(k_pass_pipe<T, N, KIND>, P::BYTES);
-      static int per_cu = 0;
+      static std::atomic<int> per_cu{0};
       const int pb = persistent_blocks(k_pass_pipe<T, N, KIND>, S::NT, P::BYTES, blocks, per_cu);
       hipLaunchKernelGGL((k_pass_pipe<T, N, KIND>), dim3(pb), dim3(S::NT), P::BYTES, s, in, out, axis, blocks, tb);
       return hipGetLastError();
