@@ -167,7 +167,7 @@ kfbi_status kfbi_solve_adjoint(kfbi_ctx* ctx, const double* rhs_dev, double* y_d
  * fused kernels of one Schur-complement CG iteration. */
 enum {
   KFBI_K_XMID = 5, /* x: forward transform, spectral weight, inverse, three components */
-  KFBI_K_ZFWD = 6, /* d = r + beta d, DST-II_z d and DCT-II_z d */
+  KFBI_K_ZFWD = 6, /* x += alpha d, r -= alpha (q - mean q), d = r + beta d, DST-II_z d and DCT-II_z d */
   KFBI_K_ZINV = 7, /* q = DST-III_z A + DCT-III_z B + c d, partial dot products */
   KFBI_K_YFWD = 8, /* DST-II_y A and DCT-II_y A */
   KFBI_K_YINV = 9  /* DST-III_y A1 + DCT-III_y B2 */
@@ -178,7 +178,7 @@ enum {
  * solver) reps times back to back on the context stream between two HIP events, on the
  * solver's own work fields (contents are overwritten).  Returns the mean duration of one
  * launch and the algorithmic HBM bytes of one launch (one read or write per N^3 field
- * touched: 2 fields for a transform pass, 6 XMID, 5 ZFWD, 4 ZINV, 3 YFWD, 3 YINV). */
+ * touched: 2 fields for a transform pass, 6 XMID, 9 ZFWD, 4 ZINV, 3 YFWD, 3 YINV). */
 kfbi_status kfbi_time_pass(kfbi_ctx* ctx, int32_t kind, int32_t axis, int32_t reps, double* avg_ms,
                            double* bytes_per_launch);
 
