@@ -356,6 +356,9 @@ struct kfbi_ctx {
   double *pr_w = nullptr, *prT_w = nullptr;
   int gm_max = 0;
   kfbi_info last;
+  // F is zero outside the irregular nodes (the correction pass then assigns those and no clear
+  // of the 4 N^3 values is needed); false after any other writer of F
+  bool f_clean = false;
   // pinned host scalars read after a later synchronisation, and the stage events of an evaluation
   double* hpin = nullptr;
   hipEvent_t sev[4] = {nullptr, nullptr, nullptr, nullptr};
@@ -561,10 +564,14 @@ void assemble_rhs(kfbi_ctx* C, const double* phi, bool vol) {
   HIPCHK(launch_fit_jump(S.T, C->nb_ptr, C->nb_idx, C->fitw, C->jmap, C->jfmap, Fj, phi, C->cp_of, C->jumps,
                          C->fitvals, s));
   HIPCHK(launch_interp_jump(S.n, C->cp_target, C->fitvals, C->emap, C->efmap, Fj, C->ejump, s));
-  HIPCHK(launch_fill<double>(4 * S.M, C->F, 0.0, s));
+  if (!C->f_clean) HIPCHK(launch_fill<double>(4 * S.M, C->F, 0.0, s));
   HIPCHK(launch_correct((int64_t)S.irr_node.size(), C->irr_node, C->irr_ptr, C->arm_t, C->arm_o, C->arm_a, C->jumps,
                         C->F, s));
-  if (vol && C->nvol) HIPCHK(launch_scatter_add(C->nvol, C->vol_idx, C->vol_val, C->F, s));
+  C->f_clean = true;
+  if (vol && C->nvol) {
+    HIPCHK(launch_scatter_add(C->nvol, C->vol_idx, C->vol_val, C->F, s));
+    C->f_clean = false;
+  }
 }
 
 // float64 MAC solve of C->F into C->u, C->p (either directly or by mixed refinement)
@@ -667,6 +674,7 @@ void transpose_from_velocity(kfbi_ctx* C, const double* w, double* out, kfbi_inf
   hipStream_t s = C->s;
   // transpose of the MAC solve: (F_u-bar, F_p-bar) = (u', -p') with (u', p') = solve(u-bar, 0)
   mac_solve(C, C->F, C->u, C->p, info);
+  C->f_clean = false;
   HIPCHK(hipMemcpyAsync(C->F, C->u, 3 * M * sizeof(double), hipMemcpyDeviceToDevice, s));
   HIPCHK(launch_axpby<double>(M, C->F + 3 * M, -1.0, C->p, 0.0, s));
   // corrections^T, jump maps^T (plus the interpolation jump term), fit^T
@@ -682,6 +690,7 @@ void adjoint_impl(kfbi_ctx* C, const double* w, double* out, kfbi_info* info) {
   hipStream_t s = C->s;
   double t0 = now_ms();
   // u-bar = W^T w (F holds the solve's right-hand side (u-bar, 0))
+  C->f_clean = false;
   HIPCHK(launch_fill<double>(4 * M, C->F, 0.0, s));
   HIPCHK(launch_interp_T((int64_t)S.uT_node.size(), C->uT_ptr, C->uT_node, C->uT_row, C->uT_w, w, C->F, s));
   transpose_from_velocity(C, w, out, info);
@@ -1168,6 +1177,7 @@ kfbi_status kfbi_probe_adjoint(kfbi_ctx* C, const double* vals_bar, double* phi_
   }
   return guarded(C, [&] {
     check_finite(C, vals_bar, 3 * C->nprobe);
+    C->f_clean = false;
     HIPCHK(launch_fill<double>(4 * C->S.M, C->F, 0.0, C->s));
     HIPCHK(launch_interp_T(C->nprobe_nodes, C->prT_ptr, C->prT_node, C->prT_row, C->prT_w, vals_bar, C->F, C->s));
     transpose_from_velocity(C, nullptr, phi_bar, info);

@@ -1202,7 +1202,7 @@ __global__ void k_correct(int64_t nirr, const int64_t* __restrict__ irr_node, co
     v += a[0] * J[0] + a[1] * J[1];
     if (arm_o[q] == 0) v += a[2] * J[2];
   }
-  F[irr_node[r]] += v;
+  F[irr_node[r]] = v;  // every irregular node appears once (its equation's arms are grouped)
 }
 
 __global__ void k_interp(int64_t n, const int64_t* __restrict__ idx, const double* __restrict__ w,

@@ -83,6 +83,8 @@ def _compare(name, N):
     off = O.rhs_off
     irr, ip = P.get("irr_node"), P.get("irr_ptr")
     at, ao, aa = P.get("arm_t"), P.get("arm_o"), P.get("arm_a").reshape(-1, 3)
+    # each irregular node has one equation (the correction pass assigns, not accumulates)
+    assert len(np.unique(irr)) == len(irr)
 
     def to_oracle(gi):
         g, l = divmod(int(gi), M)
