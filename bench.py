@@ -98,6 +98,25 @@ def run_form(K, KI, cfg, prec, rtol, inner, steps, warmup, ref, prof=None):
     return res
 
 
+def copy_bandwidth(nbytes=1 << 30, reps=10):
+    """Read+write bandwidth (GB/s) of a plain device-to-device copy of nbytes (larger than the
+    256 MB last-level cache), timed with events on torch's current stream, where the copy runs."""
+    import torch
+    src = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.empty_cache()
+    return 2 * nbytes / (ms * 1e-3) / 1e9
+
+
 def all_configs(K, KI, say):
     """Timings of every configuration (not part of the one-line result): K phi and K^T w in
     float64 and mixed form, and the Dirichlet BVP (volume trace, GMRES, unified solve)."""
@@ -198,6 +217,8 @@ def main():
 
     pr = mx["prof"]
     achieved = pr["bytes"] / (pr["avg_ms"] * 1e-3) / 1e9
+    copy_gbs = copy_bandwidth()
+    say(f"[bench] device copy: {copy_gbs:.0f} GB/s")
     # measured HBM traffic of the dominant kernel (rocprofv3 FETCH_SIZE/WRITE_SIZE, copy-calibrated),
     # valid only while the transform sources are the ones that were profiled
     traffic = None
@@ -236,7 +257,8 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK, "traffic": traffic,
                      "kernel": f"{KIND_NAMES[dominant[0]]}<float,{cfg.N}>",
-                     "launches_timed": pr["launches"], "avg_us": pr["avg_ms"] * 1e3, "bytes_per_launch": pr["bytes"]},
+                     "launches_timed": pr["launches"], "avg_us": pr["avg_ms"] * 1e3, "bytes_per_launch": pr["bytes"],
+                     "copy_gb_s": copy_gbs, "frac_of_copy": achieved / copy_gbs},
         "cg_iteration_kernels": mx.get("kernels"),
     }
     if not args.no_cpu:
