@@ -345,6 +345,10 @@ struct kfbi_ctx {
   // mixed refinement fields (float64 and float32)
   double* ru = nullptr;  // spare float64 iterate of the refinement
   float *r32 = nullptr, *x32 = nullptr;
+  float* r32b = nullptr;  // residual of the rounds after the first (r32 keeps the first right-hand side)
+  // r32 is zero outside the irregular nodes (the correction pass then assigns them), and
+  // r32_ready: r32 = float32(F) and rpart holds its partial sums, written by the last assembly
+  bool r32_clean = false, r32_ready = false;
   double* rscal = nullptr;
   double* rpart = nullptr;
   // GMRES
@@ -492,6 +496,7 @@ kfbi_status kfbi_create(const kfbi_config* cfg_in, kfbi_ctx** out) {
       C->s32.init(S.N, S.h, S.pde, S.mu, c, s, o);
       C->ru = dalloc<double>(4 * S.M, o);
       C->r32 = dalloc<float>(4 * S.M, o);
+      C->r32b = dalloc<float>(4 * S.M, o);
       C->x32 = dalloc<float>(4 * S.M, o);
       C->rscal = dalloc<double>(16, o);
       C->rpart = dalloc<double>(3 * 2048, o);
@@ -557,6 +562,10 @@ void check_finite(kfbi_ctx* C, const double* v, int64_t n) {
 }
 
 // right-hand side F (4 fields) from the density (and the stored volume force)
+// blocks of the refinement passes and of the correction pass that stands in for the first of them
+// (3 partial sums each; 2048 measured slower)
+constexpr int kRefineParts = 1024;
+
 void assemble_rhs(kfbi_ctx* C, const double* phi, bool vol) {
   const Setup& S = C->S;
   hipStream_t s = C->s;
@@ -565,10 +574,22 @@ void assemble_rhs(kfbi_ctx* C, const double* phi, bool vol) {
                          C->fitvals, s));
   HIPCHK(launch_interp_jump(S.n, C->cp_target, C->fitvals, C->emap, C->efmap, Fj, C->ejump, s));
   if (!C->f_clean) HIPCHK(launch_fill<double>(4 * S.M, C->F, 0.0, s));
-  HIPCHK(launch_correct((int64_t)S.irr_node.size(), C->irr_node, C->irr_ptr, C->arm_t, C->arm_o, C->arm_a, C->jumps,
-                        C->F, s));
+  const bool sparse = !(vol && C->nvol);
+  const int64_t nirr = (int64_t)S.irr_node.size();
+  if (C->mixed && sparse) {
+    // F is the corrections alone: the float32 right-hand side of the first refinement round
+    // and its norm partials come from the correction pass (no dense pass over F)
+    if (!C->r32_clean) HIPCHK(launch_fill<float>(4 * S.M, C->r32, 0.0f, s));
+    HIPCHK(launch_correct(nirr, C->irr_node, C->irr_ptr, C->arm_t, C->arm_o, C->arm_a, C->jumps, C->F, s, C->r32,
+                          S.M, C->rpart, kRefineParts));
+    C->r32_clean = true;
+    C->r32_ready = true;
+  } else {
+    HIPCHK(launch_correct(nirr, C->irr_node, C->irr_ptr, C->arm_t, C->arm_o, C->arm_a, C->jumps, C->F, s));
+    C->r32_ready = false;
+  }
   C->f_clean = true;
-  if (vol && C->nvol) {
+  if (!sparse) {
     HIPCHK(launch_scatter_add(C->nvol, C->vol_idx, C->vol_val, C->F, s));
     C->f_clean = false;
   }
@@ -594,10 +615,14 @@ int mac_solve(kfbi_ctx* C, const double* F, double* u, double* p, kfbi_info* inf
   // modulo constants, which the inner solve projects out).
   const bool stokes = S.pde == KFBI_STOKES;
   const double c = stokes ? 0.0 : 1.0 / (S.lam + S.mu);
-  constexpr int NP = 1024;  // blocks of the fused passes (3 partial sums each; 2048 measured slower)
+  constexpr int NP = kRefineParts;
   // |F| is copied to pinned memory and read with the first residual norm: the first inner
   // solve is queued without a synchronisation (F = 0 gives x32 = 0 and a zero residual)
-  HIPCHK(launch_refine_prep(M, F, C->r32, C->rpart, NP, s));
+  if (!(C->r32_ready && C->f_clean && F == C->F)) {
+    HIPCHK(launch_refine_prep(M, F, C->r32, C->rpart, NP, s));
+    C->r32_clean = false;
+  }
+  C->r32_ready = false;
   HIPCHK(launch_reduce(C->rpart, NP, 3, C->rscal, R_RESNORM0, stokes, M, s));
   HIPCHK(hipMemcpyAsync(C->hpin + 1, C->rscal + 5, sizeof(double), hipMemcpyDeviceToHost, s));
   const double* shift = stokes ? C->rscal + 6 : nullptr;  // mean of F_p (Stokes)
@@ -609,12 +634,13 @@ int mac_solve(kfbi_ctx* C, const double* F, double* u, double* p, kfbi_info* inf
   double rn = 1.0, f0 = 0.0;
   while (rounds == 0 || rn > C->cfg.cg_rtol * f0) {
     if (rounds >= 30) throw std::runtime_error("ENOCONV: mixed refinement did not converge");
-    int it = C->s32.solve(C->r32, C->r32 + 3 * M, C->x32, C->x32 + 3 * M, C->cfg.inner_rtol, C->cfg.cg_maxit);
+    const float* rin = (rounds == 0) ? C->r32 : C->r32b;
+    int it = C->s32.solve(rin, rin + 3 * M, C->x32, C->x32 + 3 * M, C->cfg.inner_rtol, C->cfg.cg_maxit);
     if (it < 0) throw std::runtime_error("ENOCONV: inner float32 CG reached cg_maxit");
     total += it;
     double* nu = (rounds == 0 || cu != u) ? u : C->ru;
     double* np = (rounds == 0 || cu != u) ? p : C->ru + 3 * M;
-    HIPCHK(launch_refine_residual(rounds == 0, S.N, S.h, S.mu, c, cu, cp, C->x32, F, shift, nu, np, C->r32, C->rpart,
+    HIPCHK(launch_refine_residual(rounds == 0, S.N, S.h, S.mu, c, cu, cp, C->x32, F, shift, nu, np, C->r32b, C->rpart,
                                   NP, s));
     cu = nu;
     cp = np;

@@ -105,9 +105,12 @@ hipError_t launch_fit_jump(int64_t T, const int64_t* nb_ptr, const int32_t* nb_i
                            const int64_t* cp_of, double* jumps, double* fitvals, hipStream_t s);
 hipError_t launch_interp_jump(int64_t n, const int64_t* cp_target, const double* fitvals, const double* emap,
                               const double* efmap, const double* Fj, double* ejump, hipStream_t s);
-// F[irr_node[r]] = correction of node r (assigned: each node appears once; F elsewhere untouched)
+// F[irr_node[r]] = correction of node r (assigned: each node appears once; F elsewhere untouched);
+// with r32 != nullptr also r32[irr_node[r]] = (float) the same value and, over nparts blocks,
+// partial sums (F_u.F_u, sum F_p, F_p.F_p) of the corrections (M = N^3 splits F_u from F_p)
 hipError_t launch_correct(int64_t nirr, const int64_t* irr_node, const int64_t* irr_ptr, const int32_t* arm_t,
-                          const int8_t* arm_o, const double* arm_a, const double* jumps, double* F, hipStream_t s);
+                          const int8_t* arm_o, const double* arm_a, const double* jumps, double* F, hipStream_t s,
+                          float* r32 = nullptr, int64_t M = 0, double* partials = nullptr, int nparts = 0);
 // probes: out[r] = sum_{q<8} w[8r+q] u[idx[8r+q]], r < 3 m (trilinear)
 hipError_t launch_interp8(int64_t m, const int64_t* idx, const double* w, const double* u, double* out, hipStream_t s);
 hipError_t launch_stab(int64_t n, const int64_t* ptr, const int32_t* idx, const double* sw, const double* a,

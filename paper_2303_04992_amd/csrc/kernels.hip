@@ -1190,19 +1190,46 @@ __global__ void k_interp_jump(int64_t n, const int64_t* __restrict__ cp_target, 
   ejump[r] = s;
 }
 
-__global__ void k_correct(int64_t nirr, const int64_t* __restrict__ irr_node, const int64_t* __restrict__ irr_ptr,
-                          const int32_t* __restrict__ arm_t, const int8_t* __restrict__ arm_o,
-                          const double* __restrict__ arm_a, const double* __restrict__ jumps, double* __restrict__ F) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= nirr) return;
-  double v = 0;
-  for (int64_t q = irr_ptr[r]; q < irr_ptr[r + 1]; ++q) {
-    const double* J = jumps + 5 * (int64_t)arm_t[q] + arm_o[q];
-    const double* a = arm_a + 3 * q;
-    v += a[0] * J[0] + a[1] * J[1];
-    if (arm_o[q] == 0) v += a[2] * J[2];
+// Correction of every irregular node, assigned into F (every irregular node appears once, its
+// equation's arms being grouped).  With r32 != nullptr the float32 copy is assigned as well and
+// the block writes the partial sums (F_u.F_u, sum F_p, F_p.F_p) over its nodes to partials[3b..]:
+// when F is zero elsewhere, these are the refinement's start values without a dense pass.
+__global__ __launch_bounds__(EW_NT) void k_correct(int64_t nirr, const int64_t* __restrict__ irr_node,
+                                                const int64_t* __restrict__ irr_ptr,
+                                                const int32_t* __restrict__ arm_t, const int8_t* __restrict__ arm_o,
+                                                const double* __restrict__ arm_a, const double* __restrict__ jumps,
+                                                double* __restrict__ F, float* __restrict__ r32, int64_t M,
+                                                double* __restrict__ partials) {
+  __shared__ double red[EW_NT / 64];
+  double su = 0, sp = 0, spp = 0;
+  for (int64_t r = (int64_t)blockIdx.x * EW_NT + threadIdx.x; r < nirr; r += (int64_t)gridDim.x * EW_NT) {
+    double v = 0;
+    for (int64_t q = irr_ptr[r]; q < irr_ptr[r + 1]; ++q) {
+      const double* J = jumps + 5 * (int64_t)arm_t[q] + arm_o[q];
+      const double* a = arm_a + 3 * q;
+      v += a[0] * J[0] + a[1] * J[1];
+      if (arm_o[q] == 0) v += a[2] * J[2];
+    }
+    const int64_t node = irr_node[r];
+    F[node] = v;
+    if (r32) {
+      r32[node] = (float)v;
+      if (node < 3 * M) {
+        su += v * v;
+      } else {
+        sp += v;
+        spp += v * v;
+      }
+    }
   }
-  F[irr_node[r]] = v;  // every irregular node appears once (its equation's arms are grouped)
+  if (r32) {
+    const double t0 = block_sum(su, red), t1 = block_sum(sp, red), t2 = block_sum(spp, red);
+    if (threadIdx.x == 0) {
+      partials[3 * blockIdx.x] = t0;
+      partials[3 * blockIdx.x + 1] = t1;
+      partials[3 * blockIdx.x + 2] = t2;
+    }
+  }
 }
 
 __global__ void k_interp(int64_t n, const int64_t* __restrict__ idx, const double* __restrict__ w,
@@ -1617,9 +1644,12 @@ hipError_t launch_interp_jump(int64_t n, const int64_t* cp_target, const double*
   return hipGetLastError();
 }
 hipError_t launch_correct(int64_t nirr, const int64_t* irr_node, const int64_t* irr_ptr, const int32_t* arm_t,
-                          const int8_t* arm_o, const double* arm_a, const double* jumps, double* F, hipStream_t s) {
-  hipLaunchKernelGGL(k_correct, dim3(gb(nirr)), dim3(256), 0, s, nirr, irr_node, irr_ptr, arm_t, arm_o, arm_a, jumps,
-                     F);
+                          const int8_t* arm_o, const double* arm_a, const double* jumps, double* F, hipStream_t s,
+                          float* r32, int64_t M, double* partials, int nparts) {
+  const int blocks = r32 ? nparts : gb(nirr);
+  if (r32 && (nparts < 1 || !partials)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_correct, dim3(blocks), dim3(EW_NT), 0, s, nirr, irr_node, irr_ptr, arm_t, arm_o, arm_a, jumps,
+                     F, r32, M, partials);
   return hipGetLastError();
 }
 hipError_t launch_interp(int64_t n, const int64_t* idx, const double* w, const double* u, const double* ejump,
