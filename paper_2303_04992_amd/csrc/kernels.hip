@@ -627,7 +627,10 @@ template <typename T, int N>
 __global__ __launch_bounds__(256) void k_xmid(T* A0, T* A1, T* A2, double mu, Tab<T> tb) {
   extern __shared__ __align__(16) unsigned char smem[];
   T* lds = reinterpret_cast<T*>(smem);
-  const int mc = blockIdx.y;
+  // float64: the component written last by the y passes (2) first, while it is still in the
+  // last-level cache (27.6 -> 26.9 ms per float64 evaluation at 256^3, the following inverse y
+  // pass gaining as well); float32 measured slightly better in the natural order
+  const int mc = (sizeof(T) == 8) ? 2 - (int)blockIdx.y : (int)blockIdx.y;
   if (mc == 0)
     xmid_body<T, N, DCT2, DCT3>(lds, A0, 0, mu, tb);
   else if (mc == 1)
