@@ -222,10 +222,15 @@ struct MacSolver {
   }
   void cg_iteration(bool first) {
     zfwd(first ? ZF_FIRST : ZF_FUSED);  // x, r of the last step; d = r + beta d; A = DST_z d; B = DCT_z d
-    yfwd();                // components 0, 1: A1 = DST_y A, B2 = DCT_y A
-    pass(DST2, 1, B, B3);  // component 2
-    xmid();                // x: forward, weight sigma^2 / Lambda, inverse (all components)
-    yinv();                // A = DST_y^T A1 + DCT_y^T B2 (components 0 and 1 share DST_z)
+    // y passes, ordered so that the x pass starts with the components written last (still in the
+    // 256 MB last-level cache): float32 runs component 2 first and the x pass takes components
+    // 0, 1, 2; float64 runs components 0, 1 first and the x pass takes 2, 1, 0 (measured at 256^3)
+    constexpr bool b3_first = sizeof(T) == 4;
+    if (b3_first) pass(DST2, 1, B, B3);  // component 2
+    yfwd();                               // components 0, 1: A1 = DST_y A, B2 = DCT_y A
+    if (!b3_first) pass(DST2, 1, B, B3);
+    xmid();                               // x: forward, weight sigma^2 / Lambda, inverse (all components)
+    yinv();                               // A = DST_y^T A1 + DCT_y^T B2 (components 0 and 1 share DST_z)
     pass(DST3, 1, B3, B);
     zinv();                // q = DST_z^T A + DCT_z^T B + c d, partial dots
     HIPCHK(launch_cg_coef(rpart, nparts_z, partials, nparts_x, scal, 1, M, s));  // mean-zero iterates
@@ -289,8 +294,9 @@ struct MacSolver {
     // z and y shared as in the matvec, then per component the fused x pass and the y, z inverses
     // A = DST_z p, B = DCT_z p
     HIPCHK(launch_zfwd_cg<T>(N, ZF_PLAIN, nullptr, x, nullptr, nullptr, A, B, nullptr, nullptr, tb, s));
+    if (sizeof(T) == 4) pass(DST2, 1, B, B3);                         // C_2 along y (order as in the matvec)
     HIPCHK(launch_ypair<T>(N, false, A, A, A1, B2, tb, s));          // C_0, C_1 along y
-    pass(DST2, 1, B, B3);                                             // C_2 along y
+    if (sizeof(T) != 4) pass(DST2, 1, B, B3);
     for (int m = 0; m < 3; ++m) {
       T* um = u + m * M;
       HIPCHK(launch_xfuse<T>(N, m, true, H[m], Fh[m], um, mu, tb, s));
