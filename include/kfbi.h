@@ -13,9 +13,10 @@
  * host pointers.  The library owns only what its context holds (geometry, sparse maps and
  * device workspaces), allocated in kfbi_create and released by kfbi_destroy.
  *
- * Ordering: work is issued on cfg.stream (a hipStream_t; NULL = the default stream) and
- * every call returns after its work has completed (the CG and GMRES loops read scalars back
- * to the host).  One context per thread/stream; contexts are independent.
+ * Ordering: work is issued on cfg.stream (a hipStream_t; NULL = a stream that kfbi_create
+ * creates and kfbi_destroy destroys) and every call returns after its work has completed (the
+ * CG and GMRES loops read scalars back to the host).  One context per thread/stream; contexts
+ * are independent.
  *
  * Grid layout of exported fields (numpy C order [i][j][k] <-> (x, y, z), box [lo,hi]^3,
  * h = (hi-lo)/N): u1 has shape (N+1, N, N) with u1[i][j][k] the x-velocity at
@@ -90,17 +91,23 @@ typedef struct {
   double inner_rtol;  /* MIXED_FP32: tolerance of each float32 inner solve; <= 0: 1e-5 */
   double gmres_rtol;  /* <= 0: 1e-8 */
   int32_t gmres_maxit;/* <= 0: 200 */
-  void* stream;       /* hipStream_t; NULL = default stream */
+  void* stream;       /* hipStream_t; NULL = a stream owned by the context */
   kfbi_trace trace;   /* trace form of K (eval, adjoint and the GMRES operator) */
 } kfbi_config;
 
 typedef struct {
-  int32_t cg_iters;        /* total Schur CG iterations of the last call */
+  int32_t cg_iters;        /* total Schur CG iterations of the call */
   int32_t refine_rounds;   /* MIXED_FP32 refinement rounds of the last MAC solve */
   int32_t gmres_iters;
   double final_rel_residual;
-  double ms_total;
-  double ms_stage[4];      /* jumps+corrections, MAC solve, interpolation, other */
+  double ms_total;         /* device time of the call's evaluations (HIP events on the stream) */
+  double ms_stage[6];      /* of which: [0] surface fit + jumps (and their transposes),
+                              [1] corrections, [2] MAC right-hand side, [3] Schur CG iterations
+                              and mixed refinement passes, [4] velocity back-substitution,
+                              [5] interpolation (and probes) */
+  double model_bytes;      /* algorithmic HBM bytes of the call's kernels: one read or write of
+                              every field value or map entry touched, gathers counted per
+                              element (model_bytes / ms_total = the call's effective bandwidth) */
 } kfbi_info;
 
 /* Host callback for body forces: fill out[i][3] with f at xyz[i][3], i < m. */
@@ -120,13 +127,16 @@ const char* kfbi_create_error(void);
 kfbi_status kfbi_num_points(const kfbi_ctx* ctx, int64_t* n);
 /* Control points and outward unit normals, host arrays [n][3] (normal may be NULL). */
 kfbi_status kfbi_get_points(const kfbi_ctx* ctx, double* xyz_host, double* normal_host);
-/* Number of crossings (surface points where jumps are evaluated) and MAC unknowns. */
+/* Number of crossings (surface points where jumps are evaluated) and of irregular MAC nodes
+ * (grid equations that receive a correction term). */
 kfbi_status kfbi_sizes(const kfbi_ctx* ctx, int64_t* n_crossings, int64_t* n_irregular);
 
-/* K phi = 1/2 phi - M phi (Prop. 4.2 / 4.4): the interior trace u+ at the control points of
- * the double-layer interface problem  -mu lap u + grad p = 0, div u + c p = 0 off the
- * surface, [[u]] = phi, [[sigma n]] = 0, u = 0 on the box.  phi_dev, out_dev: [n][3]
- * float64 device arrays (may not alias).  info may be NULL. */
+/* K phi = 1/2 phi - M phi (Prop. 4.2 / 4.4) at the control points, read off the double-layer
+ * interface problem  -mu lap u + grad p = 0, div u + c p = 0 off the surface, [[u]] = phi,
+ * [[sigma n]] = 0, u = 0 on the box (Sec. 4.4 interpolation), in the context's trace form:
+ * AVERAGE (default) 1/2 phi + (u+ + u-)/2, INTERIOR the interior limit u+.  phi_dev, out_dev:
+ * [n][3] float64 device arrays (may not alias).  info may be NULL.  A non-finite phi gives
+ * EINVAL. */
 kfbi_status kfbi_eval(kfbi_ctx* ctx, const double* phi_dev, double* out_dev, kfbi_info* info);
 
 /* Transpose of kfbi_eval (in the context's trace form): out = K^T w (same shapes). */
@@ -161,6 +171,13 @@ kfbi_status kfbi_probe_adjoint(kfbi_ctx* ctx, const double* vals_bar_dev, double
  * guess, gmres_rtol, gmres_maxit): the adjoint of the second-kind equation of Sec. 3, used for
  * gradients with respect to the Dirichlet data. */
 kfbi_status kfbi_solve_adjoint(kfbi_ctx* ctx, const double* rhs_dev, double* y_dev, kfbi_info* info);
+/* Reverse mode of the probe values of the Dirichlet BVP (Sec. 3: phi = K^{-1}(g - b), the
+ * representation u = G f - M phi read at the probes): for the cotangent vals_bar [m][3] of
+ * the probe values, phi_bar = P^T vals_bar (P: density -> probe values of the unified
+ * interface solve) and g_bar = K^{-T} phi_bar (GMRES on the transposed operator, as
+ * kfbi_solve_adjoint).  Either output may be NULL (not both); [n][3] device arrays. */
+kfbi_status kfbi_solve_bvp_adjoint(kfbi_ctx* ctx, const double* vals_bar_dev, double* g_bar_dev,
+                                   double* phi_bar_dev, kfbi_info* info);
 
 /* Kernels of the MAC solver that the measurement helpers can time: the single transform
  * pass (kind 0 DCT-II, 1 DST-II, 2 DCT-III, 3 DST-III, 4 DST-I, along one axis) and the

@@ -134,34 +134,58 @@ class Oracle:
         self.last_cg_iters = it
         return jumps, u, p
 
-    def eval(self, phi, f=None):
+    def _trace(self, phi, jumps, u, form, f=None):
+        """K phi read off one interface solve (jumps, grid velocity u) in trace form `form`."""
+        if form == "interior":
+            return (self.W @ self.join_u(u) + self.E @ jumps).reshape(self.n, 3)
+        if not hasattr(self, "Eavg"):
+            raise ValueError("the average form needs an oracle built with form='average'")
+        phi = np.asarray(phi, float).reshape(self.n, 3)
+        jr = self.Jmat @ (self.FitRaw @ phi.ravel())
+        if f is not None:
+            jr = jr + self.Bmat @ self.volume_source(f)[1].ravel()
+        return (0.5 * phi.ravel() + self.W @ self.join_u(u) + self.Eavg @ jr).reshape(self.n, 3)
+
+    def eval(self, phi, f=None, form=None):
         """K phi = u+ at the control points for the double-layer interface problem (f None);
-        with f, the trace of the unified interface problem (volume + double layer)."""
+        with f, the trace of the unified interface problem (volume + double layer).  form
+        overrides the oracle's trace form for this call."""
         jumps, u, p = self.interface_solve(phi, f)
-        if self.form == "interior":
-            out = self.W @ self.join_u(u) + self.E @ jumps
-        else:
-            phi = np.asarray(phi, float).reshape(self.n, 3)
-            jr = self.Jmat @ (self.FitRaw @ phi.ravel())
-            if f is not None:
-                jr = jr + self.Bmat @ self.volume_source(f)[1].ravel()
-            out = 0.5 * phi.ravel() + self.W @ self.join_u(u) + self.Eavg @ jr
+        return self._trace(phi, jumps, u, form or self.form, f)
+
+    def eval_both(self, phi):
+        """K phi in both trace forms from one interface solve (the grid solution is common to
+        the two forms; they differ only in how the trace is read off it)."""
+        jumps, u, p = self.interface_solve(phi)
+        return {fm: self._trace(phi, jumps, u, fm) for fm in ("interior", "average")}
+
+    def _adjoint_from(self, w, rhs_bar, form):
+        if form == "interior":
+            jbar = self.Cmat.T @ rhs_bar + self.E.T @ w
+            return (self.Fit.T @ (self.Jmat.T @ jbar)).reshape(self.n, 3)
+        if not hasattr(self, "Eavg"):
+            raise ValueError("the average form needs an oracle built with form='average'")
+        out = self.Fit.T @ (self.Jmat.T @ (self.Cmat.T @ rhs_bar))
+        out += self.FitRaw.T @ (self.Jmat.T @ (self.Eavg.T @ w)) + 0.5 * w
         return out.reshape(self.n, 3)
 
-    def eval_adjoint(self, w):
-        w = np.asarray(w, float).ravel()
+    def _adjoint_solve(self, w):
         ub = self.W.T @ w
         o = self.rhs_off
         ubar = [ub[o[m]:o[m + 1]].reshape(self.mac.ushape(m)) for m in range(3)]
         Fu_bar, Fp_bar, it = self.mac.solve_transpose(ubar, rtol=self.cg_rtol)
         self.last_cg_iters = it
-        rhs_bar = np.concatenate([x.ravel() for x in Fu_bar] + [Fp_bar.ravel()])
-        if self.form == "interior":
-            jbar = self.Cmat.T @ rhs_bar + self.E.T @ w
-            return (self.Fit.T @ (self.Jmat.T @ jbar)).reshape(self.n, 3)
-        out = self.Fit.T @ (self.Jmat.T @ (self.Cmat.T @ rhs_bar))
-        out += self.FitRaw.T @ (self.Jmat.T @ (self.Eavg.T @ w)) + 0.5 * w
-        return out.reshape(self.n, 3)
+        return np.concatenate([x.ravel() for x in Fu_bar] + [Fp_bar.ravel()])
+
+    def eval_adjoint(self, w, form=None):
+        w = np.asarray(w, float).ravel()
+        return self._adjoint_from(w, self._adjoint_solve(w), form or self.form)
+
+    def eval_adjoint_both(self, w):
+        """K^T w in both trace forms from one transposed MAC solve (W^T w is common)."""
+        w = np.asarray(w, float).ravel()
+        rb = self._adjoint_solve(w)
+        return {fm: self._adjoint_from(w, rb, fm) for fm in ("interior", "average")}
 
     # ------------------------------------------------------------------ GMRES + BVP
     @staticmethod

@@ -4,8 +4,8 @@ Every step of the operator runs in the HIP library; PyTorch supplies device memo
 streams.  Importing this package loads ``libkfbi.so`` from the package directory and fails
 loudly if it is missing (build it with ``python paper_2303_04992_amd/build.py``).
 
-Names follow include/kfbi.h: ``Operator.eval`` is kfbi_eval (K phi = 1/2 phi - M phi, the
-interior trace of the double-layer interface problem), ``Operator.eval_adjoint`` its
+Names follow include/kfbi.h: ``Operator.eval`` is kfbi_eval (K phi = 1/2 phi - M phi read off
+the double-layer interface problem in the context's trace form), ``Operator.eval_adjoint`` its
 transpose, ``Operator.solve_bvp`` the Dirichlet boundary-value solve (GMRES on the
 second-kind integral equation), ``Operator.interface_solve`` the grid solution of the
 unified interface problem, ``Operator.probe`` the velocity at interior probes.  ``BIEEval``,
@@ -57,12 +57,15 @@ class Config(C.Structure):
 
 class Info(C.Structure):
     _fields_ = [("cg_iters", C.c_int32), ("refine_rounds", C.c_int32), ("gmres_iters", C.c_int32),
-                ("final_rel_residual", C.c_double), ("ms_total", C.c_double), ("ms_stage", C.c_double * 4)]
+                ("final_rel_residual", C.c_double), ("ms_total", C.c_double), ("ms_stage", C.c_double * 6),
+                ("model_bytes", C.c_double)]
+
+    STAGES = ("jumps", "corrections", "rhs", "cg", "backsub", "interp")
 
     def as_dict(self):
         return {"cg_iters": self.cg_iters, "refine_rounds": self.refine_rounds, "gmres_iters": self.gmres_iters,
                 "final_rel_residual": self.final_rel_residual, "ms_total": self.ms_total,
-                "ms_stage": list(self.ms_stage)}
+                "ms_stage": dict(zip(self.STAGES, self.ms_stage)), "model_bytes": self.model_bytes}
 
 
 VecFn = C.CFUNCTYPE(None, C.POINTER(C.c_double), C.c_int64, C.POINTER(C.c_double), C.c_void_p)
@@ -84,6 +87,7 @@ _sig = {
     "kfbi_probe": (C.c_int, [_P, _P, C.c_int32, _P, C.POINTER(Info)]),
     "kfbi_probe_adjoint": (C.c_int, [_P, _P, _P, C.POINTER(Info)]),
     "kfbi_solve_adjoint": (C.c_int, [_P, _P, _P, C.POINTER(Info)]),
+    "kfbi_solve_bvp_adjoint": (C.c_int, [_P, _P, _P, _P, C.POINTER(Info)]),
     "kfbi_time_pass": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double),
                                  C.POINTER(C.c_double)]),
     "kfbi_profile_pass": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int64),
@@ -290,6 +294,20 @@ class Operator:
         self.last_info = info.as_dict()
         self._check(st)
         return out
+
+    def solve_bvp_adjoint(self, vbar, want_g=True, want_phi=True):
+        """(g_bar, phi_bar) for the cotangent vbar of the probe values of the BVP solution:
+        phi_bar = P^T vbar, g_bar = K^{-T} phi_bar (kfbi_solve_bvp_adjoint)."""
+        torch = _torch()
+        vbar = torch.as_tensor(vbar, dtype=torch.float64, device=self.device).reshape(self.nprobe, 3).contiguous()
+        gb = torch.empty((self.n, 3), dtype=torch.float64, device=self.device) if want_g else None
+        pb = torch.empty((self.n, 3), dtype=torch.float64, device=self.device) if want_phi else None
+        info = Info()
+        st = _lib.kfbi_solve_bvp_adjoint(self._h, _ptr(vbar), _ptr(gb) if gb is not None else None,
+                                         _ptr(pb) if pb is not None else None, C.byref(info))
+        self.last_info = info.as_dict()
+        self._check(st)
+        return gb, pb
 
     def time_pass(self, kind=1, axis=1, reps=20):
         """Mean duration (ms) and algorithmic bytes of one transform-pass launch."""

@@ -56,6 +56,50 @@ T* dupload(const std::vector<T>& v, std::vector<void*>& owned, hipStream_t s) {
   return p;
 }
 
+void dfree(void* p, std::vector<void*>& owned) {
+  if (!p) return;
+  auto it = std::find(owned.begin(), owned.end(), p);
+  if (it != owned.end()) owned.erase(it);
+  (void)hipFree(p);
+}
+
+// Stage timing of one call from HIP events on the call's stream (no synchronisation between
+// stages): mark(k) starts stage k; after the call's final synchronisation collect() sums the
+// intervals per stage into kfbi_info.ms_stage and the whole span into ms_total.
+enum Stage { ST_JUMPS = 0, ST_CORRECT = 1, ST_RHS = 2, ST_CG = 3, ST_BACKSUB = 4, ST_INTERP = 5, ST_END = 6 };
+struct StageClock {
+  static constexpr int CAP = 192;
+  hipEvent_t ev[CAP] = {};
+  int stage[CAP] = {};
+  int used = 0;
+  void init() {
+    for (auto& e : ev) HIPCHK(hipEventCreate(&e));
+  }
+  void release() {
+    for (auto& e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
+  void mark(int st, hipStream_t s) {
+    if (used < CAP - 1 || (st == ST_END && used < CAP)) {
+      HIPCHK(hipEventRecord(ev[used], s));
+      stage[used++] = st;
+    }
+  }
+  void collect(kfbi_info* info) {
+    if (info && used >= 2) {
+      for (int i = 0; i + 1 < used; ++i) {
+        float ms = 0;
+        HIPCHK(hipEventElapsedTime(&ms, ev[i], ev[i + 1]));
+        if (stage[i] < ST_END) info->ms_stage[stage[i]] += ms;
+      }
+      float tot = 0;
+      HIPCHK(hipEventElapsedTime(&tot, ev[0], ev[used - 1]));
+      info->ms_total += tot;
+    }
+    used = 0;
+  }
+};
+
 // ---------------------------------------------------------------------------------------
 // spectral MAC solver in precision T
 // ---------------------------------------------------------------------------------------
@@ -68,11 +112,15 @@ struct MacSolver {
   hipStream_t s = nullptr;
   DevTables<T> tb;
   T *Fh[3] = {nullptr, nullptr, nullptr}, *b = nullptr, *x = nullptr, *r = nullptr, *d = nullptr, *q = nullptr;
-  T *A = nullptr, *B = nullptr, *A1 = nullptr, *B2 = nullptr, *B3 = nullptr, *tmp = nullptr;
+  T *A = nullptr, *B = nullptr, *A1 = nullptr, *B2 = nullptr, *B3 = nullptr;
   double* partials = nullptr;
   double* rpart = nullptr;  // partial r.r of the forward z pass
   double* scal = nullptr;
-  double* host_rr = nullptr;  // pinned: [0], [1] look-ahead slots, [2] r.r of the start
+  double* host_rr = nullptr;  // pinned: two look-ahead slots of the 8 CG scalars (scal[0..7])
+  StageClock* clock = nullptr;  // stage marks of the calling context
+  void mark(int st) {
+    if (clock) clock->mark(st, s);
+  }
   hipEvent_t ev[2] = {nullptr, nullptr};
   int nparts_x = 0, nparts_z = 0, nparts_u = 1024;
   // live timing of one transform-pass kind with HIP events on the solver stream
@@ -81,6 +129,9 @@ struct MacSolver {
   size_t prof_used = 0;
   int64_t prof_launches = 0;
   double prof_ms = 0;
+  // algorithmic HBM bytes of the launches issued (one read or write per N^3 field touched)
+  double bytes = 0;
+  void count(double fields) { bytes += fields * (double)M * sizeof(T); }
 
   void init(int N_, double h, int pde_, double mu_, double c_, hipStream_t s_, std::vector<void*>& owned) {
     N = N_;
@@ -135,13 +186,12 @@ struct MacSolver {
     A1 = dalloc<T>(M, owned);
     B2 = dalloc<T>(M, owned);
     B3 = dalloc<T>(M, owned);
-    tmp = dalloc<T>(M, owned);
     nparts_x = zinv_blocks(N, sizeof(T));
     nparts_z = zfwd_blocks(N, sizeof(T));
     partials = dalloc<double>(std::max(4 * nparts_x, nparts_u), owned);
     rpart = dalloc<double>(nparts_z, owned);
     scal = dalloc<double>(16, owned);
-    HIPCHK(hipHostMalloc((void**)&host_rr, 4 * sizeof(double), hipHostMallocDefault));
+    HIPCHK(hipHostMalloc((void**)&host_rr, 16 * sizeof(double), hipHostMallocDefault));
     HIPCHK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
   }
@@ -174,6 +224,7 @@ struct MacSolver {
     if (on) HIPCHK(hipEventRecord(prof_ev[prof_used++].second, s));
   }
   void pass(int kind, int axis, const T* in, T* out, bool acc = false) {
+    count(acc ? 3 : 2);
     timed(kind == prof_kind && (prof_axis < 0 || axis == prof_axis) && !acc,
           [&] { return launch_pass<T>(N, kind, axis, in, out, acc, tb, s); });
   }
@@ -201,6 +252,7 @@ struct MacSolver {
   }
   // v -= mean v; the sum of v is left in scal[keep] when keep >= 0
   void project_mean(T* v, int keep = -1) {
+    count(3);
     HIPCHK(launch_sum_partials<T>(M, v, partials, nparts_u, s));
     HIPCHK(launch_reduce(partials, nparts_u, 1, scal, R_SUM, 1, M, s, keep >= 0 ? scal + keep : nullptr));
     HIPCHK(launch_add_scalar<T>(M, v, scal, keep >= 0 ? keep : 5, -1.0 / (double)M, s));
@@ -211,13 +263,21 @@ struct MacSolver {
   // C_0 = DCT_x DST_y DST_z, C_1 = DST_x DCT_y DST_z, C_2 = DST_x DST_y DCT_z (orthonormal);
   // order z, y, [x fused with the weights], y, z
   void zfwd(int mode = ZF_FUSED) {
+    count(mode == ZF_FUSED ? 9 : mode == ZF_FIRST ? 4 : 3);
     timed(prof_kind == KFBI_K_ZFWD && mode == ZF_FUSED,
           [&] { return launch_zfwd_cg<T>(N, mode, x, r, d, q, A, B, scal, rpart, tb, s); });
   }
-  void yfwd() { timed(prof_kind == KFBI_K_YFWD, [&] { return launch_ypair<T>(N, false, A, A, A1, B2, tb, s); }); }
-  void xmid() { timed(prof_kind == KFBI_K_XMID, [&] { return launch_xmid<T>(N, A1, B2, B3, mu, tb, s); }); }
-  void yinv() { timed(prof_kind == KFBI_K_YINV, [&] { return launch_ypair<T>(N, true, A1, B2, A, A, tb, s); }); }
+  void yfwd() {
+    count(3);
+    timed(prof_kind == KFBI_K_YFWD, [&] { return launch_ypair<T>(N, false, A, A, A1, B2, tb, s); }); }
+  void xmid() {
+    count(6);
+    timed(prof_kind == KFBI_K_XMID, [&] { return launch_xmid<T>(N, A1, B2, B3, mu, tb, s); }); }
+  void yinv() {
+    count(3);
+    timed(prof_kind == KFBI_K_YINV, [&] { return launch_ypair<T>(N, true, A1, B2, A, A, tb, s); }); }
   void zinv() {
+    count(4);
     timed(prof_kind == KFBI_K_ZINV, [&] { return launch_zinv_cg<T>(N, A, B, q, d, c, partials, tb, s); });
   }
   void cg_iteration(bool first) {
@@ -244,14 +304,17 @@ struct MacSolver {
     // y, then the fused x pass keeps Fh[m] = T_m F_m and leaves C_m,x^T of the weighted
     // spectrum; the y and z inverses of the three components are shared as in the matvec.
     T* H[3] = {A1, B2, B3};
+    mark(ST_RHS);
     for (int m = 0; m < 3; ++m) {
       pass(m == 2 ? DST1 : DST2, 2, Fu + m * M, Fh[m]);
       pass(m == 1 ? DST1 : DST2, 1, Fh[m], Fh[m]);
       HIPCHK(launch_xfuse<T>(N, m, false, Fh[m], Fh[m], H[m], mu, tb, s));
+      count(3);
     }
     HIPCHK(launch_ypair<T>(N, true, A1, B2, A, A, tb, s));       // A = DST_y^T H0 + DCT_y^T H1
     pass(DST3, 1, B3, B);                                        // B = DST_y^T H2
     HIPCHK(launch_zinv_cg<T>(N, A, B, b, Fp, 1.0, partials, tb, s));  // b = DST_z^T A + DCT_z^T B + F_p
+    count(3 + 4);
     // Both PDEs iterate on mean-zero pressures.  S = S_0 + cI with S_0 1 = 0 (G annihilates
     // constants, sigma_0 = 0) and S_0 symmetric, so the mean of S p is c mean(p): for Navier
     // (c > 0) the constant mode, whose eigenvalue c = 1/(lambda + mu) is the smallest of S and
@@ -261,49 +324,83 @@ struct MacSolver {
     // 3. CG on S x = b.  Iteration k forms x_k, r_k (with alpha_{k-1}) and d_k in its first
     // pass, so x lags one step until the final x += alpha d.
     // The residual starts as b itself (b is not needed afterwards: the buffers swap roles), and
-    // the first iteration's coefficient kernel leaves r.r of the start in scal[7], read at the
+    // the first iteration's coefficient kernel leaves r_0.r_0 = |b|^2 in scal[7], read at the
     // first check (no synchronisation before the first iterations are queued; b = 0 converges
     // at that check with x = 0).
+    mark(ST_CG);
     HIPCHK(launch_fill<T>(M, x, T(0), s));
+    count(1);
     std::swap(r, b);
+    // Stop test.  Iteration k leaves in scal[7] the r_k.r_k that its forward z pass summed over
+    // the updated residual r_k, and in scal[0] the recurrence estimate of |r_{k+1}|^2 (used
+    // for beta only: it assumes the conjugacy of d_k and d_{k-1}).  With one iteration of
+    // look-ahead, iteration k+1 is queued before the values of k are read.  The solve has
+    // converged when the summed r_k.r_k is below the threshold, or when the estimate of
+    // |r_{k+1}|^2 is and the r_{k+1}.r_{k+1} that the queued iteration k+1 sums confirms it
+    // (a non-positive or drifted estimate alone never stops the solve).
+    auto slot = [&](int i) { return host_rr + 8 * (i & 1); };
+    double bb = 0.0;
     int it = 0;
     bool conv = false;
-    // one iteration of look-ahead: iteration k+1 is queued before the residual of k is read
+    auto nan_check = [&](double v) {
+      if (std::isnan(v)) throw DevErr{"NaN in the Schur CG residual"};
+    };
     while (!conv && it < maxit) {
       cg_iteration(it == 0);
-      if (it == 0) HIPCHK(hipMemcpyAsync(&host_rr[2], scal + 7, sizeof(double), hipMemcpyDeviceToHost, s));
-      HIPCHK(hipMemcpyAsync(&host_rr[it & 1], scal, sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipMemcpyAsync(slot(it), scal, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
       HIPCHK(hipEventRecord(ev[it & 1], s));
       ++it;
       if (it >= 2) {
-        HIPCHK(hipEventSynchronize(ev[(it - 2) & 1]));
-        if (!(host_rr[(it - 2) & 1] > rtol * rtol * host_rr[2])) conv = true;
-        if (std::isnan(host_rr[(it - 2) & 1])) throw DevErr{"NaN in the Schur CG residual"};
+        const int k = it - 2;
+        HIPCHK(hipEventSynchronize(ev[k & 1]));
+        if (k == 0) bb = slot(0)[7];
+        const double thr = rtol * rtol * bb, est = slot(k)[0], tru = slot(k)[7];
+        nan_check(est);
+        nan_check(tru);
+        if (!(tru > thr)) {
+          conv = true;
+        } else if (!(est > thr)) {
+          HIPCHK(hipEventSynchronize(ev[(k + 1) & 1]));
+          nan_check(slot(k + 1)[7]);
+          if (!(slot(k + 1)[7] > thr)) conv = true;
+        }
       }
     }
-    if (it > 0) HIPCHK(launch_axpy_scal<T>(M, x, d, scal, 1, s));  // the pending x += alpha d
-    if (!conv && it > 0) {
+    if (it > 0) {
+      HIPCHK(launch_axpy_scal<T>(M, x, d, scal, 1, s));  // the pending x += alpha d
+      count(3);
+    }
+    if (!conv && it > 0) {  // maxit reached: the last iteration's summed residual decides
       HIPCHK(hipEventSynchronize(ev[(it - 1) & 1]));
-      const double last = host_rr[(it - 1) & 1];
-      if (std::isnan(last)) throw DevErr{"NaN in the Schur CG residual"};
-      if (!(last > rtol * rtol * host_rr[2])) conv = true;
+      if (it == 1) bb = slot(0)[7];
+      nan_check(slot(it - 1)[7]);
+      if (!(slot(it - 1)[7] > rtol * rtol * bb)) conv = true;
     }
     project_mean(x);
-    if (c > 0) HIPCHK(launch_add_scalar<T>(M, x, scal, 9, 1.0 / ((double)M * c), s));  // + mean(b) / c
+    if (c > 0) {
+      HIPCHK(launch_add_scalar<T>(M, x, scal, 9, 1.0 / ((double)M * c), s));  // + mean(b) / c
+      count(2);
+    }
     // 4. velocity back-substitution u_m = T_m^T [(T_m F_m + sigma C_m p) / Lambda_m]: C_m p along
     // z and y shared as in the matvec, then per component the fused x pass and the y, z inverses
     // A = DST_z p, B = DCT_z p
+    mark(ST_BACKSUB);
     HIPCHK(launch_zfwd_cg<T>(N, ZF_PLAIN, nullptr, x, nullptr, nullptr, A, B, nullptr, nullptr, tb, s));
     if (sizeof(T) == 4) pass(DST2, 1, B, B3);                         // C_2 along y (order as in the matvec)
     HIPCHK(launch_ypair<T>(N, false, A, A, A1, B2, tb, s));          // C_0, C_1 along y
+    count(3 + 3);
     if (sizeof(T) != 4) pass(DST2, 1, B, B3);
     for (int m = 0; m < 3; ++m) {
       T* um = u + m * M;
       HIPCHK(launch_xfuse<T>(N, m, true, H[m], Fh[m], um, mu, tb, s));
+      count(3);
       pass(m == 1 ? DST1 : DST3, 1, um, um);
       pass(m == 2 ? DST1 : DST3, 2, um, um);
     }
-    if (p) HIPCHK(hipMemcpyAsync(p, x, M * sizeof(T), hipMemcpyDeviceToDevice, s));
+    if (p) {
+      HIPCHK(hipMemcpyAsync(p, x, M * sizeof(T), hipMemcpyDeviceToDevice, s));
+      count(2);
+    }
     if (prof_used) {
       HIPCHK(hipStreamSynchronize(s));
       prof_collect();
@@ -339,11 +436,13 @@ struct kfbi_ctx {
   // work
   double *jumps, *fitvals, *ejump, *F, *u, *p, *jbar, *fitbar;
   int* flag;
-  // volume force of the last BVP
+  // body force of the last kfbi_solve_bvp with f != NULL: the force jumps at the crossings (Fj)
+  // and the volume values at the interior nodes; has_force covers both (set together)
+  bool has_force = false;
   double* Fj = nullptr;
   double* vol_val = nullptr;
   int64_t* vol_idx = nullptr;
-  int64_t nvol = 0;
+  int64_t nvol = 0, vol_cap = 0;
   // solvers
   MacSolver<double> s64;
   MacSolver<float> s32;
@@ -365,17 +464,23 @@ struct kfbi_ctx {
   int32_t* prT_row = nullptr;
   double *pr_w = nullptr, *prT_w = nullptr;
   int gm_max = 0;
+  double* pbar = nullptr;  // probe cotangent pulled back to the density (kfbi_solve_bvp_adjoint)
   kfbi_info last;
+  // algorithmic HBM bytes of the surface stages of one evaluation (fit + jumps, corrections,
+  // interpolation), from the map sizes; refinement passes are counted as they run
+  double bytes_jumps = 0, bytes_correct = 0, bytes_interp = 0, bytes_extra = 0;
   // F is zero outside the irregular nodes (the correction pass then assigns those and no clear
   // of the 4 N^3 values is needed); false after any other writer of F
   bool f_clean = false;
-  // pinned host scalars read after a later synchronisation, and the stage events of an evaluation
+  // pinned host scalars read after a later synchronisation (hflag: non-finite input seen by the
+  // check of the current call), and the stage clock of a call
   double* hpin = nullptr;
-  hipEvent_t sev[4] = {nullptr, nullptr, nullptr, nullptr};
+  int* hflag = nullptr;
+  StageClock clock;
   ~kfbi_ctx() {
     if (hpin) (void)hipHostFree(hpin);
-    for (auto& e : sev)
-      if (e) (void)hipEventDestroy(e);
+    if (hflag) (void)hipHostFree(hflag);
+    clock.release();
     s64.release();
     s32.release();
     for (void* q : owned) (void)hipFree(q);
@@ -444,7 +549,9 @@ kfbi_status kfbi_create(const kfbi_config* cfg_in, kfbi_ctx** out) {
     hipStream_t s = C->s;
     auto& o = C->owned;
     HIPCHK(hipHostMalloc((void**)&C->hpin, 16 * sizeof(double), hipHostMallocDefault));
-    for (auto& e : C->sev) HIPCHK(hipEventCreate(&e));
+    HIPCHK(hipHostMalloc((void**)&C->hflag, sizeof(int), hipHostMallocDefault));
+    *C->hflag = 0;
+    C->clock.init();
     C->M = S.M;
     C->nb_ptr = dupload(S.nb_ptr, o, s);
     C->nb_idx = dupload(S.nb_idx, o, s);
@@ -509,6 +616,18 @@ kfbi_status kfbi_create(const kfbi_config* cfg_in, kfbi_ctx** out) {
     } else {
       C->s64.init(S.N, S.h, S.pde, S.mu, c, s, o);
     }
+    C->s32.clock = &C->clock;
+    C->s64.clock = &C->clock;
+    {  // surface-stage bytes: one read of every map entry used, gathers counted per element
+      const double T = (double)S.T, n = (double)S.n, nnz = (double)S.nb_idx.size();
+      const double nirr = (double)S.irr_node.size(), narm = (double)S.arm_t.size();
+      C->bytes_jumps = 8 * (T + 1) + nnz * (4 + 48 + 24) + T * (720 + 8 + 40) + 144 * n  // k_fit_jump
+                       + n * (8 + 144 + 432 + 24);                                      // k_interp_jump
+      C->bytes_correct = nirr * (8 + 8 + 8) + narm * (4 + 1 + 24 + 24);
+      C->bytes_interp = 3 * n * (8 + 80 + 80 + 80 + 8);                                  // k_interp
+      if (C->cfg.trace == KFBI_TRACE_AVERAGE)
+        C->bytes_interp += (double)S.sv_idx.size() * (4 + 8 + 24) + 3 * n * (8 + 8 + 8 + 8) + 8 * (n + 1);
+    }
     HIPCHK(hipStreamSynchronize(s));
   } catch (const DevErr& de) {
     g_create_error = de.msg;
@@ -554,38 +673,52 @@ kfbi_status kfbi_sizes(const kfbi_ctx* ctx, int64_t* n_crossings, int64_t* n_irr
 // ---------------------------------------------------------------------------------------
 namespace {
 
-double now_ms() {
-  return std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now().time_since_epoch()).count();
-}
-
+// Non-finite check of an input vector: the flag is cleared by a fill kernel, set by the check
+// kernel and copied to pinned host memory, all on the stream; it is read at the call's next
+// synchronisation (finish_input_check, or guarded() when the call fails), so the check costs
+// no synchronisation of its own.
 void check_finite(kfbi_ctx* C, const double* v, int64_t n) {
-  HIPCHK(hipMemsetAsync(C->flag, 0, sizeof(int), C->s));
+  HIPCHK(launch_fill<int>(1, C->flag, 0, C->s));
   HIPCHK(launch_check_finite(n, v, C->flag, C->s));
-  int f = 0;
-  HIPCHK(hipMemcpyAsync(&f, C->flag, sizeof(int), hipMemcpyDeviceToHost, C->s));
+  HIPCHK(hipMemcpyAsync(C->hflag, C->flag, sizeof(int), hipMemcpyDeviceToHost, C->s));
+}
+void finish_input_check(kfbi_ctx* C) {
   HIPCHK(hipStreamSynchronize(C->s));
-  if (f) throw std::invalid_argument("non-finite input");
+  if (*C->hflag) {
+    *C->hflag = 0;
+    throw std::invalid_argument("non-finite input");
+  }
 }
 
-// right-hand side F (4 fields) from the density (and the stored volume force)
 // blocks of the refinement passes and of the correction pass that stands in for the first of them
 // (3 partial sums each; 2048 measured slower)
 constexpr int kRefineParts = 1024;
 
+// right-hand side F (4 fields) from the density (and, with vol, the stored body force)
 void assemble_rhs(kfbi_ctx* C, const double* phi, bool vol) {
   const Setup& S = C->S;
   hipStream_t s = C->s;
-  const double* Fj = (vol && C->Fj) ? C->Fj : nullptr;
+  const bool force = vol && C->has_force;
+  const double* Fj = force ? C->Fj : nullptr;
+  C->clock.mark(ST_JUMPS, s);
   HIPCHK(launch_fit_jump(S.T, C->nb_ptr, C->nb_idx, C->fitw, C->jmap, C->jfmap, Fj, phi, C->cp_of, C->jumps,
                          C->fitvals, s));
   HIPCHK(launch_interp_jump(S.n, C->cp_target, C->fitvals, C->emap, C->efmap, Fj, C->ejump, s));
-  if (!C->f_clean) HIPCHK(launch_fill<double>(4 * S.M, C->F, 0.0, s));
-  const bool sparse = !(vol && C->nvol);
+  C->clock.mark(ST_CORRECT, s);
+  C->bytes_extra += C->bytes_jumps + C->bytes_correct;
+  if (!C->f_clean) {
+    HIPCHK(launch_fill<double>(4 * S.M, C->F, 0.0, s));
+    C->bytes_extra += 32.0 * (double)S.M;
+  }
+  const bool sparse = !(force && C->nvol);
   const int64_t nirr = (int64_t)S.irr_node.size();
   if (C->mixed && sparse) {
     // F is the corrections alone: the float32 right-hand side of the first refinement round
     // and its norm partials come from the correction pass (no dense pass over F)
-    if (!C->r32_clean) HIPCHK(launch_fill<float>(4 * S.M, C->r32, 0.0f, s));
+    if (!C->r32_clean) {
+      HIPCHK(launch_fill<float>(4 * S.M, C->r32, 0.0f, s));
+      C->bytes_extra += 16.0 * (double)S.M;
+    }
     HIPCHK(launch_correct(nirr, C->irr_node, C->irr_ptr, C->arm_t, C->arm_o, C->arm_a, C->jumps, C->F, s, C->r32,
                           S.M, C->rpart, kRefineParts));
     C->r32_clean = true;
@@ -597,6 +730,7 @@ void assemble_rhs(kfbi_ctx* C, const double* phi, bool vol) {
   C->f_clean = true;
   if (!sparse) {
     HIPCHK(launch_scatter_add(C->nvol, C->vol_idx, C->vol_val, C->F, s));
+    C->bytes_extra += 24.0 * (double)C->nvol;
     C->f_clean = false;
   }
 }
@@ -621,11 +755,13 @@ int mac_solve(kfbi_ctx* C, const double* F, double* u, double* p, kfbi_info* inf
   // modulo constants, which the inner solve projects out).
   const bool stokes = S.pde == KFBI_STOKES;
   const double c = stokes ? 0.0 : 1.0 / (S.lam + S.mu);
+  const double Md = (double)M;
   constexpr int NP = kRefineParts;
   // |F| is copied to pinned memory and read with the first residual norm: the first inner
   // solve is queued without a synchronisation (F = 0 gives x32 = 0 and a zero residual)
   if (!(C->r32_ready && C->f_clean && F == C->F)) {
     HIPCHK(launch_refine_prep(M, F, C->r32, C->rpart, NP, s));
+    C->bytes_extra += 48.0 * Md;
     C->r32_clean = false;
   }
   C->r32_ready = false;
@@ -646,8 +782,10 @@ int mac_solve(kfbi_ctx* C, const double* F, double* u, double* p, kfbi_info* inf
     total += it;
     double* nu = (rounds == 0 || cu != u) ? u : C->ru;
     double* np = (rounds == 0 || cu != u) ? p : C->ru + 3 * M;
+    C->clock.mark(ST_CG, s);
     HIPCHK(launch_refine_residual(rounds == 0, S.N, S.h, S.mu, c, cu, cp, C->x32, F, shift, nu, np, C->r32b, C->rpart,
                                   NP, s));
+    C->bytes_extra += (rounds == 0 ? 96.0 : 128.0) * Md;
     cu = nu;
     cp = np;
     HIPCHK(launch_reduce(C->rpart, NP, 3, C->rscal, R_RESNORM, stokes, M, s));
@@ -661,11 +799,13 @@ int mac_solve(kfbi_ctx* C, const double* F, double* u, double* p, kfbi_info* inf
   if (cu != u) {
     HIPCHK(hipMemcpyAsync(u, cu, 3 * M * sizeof(double), hipMemcpyDeviceToDevice, s));
     HIPCHK(hipMemcpyAsync(p, cp, M * sizeof(double), hipMemcpyDeviceToDevice, s));
+    C->bytes_extra += 64.0 * Md;
   }
   if (stokes) {
     HIPCHK(launch_sum_partials<double>(M, p, C->rpart, NP, s));
     HIPCHK(launch_reduce(C->rpart, NP, 1, C->rscal, R_SUM, 1, M, s));
     HIPCHK(launch_add_scalar<double>(M, p, C->rscal, 5, -1.0 / (double)M, s));
+    C->bytes_extra += 24.0 * Md;
   }
   if (info) {
     info->cg_iters += total;
@@ -674,27 +814,28 @@ int mac_solve(kfbi_ctx* C, const double* F, double* u, double* p, kfbi_info* inf
   return total;
 }
 
+// bytes counted by the solvers and the surface stages since the last call, into info
+void take_bytes(kfbi_ctx* C, kfbi_info* info) {
+  const double b = C->bytes_extra + C->s32.bytes + C->s64.bytes;
+  C->bytes_extra = C->s32.bytes = C->s64.bytes = 0;
+  if (info) info->model_bytes += b;
+}
+
 void eval_impl(kfbi_ctx* C, const double* phi, double* out, bool vol, kfbi_info* info) {
   const Setup& S = C->S;
   hipStream_t s = C->s;
   // stage times from events on the stream (no synchronisation between the stages)
-  HIPCHK(hipEventRecord(C->sev[0], s));
   assemble_rhs(C, phi, vol);
-  HIPCHK(hipEventRecord(C->sev[1], s));
   mac_solve(C, C->F, C->u, C->p, info);
-  HIPCHK(hipEventRecord(C->sev[2], s));
+  C->clock.mark(ST_INTERP, s);
   HIPCHK(launch_interp(S.n, C->itp_idx, C->itp_w, C->u, C->ejump, out, s));
   if (C->cfg.trace == KFBI_TRACE_AVERAGE)
     HIPCHK(launch_stab(S.n, C->sv_ptr, C->sv_idx, C->sv_w, C->stab_a, phi, out, s));
-  HIPCHK(hipEventRecord(C->sev[3], s));
-  HIPCHK(hipEventSynchronize(C->sev[3]));
-  if (info) {
-    float ms[4] = {0, 0, 0, 0};
-    for (int k = 0; k < 3; ++k) HIPCHK(hipEventElapsedTime(&ms[k], C->sev[k], C->sev[k + 1]));
-    HIPCHK(hipEventElapsedTime(&ms[3], C->sev[0], C->sev[3]));
-    for (int k = 0; k < 3; ++k) info->ms_stage[k] += ms[k];
-    info->ms_total += ms[3];
-  }
+  C->bytes_extra += C->bytes_interp;
+  C->clock.mark(ST_END, s);
+  HIPCHK(hipStreamSynchronize(s));
+  C->clock.collect(info);
+  take_bytes(C, info);
 }
 
 // Transpose of (density -> grid velocity of the double-layer interface problem), applied to
@@ -707,51 +848,91 @@ void transpose_from_velocity(kfbi_ctx* C, const double* w, double* out, kfbi_inf
   // transpose of the MAC solve: (F_u-bar, F_p-bar) = (u', -p') with (u', p') = solve(u-bar, 0)
   mac_solve(C, C->F, C->u, C->p, info);
   C->f_clean = false;
+  C->clock.mark(ST_CORRECT, s);
   HIPCHK(hipMemcpyAsync(C->F, C->u, 3 * M * sizeof(double), hipMemcpyDeviceToDevice, s));
   HIPCHK(launch_axpby<double>(M, C->F + 3 * M, -1.0, C->p, 0.0, s));
+  C->bytes_extra += 72.0 * (double)M;
   // corrections^T, jump maps^T (plus the interpolation jump term), fit^T
   HIPCHK(launch_correct_T(S.T, C->cT_ptr, C->cT_node, C->cT_slot, C->cT_a, C->F, C->jbar, s));
+  C->bytes_extra += C->bytes_correct;
+  C->clock.mark(ST_JUMPS, s);
   HIPCHK(launch_jump_T(S.T, C->cp_of, C->jmap, C->emap, C->jbar, w, C->fitbar, s));
   HIPCHK(launch_fit_T(S.n, C->fT_ptr, C->fT_entry, C->fT_target, C->fitw, C->fitbar, out, s));
-  HIPCHK(hipStreamSynchronize(s));
+  C->bytes_extra += C->bytes_jumps;
 }
 
 void adjoint_impl(kfbi_ctx* C, const double* w, double* out, kfbi_info* info) {
   const Setup& S = C->S;
   const int64_t M = S.M;
   hipStream_t s = C->s;
-  double t0 = now_ms();
   // u-bar = W^T w (F holds the solve's right-hand side (u-bar, 0))
   C->f_clean = false;
+  C->clock.mark(ST_INTERP, s);
   HIPCHK(launch_fill<double>(4 * M, C->F, 0.0, s));
   HIPCHK(launch_interp_T((int64_t)S.uT_node.size(), C->uT_ptr, C->uT_node, C->uT_row, C->uT_w, w, C->F, s));
+  C->bytes_extra += 32.0 * (double)M + C->bytes_interp;
   transpose_from_velocity(C, w, out, info);
   if (C->cfg.trace == KFBI_TRACE_AVERAGE) {
+    C->clock.mark(ST_INTERP, s);
     HIPCHK(launch_stab_T(S.n, C->svT_ptr, C->svT_row, C->svT_w, C->stab_a, w, out, s));
-    HIPCHK(hipStreamSynchronize(s));
   }
-  if (info) info->ms_total += now_ms() - t0;
+  C->clock.mark(ST_END, s);
+  HIPCHK(hipStreamSynchronize(s));
+  C->clock.collect(info);
+  take_bytes(C, info);
 }
 
 template <typename F>
 kfbi_status guarded(kfbi_ctx* C, F&& f) {
   if (!C) return KFBI_EINVAL;
+  auto bad_input = [&]() -> bool {  // a failure caused by a non-finite input reports EINVAL
+    (void)hipStreamSynchronize(C->s);
+    const bool b = *C->hflag != 0;
+    *C->hflag = 0;
+    return b;
+  };
+  C->clock.used = 0;
+  C->bytes_extra = C->s32.bytes = C->s64.bytes = 0;
   try {
     f();
     return KFBI_OK;
   } catch (const DevErr& e) {
     C->err = e.msg;
+    if (bad_input()) {
+      C->err = "non-finite input";
+      return KFBI_EINVAL;
+    }
     return KFBI_EDEVICE;
   } catch (const std::invalid_argument& e) {
     C->err = e.what();
     return KFBI_EINVAL;
   } catch (const std::runtime_error& e) {
     C->err = e.what();
+    if (bad_input()) {
+      C->err = "non-finite input";
+      return KFBI_EINVAL;
+    }
     return std::string(e.what()).rfind("ENOCONV", 0) == 0 ? KFBI_ENOCONV : KFBI_EDEVICE;
   } catch (const std::bad_alloc&) {
     C->err = "host allocation failed";
     return KFBI_ENOMEM;
   }
+}
+
+// transpose of density -> probe values of the unified interface solve (the affine body-force
+// part drops out), into phi_bar
+void probe_adjoint_impl(kfbi_ctx* C, const double* vals_bar, double* phi_bar, kfbi_info* info) {
+  hipStream_t s = C->s;
+  C->f_clean = false;
+  C->clock.mark(ST_INTERP, s);
+  HIPCHK(launch_fill<double>(4 * C->S.M, C->F, 0.0, s));
+  HIPCHK(launch_interp_T(C->nprobe_nodes, C->prT_ptr, C->prT_node, C->prT_row, C->prT_w, vals_bar, C->F, s));
+  C->bytes_extra += 32.0 * (double)C->S.M;
+  transpose_from_velocity(C, nullptr, phi_bar, info);
+  C->clock.mark(ST_END, s);
+  HIPCHK(hipStreamSynchronize(s));
+  C->clock.collect(info);
+  take_bytes(C, info);
 }
 
 // GMRES dot product into a device slot (float64, deterministic)
@@ -787,7 +968,11 @@ int gmres(kfbi_ctx* C, const double* rhs, double* phi, double tol, int maxit, do
   const Setup& S = C->S;
   const int64_t n3 = 3 * S.n;
   hipStream_t s = C->s;
-  if (C->gm_max < maxit) {
+  if (C->gm_max < maxit) {  // Krylov basis and Hessenberg columns, regrown (old buffers freed)
+    dfree(C->V, C->owned);
+    dfree(C->H, C->owned);
+    C->V = C->H = nullptr;
+    C->gm_max = 0;
     C->V = dalloc<double>((size_t)(maxit + 1) * n3, C->owned);
     C->H = dalloc<double>((size_t)(maxit + 2) * (maxit + 1) + 16, C->owned);
     C->gm_max = maxit;
@@ -795,11 +980,11 @@ int gmres(kfbi_ctx* C, const double* rhs, double* phi, double tol, int maxit, do
   if (!C->rpart) C->rpart = dalloc<double>(3 * 2048, C->owned);
   if (!C->rscal) C->rscal = dalloc<double>(16, C->owned);
   const int LD = maxit + 2;  // column stride of H
-  double* scratch = C->rscal;  // scratch[5] = norm^2
+  double* sc = C->rscal;  // sc[5] = norm^2, sc[6] = norm
   HIPCHK(hipMemcpyAsync(C->V, rhs, n3 * sizeof(double), hipMemcpyDeviceToDevice, s));
-  dev_dot(C, C->V, C->V, n3, scratch + 5);
+  dev_dot(C, C->V, C->V, n3, sc + 5);
   double beta2 = 0;
-  HIPCHK(hipMemcpyAsync(&beta2, scratch + 5, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&beta2, sc + 5, sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   const double beta = std::sqrt(beta2);
   HIPCHK(launch_fill<double>(n3, phi, 0.0, s));
@@ -807,7 +992,7 @@ int gmres(kfbi_ctx* C, const double* rhs, double* phi, double tol, int maxit, do
     *relres = 0;
     return 0;
   }
-  hipLaunchKernelGGL(k_scale_inv_norm, dim3(64), dim3(256), 0, s, n3, C->V, scratch + 5, scratch + 6);
+  hipLaunchKernelGGL(k_scale_inv_norm, dim3(64), dim3(256), 0, s, n3, C->V, sc + 5, sc + 6);
   std::vector<double> Hh((size_t)LD * (maxit + 1), 0.0), cs(maxit + 1), sn(maxit + 1), g(maxit + 2, 0.0);
   g[0] = beta;
   int k = 0;
@@ -824,8 +1009,8 @@ int gmres(kfbi_ctx* C, const double* rhs, double* phi, double tol, int maxit, do
       dev_dot(C, C->V + (size_t)i * n3, w, n3, Hc + i);
       hipLaunchKernelGGL(k_axpy_dev, dim3(64), dim3(256), 0, s, n3, w, C->V + (size_t)i * n3, Hc + i, -1.0);
     }
-    dev_dot(C, w, w, n3, scratch + 5);
-    hipLaunchKernelGGL(k_scale_inv_norm, dim3(64), dim3(256), 0, s, n3, w, scratch + 5, Hc + k + 1);
+    dev_dot(C, w, w, n3, sc + 5);
+    hipLaunchKernelGGL(k_scale_inv_norm, dim3(64), dim3(256), 0, s, n3, w, sc + 5, Hc + k + 1);
     HIPCHK(hipGetLastError());
     std::vector<double> col(k + 2);
     HIPCHK(hipMemcpyAsync(col.data(), Hc, (k + 2) * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -896,11 +1081,20 @@ void set_volume_force(kfbi_ctx* C, kfbi_vec_fn f, void* user) {
   }
   std::vector<double> Fj(3 * S.T);
   f(S.xyz.data(), S.T, Fj.data(), user);
+  for (double v : Fj)
+    if (!std::isfinite(v)) throw std::invalid_argument("non-finite body force");
+  C->has_force = false;
   if (!C->Fj) C->Fj = dalloc<double>(3 * S.T, C->owned);
   HIPCHK(hipMemcpyAsync(C->Fj, Fj.data(), Fj.size() * sizeof(double), hipMemcpyHostToDevice, s));
-  if (C->nvol < nv || !C->vol_idx) {
+  if (C->vol_cap < nv || !C->vol_idx) {
+    dfree(C->vol_idx, C->owned);
+    dfree(C->vol_val, C->owned);
+    C->vol_idx = nullptr;
+    C->vol_val = nullptr;
+    C->vol_cap = 0;
     C->vol_idx = dalloc<int64_t>(std::max<int64_t>(nv, 1), C->owned);
     C->vol_val = dalloc<double>(std::max<int64_t>(nv, 1), C->owned);
+    C->vol_cap = std::max<int64_t>(nv, 1);
   }
   C->nvol = nv;
   if (nv) {
@@ -908,6 +1102,7 @@ void set_volume_force(kfbi_ctx* C, kfbi_vec_fn f, void* user) {
     HIPCHK(hipMemcpyAsync(C->vol_val, val.data(), nv * sizeof(double), hipMemcpyHostToDevice, s));
   }
   HIPCHK(hipStreamSynchronize(s));
+  C->has_force = true;
 }
 
 }  // namespace
@@ -920,6 +1115,7 @@ kfbi_status kfbi_eval(kfbi_ctx* C, const double* phi, double* out, kfbi_info* in
   return guarded(C, [&] {
     check_finite(C, phi, 3 * C->S.n);
     eval_impl(C, phi, out, false, info);
+    finish_input_check(C);
   });
 }
 
@@ -929,6 +1125,7 @@ kfbi_status kfbi_eval_adjoint(kfbi_ctx* C, const double* w, double* out, kfbi_in
   return guarded(C, [&] {
     check_finite(C, w, 3 * C->S.n);
     adjoint_impl(C, w, out, info);
+    finish_input_check(C);
   });
 }
 
@@ -940,6 +1137,7 @@ kfbi_status kfbi_solve_bvp(kfbi_ctx* C, const double* g, kfbi_vec_fn f, void* us
     const Setup& S = C->S;
     const int64_t n3 = 3 * S.n;
     check_finite(C, g, n3);
+    finish_input_check(C);
     if (!C->gtmp) C->gtmp = dalloc<double>(n3, C->owned);
     if (f) {
       set_volume_force(C, f, user);
@@ -948,7 +1146,6 @@ kfbi_status kfbi_solve_bvp(kfbi_ctx* C, const double* g, kfbi_vec_fn f, void* us
       eval_impl(C, phi, C->gtmp, true, info);
       HIPCHK(launch_axpby<double>(n3, C->gtmp, 1.0, g, -1.0, C->s));  // g - b
     } else {
-      C->nvol = 0;
       HIPCHK(hipMemcpyAsync(C->gtmp, g, n3 * sizeof(double), hipMemcpyDeviceToDevice, C->s));
     }
     double rr = 0;
@@ -958,7 +1155,10 @@ kfbi_status kfbi_solve_bvp(kfbi_ctx* C, const double* g, kfbi_vec_fn f, void* us
       mac_solve(C, C->F, C->u, C->p, info);
       if (u_ext) HIPCHK(launch_export_u(S.N, C->u, u_ext, C->s));
       if (p_ext) HIPCHK(hipMemcpyAsync(p_ext, C->p, S.M * sizeof(double), hipMemcpyDeviceToDevice, C->s));
+      C->clock.mark(ST_END, C->s);
       HIPCHK(hipStreamSynchronize(C->s));
+      C->clock.collect(info);
+      take_bytes(C, info);
     }
   });
 }
@@ -974,7 +1174,10 @@ kfbi_status kfbi_interface_solve(kfbi_ctx* C, const double* phi, int32_t use_for
     mac_solve(C, C->F, C->u, C->p, info);
     if (u_ext) HIPCHK(launch_export_u(S.N, C->u, u_ext, C->s));
     if (p_ext) HIPCHK(hipMemcpyAsync(p_ext, C->p, S.M * sizeof(double), hipMemcpyDeviceToDevice, C->s));
-    HIPCHK(hipStreamSynchronize(C->s));
+    C->clock.mark(ST_END, C->s);
+    finish_input_check(C);
+    C->clock.collect(info);
+    take_bytes(C, info);
   });
 }
 
@@ -1195,8 +1398,12 @@ kfbi_status kfbi_probe(kfbi_ctx* C, const double* phi, int32_t use_force, double
     assemble_rhs(C, phi, use_force != 0);
     mac_solve(C, C->F, C->u, C->p, info);
     // trilinear interpolation: 8 weights per (probe, component)
+    C->clock.mark(ST_INTERP, C->s);
     HIPCHK(launch_interp8(C->nprobe, C->pr_idx, C->pr_w, C->u, vals, C->s));
-    HIPCHK(hipStreamSynchronize(C->s));
+    C->clock.mark(ST_END, C->s);
+    finish_input_check(C);
+    C->clock.collect(info);
+    take_bytes(C, info);
   });
 }
 
@@ -1209,10 +1416,8 @@ kfbi_status kfbi_probe_adjoint(kfbi_ctx* C, const double* vals_bar, double* phi_
   }
   return guarded(C, [&] {
     check_finite(C, vals_bar, 3 * C->nprobe);
-    C->f_clean = false;
-    HIPCHK(launch_fill<double>(4 * C->S.M, C->F, 0.0, C->s));
-    HIPCHK(launch_interp_T(C->nprobe_nodes, C->prT_ptr, C->prT_node, C->prT_row, C->prT_w, vals_bar, C->F, C->s));
-    transpose_from_velocity(C, nullptr, phi_bar, info);
+    probe_adjoint_impl(C, vals_bar, phi_bar, info);
+    finish_input_check(C);
   });
 }
 
@@ -1222,10 +1427,40 @@ kfbi_status kfbi_solve_adjoint(kfbi_ctx* C, const double* rhs, double* y, kfbi_i
   return guarded(C, [&] {
     const int64_t n3 = 3 * C->S.n;
     check_finite(C, rhs, n3);
+    finish_input_check(C);
     if (!C->gtmp) C->gtmp = dalloc<double>(n3, C->owned);
     HIPCHK(hipMemcpyAsync(C->gtmp, rhs, n3 * sizeof(double), hipMemcpyDeviceToDevice, C->s));
     double rr = 0;
     gmres(C, C->gtmp, y, C->cfg.gmres_rtol, C->cfg.gmres_maxit, &rr, info, true);
+  });
+}
+
+kfbi_status kfbi_solve_bvp_adjoint(kfbi_ctx* C, const double* vals_bar, double* g_bar, double* phi_bar,
+                                   kfbi_info* info) {
+  if (!C || !vals_bar || (!g_bar && !phi_bar)) return KFBI_EINVAL;
+  if (info) std::memset(info, 0, sizeof(*info));
+  if (C->nprobe == 0) {
+    C->err = "no probes set";
+    return KFBI_EINVAL;
+  }
+  return guarded(C, [&] {
+    const int64_t n3 = 3 * C->S.n;
+    check_finite(C, vals_bar, 3 * C->nprobe);
+    finish_input_check(C);
+    // phi-bar = P^T v-bar (probe values as a function of the density), then g-bar = K^{-T} phi-bar
+    double* pb = phi_bar;
+    if (!pb) {
+      if (!C->pbar) C->pbar = dalloc<double>(n3, C->owned);
+      pb = C->pbar;
+    }
+    probe_adjoint_impl(C, vals_bar, pb, info);
+    HIPCHK(hipStreamSynchronize(C->s));
+    if (g_bar) {
+      if (!C->gtmp) C->gtmp = dalloc<double>(n3, C->owned);
+      HIPCHK(hipMemcpyAsync(C->gtmp, pb, n3 * sizeof(double), hipMemcpyDeviceToDevice, C->s));
+      double rr = 0;
+      gmres(C, C->gtmp, g_bar, C->cfg.gmres_rtol, C->cfg.gmres_maxit, &rr, info, true);
+    }
   });
 }
 

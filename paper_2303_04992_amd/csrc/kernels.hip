@@ -918,7 +918,9 @@ __global__ __launch_bounds__(CG_NT) void k_cg_coef(const double* __restrict__ rp
     const double qq = tot[4] - (stokes ? mq * mq * (double)M : 0.0);
     const double alpha = (dq != 0.0) ? rr / dq : 0.0;
     double rn = alpha * alpha * qq - rr;
-    if (!(rn > 0.0)) rn = (rn == rn) ? 0.0 : rn;  // a rounding-level negative value means converged
+    // a non-positive estimate (cancellation near convergence, or lost conjugacy) restarts the
+    // directions with beta = 0; the host never stops the solve on this estimate alone
+    if (!(rn > 0.0)) rn = (rn == rn) ? 0.0 : rn;
     scal[0] = rn;
     scal[1] = alpha;
     scal[2] = (rr > 0.0) ? rn / rr : 0.0;
@@ -1729,5 +1731,6 @@ hipError_t launch_check_finite(int64_t n, const double* a, int* flag, hipStream_
   template hipError_t launch_axpby<T>(int64_t, T*, double, const T*, double, hipStream_t);
 KFBI_INST(float)
 KFBI_INST(double)
+template hipError_t launch_fill<int>(int64_t, int*, int, hipStream_t);
 
 }  // namespace kfbi

@@ -59,3 +59,36 @@ def test_interleaved_calls_leave_evaluations_unchanged(K, prec, name):
     check("probe_adjoint")
     op.eval(2.0 * phi)
     check("eval of another density")
+
+
+def test_stored_force_survives_a_force_free_solve(K):
+    """The body force of the last kfbi_solve_bvp with f != NULL (its crossing jumps and its
+    volume values, kept together) is what kfbi_probe(use_force=1) adds, also after a force-free
+    BVP solve on the same context; the probe values match the oracle's unified interface solve
+    with that force."""
+    import torch
+    from oracle.kfbi import Oracle
+    cfg = KI.WORKLOADS["sphere32"]
+    op = K.Operator(cfg, K.FP64, cg_rtol=1e-13)
+    probes = KI.probe_points(cfg, 256, seed=0)
+    op.set_probes(probes)
+    xyz, _ = op.points()
+    g = torch.as_tensor(KI.exact_u(cfg.solution, xyz[:, 0], xyz[:, 1], xyz[:, 2]), device="cuda")
+    f = lambda x, y, z: KI.body_force(cfg.solution, x, y, z, cfg.mu, cfg.lam)
+    phi = torch.as_tensor(KI.random_density(op.n, seed=4), device="cuda")
+    op.solve_bvp(g, f, return_fields=False)
+    forced = op.probe(phi, use_force=True).cpu().numpy()
+    free = op.probe(phi, use_force=False).cpu().numpy()
+    op.solve_bvp(g, None, return_fields=False)
+    again = op.probe(phi, use_force=True).cpu().numpy()
+    d = np.abs(again - forced).max() / np.abs(forced).max()
+    _say(f"[force] probe with the stored force after a force-free solve: rel diff {d:.2e}")
+    assert d < 1e-12
+    assert np.abs(forced - free).max() > 1e-3 * np.abs(forced).max()
+    O = Oracle(cfg, form="average")
+    _, uo, _ = O.interface_solve(phi.cpu().numpy(), f)
+    import test_gpu_autograd as TA
+    ref = TA._trilinear(uo, probes, cfg.N, cfg.lo, cfg.h)
+    r = np.abs(forced - ref).max() / np.abs(ref).max()
+    _say(f"   against the oracle: rel max {r:.2e}")
+    assert r < 1e-10

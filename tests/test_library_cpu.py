@@ -125,7 +125,8 @@ def _compare(name, N):
     assert np.abs(el - eo).max() < 1e-11 * max(1.0, np.abs(eo).max())
 
 
-@pytest.mark.parametrize("name,N", [("sphere32", 32), ("ellip128", 32), ("star128", 32)])
+@pytest.mark.parametrize("name,N", [("sphere32", 32), ("ellip128", 32), ("star128", 32), ("ex53", 32),
+                                    ("ex56", 32)])
 def test_host_setup_matches_oracle(name, N):
     _compare(name, N)
 

@@ -404,3 +404,66 @@ def test_paper_example_solutions_are_consistent():
             f = -cfg.mu * lap - (cfg.lam + cfg.mu) * gdiv
         fo = KI.body_force(cfg.solution, P[:, 0], P[:, 1], P[:, 2], cfg.mu, cfg.lam)
         assert np.abs(f - fo).max() < 1e-4 * (1 + np.abs(fo).max()), name
+
+
+# ------------------------------------------------------------------------------------------
+# Torus level set (Sec. 5, Examples 5.3 and 5.6): crossings, normals and curvatures against
+# the closed-form roots and principal curvatures of the torus
+# ------------------------------------------------------------------------------------------
+def _torus_roots(a, c, k, q):
+    """Roots along a k-line of psi = sqrt((rho - c)^2 + z^2) - a, rho = sqrt(x^2 + y^2), with
+    the two transverse coordinates q (in axis order).  Solved in closed form: for a z-line,
+    z = +-sqrt(a^2 - (rho - c)^2); for an x-line (y = q0, z = q1, and likewise for y-lines),
+    rho = c +- sqrt(a^2 - z^2) and x = +-sqrt(rho^2 - y^2)."""
+    out = []
+    if k == 2:
+        rho = math.hypot(q[0], q[1])
+        s = a * a - (rho - c) ** 2
+        if s > 0:
+            out = [-math.sqrt(s), math.sqrt(s)]
+    else:
+        other, z = q[0], q[1]
+        s = a * a - z * z
+        if s > 0:
+            for rho in (c - math.sqrt(s), c + math.sqrt(s)):
+                t = rho * rho - other * other
+                if rho > 0 and t > 0:
+                    out += [-math.sqrt(t), math.sqrt(t)]
+    return sorted(out)
+
+
+@pytest.mark.parametrize("N", [32, 64])
+def test_torus_crossings_normals_curvature_closed_form(N):
+    """Every crossing of the oracle on the torus of Examples 5.3 / 5.6 (a = 0.35, c = 0.7, box
+    [-1.2, 1.2]^3) is one closed-form root of its grid line, every root is found (lines through
+    the hole cross four times), the normal is the closed-form one and the curvature tensor has
+    the torus's principal curvatures -1/a and -(rho - c)/(a rho) (sphere convention -1/R)."""
+    from oracle.geometry import FAMILIES, transverse_axes
+    cfg = KI.WORKLOADS["ex53"].with_N(N)
+    a, c = cfg.shape.param[0], cfg.shape.param[1]
+    grid, ls = Grid(N, cfg.lo, cfg.hi), LevelSet(cfg.shape)
+    cr = build_crossings(grid, ls)
+    h = grid.h
+    lines = {}
+    for t in range(len(cr.fam)):
+        lines.setdefault((int(cr.fam[t]), int(cr.line[t, 0]), int(cr.line[t, 1])), []).append(t)
+    four = 0
+    for (f, i1, i2), ts in lines.items():
+        k, g = FAMILIES[f]
+        ax = transverse_axes(k)
+        q = [cfg.lo + (ii + (0.0 if d == g else 0.5)) * h for ii, d in zip((i1, i2), ax)]
+        roots = _torus_roots(a, c, k, q)
+        # grazing lines (two roots within one half-step sample interval) are not resolved by
+        # the sign test; the workloads have none within 1e-3 h
+        pos = sorted(cr.pos[ts])
+        assert len(pos) == len(roots), (f, i1, i2, pos, roots)
+        assert np.abs(np.array(pos) - np.array(roots)).max() < 1e-13
+        four += len(roots) == 4
+    assert four > 0  # lines through the hole
+    X = cr.xyz
+    rho = np.hypot(X[:, 0], X[:, 1])
+    n_exact = np.stack([(rho - c) * X[:, 0] / rho, (rho - c) * X[:, 1] / rho, X[:, 2]], -1) / a
+    assert np.abs(cr.normal - n_exact).max() < 1e-12
+    ev = np.sort(np.linalg.eigvalsh(0.5 * (cr.kappa + cr.kappa.transpose(0, 2, 1))), axis=1)
+    ex = np.sort(np.stack([np.full(len(rho), -1.0 / a), -(rho - c) / (a * rho)], -1), axis=1)
+    assert np.abs(ev - ex).max() < 1e-10
