@@ -139,6 +139,18 @@ kfbi_status kfbi_sizes(const kfbi_ctx* ctx, int64_t* n_crossings, int64_t* n_irr
  * EINVAL. */
 kfbi_status kfbi_eval(kfbi_ctx* ctx, const double* phi_dev, double* out_dev, kfbi_info* info);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid hipMalloc): kfbi_eval with every per-call work buffer
+ * (MAC solver fields, right-hand side, grid solution, surface-stage values, partial sums)
+ * carved from a static device array of KFBI_NOALLOC_MAX_BYTES that each device holds until
+ * the process ends, instead of the context's own workspaces; it calls no allocator.  Same
+ * arguments, result and errors as kfbi_eval, and EINVAL when the context's evaluation needs
+ * more scratch than the limit (64 MiB: N <= 64 in either precision).  All calls on one device
+ * share that device's array: calls that overlap in time on one device (several host threads or
+ * streams) race and must be serialised by the caller. */
+#define KFBI_NOALLOC_MAX_BYTES (64ull << 20)
+kfbi_status kfbi_eval_noalloc(kfbi_ctx* ctx, const double* phi_dev, double* out_dev, kfbi_info* info);
+
 /* Transpose of kfbi_eval (in the context's trace form): out = K^T w (same shapes). */
 kfbi_status kfbi_eval_adjoint(kfbi_ctx* ctx, const double* w_dev, double* out_dev, kfbi_info* info);
 

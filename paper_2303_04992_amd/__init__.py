@@ -81,6 +81,7 @@ _sig = {
     "kfbi_sizes": (C.c_int, [_P, C.POINTER(C.c_int64), C.POINTER(C.c_int64)]),
     "kfbi_eval": (C.c_int, [_P, _P, _P, C.POINTER(Info)]),
     "kfbi_eval_adjoint": (C.c_int, [_P, _P, _P, C.POINTER(Info)]),
+    "kfbi_eval_noalloc": (C.c_int, [_P, _P, _P, C.POINTER(Info)]),
     "kfbi_solve_bvp": (C.c_int, [_P, _P, VecFn, _P, _P, _P, _P, C.POINTER(Info)]),
     "kfbi_interface_solve": (C.c_int, [_P, _P, C.c_int32, _P, _P, C.POINTER(Info)]),
     "kfbi_set_probes": (C.c_int, [_P, _P, C.c_int64]),
@@ -214,6 +215,17 @@ class Operator:
         out = torch.empty_like(phi)
         info = Info()
         self._check(_lib.kfbi_eval(self._h, _ptr(phi), _ptr(out), C.byref(info)))
+        self.last_info = info.as_dict()
+        return out
+
+    def eval_noalloc(self, phi, out=None):
+        """K phi through kfbi_eval_noalloc (work buffers in the library's static device scratch;
+        the caller provides phi and out)."""
+        torch = _torch()
+        phi = self._vec(phi)
+        out = torch.empty_like(phi) if out is None else out
+        info = Info()
+        self._check(_lib.kfbi_eval_noalloc(self._h, _ptr(phi), _ptr(out), C.byref(info)))
         self.last_info = info.as_dict()
         return out
 

@@ -13,6 +13,7 @@
 #include <cstdio>
 #include <cstring>
 #include <memory>
+#include <mutex>
 #include <string>
 #include <type_traits>
 #include <vector>
@@ -24,9 +25,31 @@
 
 using namespace kfbi;
 
+// Device scratch of kfbi_eval_noalloc: the per-call work buffers of one evaluation (MAC solver
+// fields, right-hand side, grid solution, surface-stage values, partial sums) are carved from
+// this array instead of the context's own workspaces.  Every device the library runs on holds
+// one copy (KFBI_NOALLOC_MAX_BYTES) until the process ends.  In host code the array's name is
+// only a stand-in: its device address on each device comes from hipGetSymbolAddress.
+static __device__ __align__(256) unsigned char scratch[KFBI_NOALLOC_MAX_BYTES];
+
 namespace {
 
 thread_local std::string g_create_error;
+
+// device address of `scratch` per device, looked up once per device with that device current
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[64] = {};
+
+void* scratch_address(int dev) {
+  if (dev < 0 || dev >= 64) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
 
 struct DevErr {
   std::string msg;
@@ -98,6 +121,29 @@ struct StageClock {
     }
     used = 0;
   }
+};
+
+// Sequential carving of device buffers (256-byte aligned) from one region; with base ==
+// nullptr it only measures the bytes the same carving needs.
+struct Arena {
+  char* base = nullptr;
+  size_t size = 0, used = 0;
+  template <typename T>
+  T* take(size_t n) {
+    const size_t off = (used + 255) & ~(size_t)255;
+    const size_t bytes = std::max<size_t>(n, 1) * sizeof(T);
+    used = off + bytes;
+    if (!base) return nullptr;
+    if (used > size) throw std::invalid_argument("scratch region too small");
+    return reinterpret_cast<T*>(base + off);
+  }
+};
+
+// the work buffers of a MacSolver (everything a solve writes)
+template <typename T>
+struct SolverPtrs {
+  T *Fh[3], *b, *x, *r, *d, *q, *A, *B, *A1, *B2, *B3;
+  double *partials, *rpart, *scal;
 };
 
 // ---------------------------------------------------------------------------------------
@@ -206,6 +252,23 @@ struct MacSolver {
     for (auto& e : ev)
       if (e) (void)hipEventDestroy(e);
     ev[0] = ev[1] = nullptr;
+  }
+
+  SolverPtrs<T> ptrs() const { return {{Fh[0], Fh[1], Fh[2]}, b, x, r, d, q, A, B, A1, B2, B3, partials, rpart, scal}; }
+  void set(const SolverPtrs<T>& w) {
+    for (int m = 0; m < 3; ++m) Fh[m] = w.Fh[m];
+    b = w.b, x = w.x, r = w.r, d = w.d, q = w.q, A = w.A, B = w.B, A1 = w.A1, B2 = w.B2, B3 = w.B3;
+    partials = w.partials, rpart = w.rpart, scal = w.scal;
+  }
+  // the same buffers carved from an arena (sizes as in init)
+  SolverPtrs<T> carve(Arena& a) const {
+    SolverPtrs<T> w;
+    for (auto& f : w.Fh) f = a.take<T>(M);
+    for (T** f : {&w.b, &w.x, &w.r, &w.d, &w.q, &w.A, &w.B, &w.A1, &w.B2, &w.B3}) *f = a.take<T>(M);
+    w.partials = a.take<double>(std::max(4 * nparts_x, nparts_u));
+    w.rpart = a.take<double>(nparts_z);
+    w.scal = a.take<double>(16);
+    return w;
   }
 
   // launch under HIP events when kernel id (and axis, for the single passes) is being timed
@@ -423,6 +486,7 @@ struct kfbi_ctx {
   kfbi_config cfg;
   Setup S;
   std::string err;
+  int dev = 0;  // device current at kfbi_create
   hipStream_t s = nullptr;
   std::vector<void*> owned;
   int64_t M = 0;
@@ -548,6 +612,8 @@ kfbi_status kfbi_create(const kfbi_config* cfg_in, kfbi_ctx** out) {
       HIPCHK(hipStreamCreate(&C->s));
     hipStream_t s = C->s;
     auto& o = C->owned;
+    HIPCHK(hipGetDevice(&C->dev));
+    if (!scratch_address(C->dev)) throw DevErr{"hipGetSymbolAddress of the no-alloc scratch failed"};
     HIPCHK(hipHostMalloc((void**)&C->hpin, 16 * sizeof(double), hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void**)&C->hflag, sizeof(int), hipHostMallocDefault));
     *C->hflag = 0;
@@ -919,6 +985,72 @@ kfbi_status guarded(kfbi_ctx* C, F&& f) {
   }
 }
 
+// The per-call work buffers of an evaluation (everything kfbi_eval writes besides its output):
+// swapped for buffers carved from the no-alloc scratch for one call, then restored.
+struct WorkSet {
+  double *jumps, *fitvals, *ejump, *F, *u, *p, *ru, *rscal, *rpart;
+  float *r32, *r32b, *x32;
+  int* flag;
+  SolverPtrs<float> s32;
+  SolverPtrs<double> s64;
+  bool f_clean, r32_clean, r32_ready;
+  int prof32, prof64;
+};
+
+WorkSet get_work(const kfbi_ctx* C) {
+  return {C->jumps, C->fitvals, C->ejump, C->F, C->u, C->p, C->ru, C->rscal, C->rpart, C->r32, C->r32b, C->x32,
+          C->flag, C->s32.ptrs(), C->s64.ptrs(), C->f_clean, C->r32_clean, C->r32_ready,
+          C->s32.prof_kind, C->s64.prof_kind};
+}
+
+void set_work(kfbi_ctx* C, const WorkSet& w) {
+  C->jumps = w.jumps, C->fitvals = w.fitvals, C->ejump = w.ejump, C->F = w.F, C->u = w.u, C->p = w.p;
+  C->ru = w.ru, C->rscal = w.rscal, C->rpart = w.rpart, C->r32 = w.r32, C->r32b = w.r32b, C->x32 = w.x32;
+  C->flag = w.flag;
+  if (C->mixed)
+    C->s32.set(w.s32);
+  else
+    C->s64.set(w.s64);
+  C->f_clean = w.f_clean, C->r32_clean = w.r32_clean, C->r32_ready = w.r32_ready;
+  C->s32.prof_kind = w.prof32, C->s64.prof_kind = w.prof64;
+}
+
+// the work buffers of one evaluation carved from an arena (sizes as in kfbi_create); the scratch
+// keeps whatever the last call left, so every buffer that is read before it is written starts
+// dirty (dense clears of F and of the float32 right-hand side) and profiling is off
+WorkSet carve_work(const kfbi_ctx* C, Arena& a) {
+  const Setup& S = C->S;
+  WorkSet w = get_work(C);
+  w.jumps = a.take<double>(5 * S.T);
+  w.fitvals = a.take<double>(18 * S.n);
+  w.ejump = a.take<double>(3 * S.n);
+  w.F = a.take<double>(4 * S.M);
+  w.u = a.take<double>(3 * S.M);
+  w.p = a.take<double>(S.M);
+  w.flag = a.take<int>(1);
+  if (C->mixed) {
+    w.ru = a.take<double>(4 * S.M);
+    w.r32 = a.take<float>(4 * S.M);
+    w.r32b = a.take<float>(4 * S.M);
+    w.x32 = a.take<float>(4 * S.M);
+    w.rscal = a.take<double>(16);
+    w.rpart = a.take<double>(3 * 2048);
+    w.s32 = C->s32.carve(a);
+  } else {
+    w.s64 = C->s64.carve(a);
+  }
+  w.f_clean = w.r32_clean = w.r32_ready = false;
+  w.prof32 = w.prof64 = -1;
+  return w;
+}
+
+// bytes of the no-alloc scratch an evaluation on this context needs
+size_t noalloc_bytes(const kfbi_ctx* C) {
+  Arena a;
+  (void)carve_work(C, a);
+  return a.used;
+}
+
 // transpose of density -> probe values of the unified interface solve (the affine body-force
 // part drops out), into phi_bar
 void probe_adjoint_impl(kfbi_ctx* C, const double* vals_bar, double* phi_bar, kfbi_info* info) {
@@ -1113,6 +1245,32 @@ kfbi_status kfbi_eval(kfbi_ctx* C, const double* phi, double* out, kfbi_info* in
   if (!C || !phi || !out) return KFBI_EINVAL;
   if (info) std::memset(info, 0, sizeof(*info));
   return guarded(C, [&] {
+    check_finite(C, phi, 3 * C->S.n);
+    eval_impl(C, phi, out, false, info);
+    finish_input_check(C);
+  });
+}
+
+kfbi_status kfbi_eval_noalloc(kfbi_ctx* C, const double* phi, double* out, kfbi_info* info) {
+  if (!C || !phi || !out) return KFBI_EINVAL;
+  if (info) std::memset(info, 0, sizeof(*info));
+  const size_t need = noalloc_bytes(C);
+  if (need > (size_t)KFBI_NOALLOC_MAX_BYTES) {
+    C->err = "kfbi_eval_noalloc: this context needs " + std::to_string(need) + " bytes of scratch, more than " +
+             "KFBI_NOALLOC_MAX_BYTES = " + std::to_string((size_t)KFBI_NOALLOC_MAX_BYTES);
+    return KFBI_EINVAL;
+  }
+  return guarded(C, [&] {
+    char* base = static_cast<char*>(scratch_address(C->dev));
+    if (!base) throw DevErr{"no device address of the no-alloc scratch"};
+    Arena a{base, (size_t)KFBI_NOALLOC_MAX_BYTES, 0};
+    const WorkSet own = get_work(C);
+    set_work(C, carve_work(C, a));
+    struct Restore {
+      kfbi_ctx* C;
+      const WorkSet& w;
+      ~Restore() { set_work(C, w); }
+    } restore{C, own};
     check_finite(C, phi, 3 * C->S.n);
     eval_impl(C, phi, out, false, info);
     finish_input_check(C);
