@@ -24,6 +24,8 @@ import numpy as np
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
+import kfbi_inputs as KI  # noqa: E402  (problem data only; no device work)
+
 METRIC = "BIE operator evals/s at 256^3 (mixed vs FP64, rel err ≤1e-6) + HBM GB/s"
 HBM_PEAK = 8000.0  # GB/s, MI355X
 DCT2, DST2, DCT3, DST3, DST1 = 0, 1, 2, 3, 4
@@ -33,26 +35,68 @@ KIND_NAMES = {DCT2: "k_pass DCT2", DST2: "k_pass DST2", DCT3: "k_pass DCT3", DST
               K_YFWD: "k_ypair_fwd", K_YINV: "k_ypair_inv"}
 
 
-def cpu_baseline(cfg, n_cg):
-    """The oracle as it stands, on the host cores, on a bounded sample: Schur-complement
-    applications (each three sine-transform Poisson solves plus the MAC gradient and
-    divergence) at the full 256^3 size, as many as fit in about 10 s (2 to 40); one K phi
-    costs about (n_cg + 2) of them (right-hand side and velocity back-substitution add the
-    equivalent of two), the surface stages are below 1%."""
-    from oracle.mac import MAC
-    workers = os.cpu_count()
-    mac = MAC(cfg.N, cfg.lo, cfg.hi, cfg.pde, cfg.mu, cfg.lam, workers=workers)
-    p = np.random.default_rng(0).standard_normal((cfg.N,) * 3)
+def _host_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _schur_seconds(mac, N, budget_s):
+    """Mean seconds of one oracle Schur-complement application (three sine-transform Poisson
+    solves plus the MAC gradient and divergence), over as many as fit in budget_s (2 to 40)."""
+    p = np.random.default_rng(0).standard_normal((N,) * 3)
     t0 = time.perf_counter()
-    mac.schur(p)  # warm-up, also sizes the sample to about 10 s of host work
-    reps = int(min(40, max(2, 10.0 / max(time.perf_counter() - t0, 1e-3))))
+    mac.schur(p)  # warm-up, also sizes the sample
+    reps = int(min(40, max(2, budget_s / max(time.perf_counter() - t0, 1e-3))))
     t0 = time.perf_counter()
     for _ in range(reps):
         mac.schur(p)
-    t = (time.perf_counter() - t0) / reps
-    return {"value": 1.0 / (t * (n_cg + 2)), "unit": "evals/s", "cores": workers, "kind": "oracle",
-            "sample": f"{reps} oracle Schur-complement applications at {cfg.N}^3 ({t:.2f} s each, scipy.fft "
-                      f"workers={workers}), scaled by the oracle's CG count + 2 = {n_cg + 2}"}
+    return (time.perf_counter() - t0) / reps, reps
+
+
+def cpu_baseline(cfg, n_cg, calib_N=128):
+    """The oracle as it stands, on the host cores, on a bounded sample of the workload.
+
+    At the full size one K phi costs about (n_cg + 2) Schur-complement applications (the
+    right-hand side and the velocity back-substitution add the equivalent of two); those are
+    timed on a sample of about 10 s.  The remaining work of a complete evaluation (surface
+    stages, sparse corrections and interpolation, Python overhead) is calibrated on the same
+    workload at calib_N^3: complete oracle evaluations (median of 3 after a warm-up, setup not
+    timed) against the same extrapolation at that size; the ratio is applied at full size."""
+    from oracle.kfbi import Oracle
+    from oracle.mac import MAC
+    workers = os.cpu_count()
+    c = cfg.with_N(calib_N)
+    O = Oracle(c, workers=workers, form="average")
+    X = O.points
+    phi = KI.exact_u(c.solution, X[:, 0], X[:, 1], X[:, 2])
+    O.eval(phi)
+    full = []
+    for _ in range(3):
+        t0 = time.perf_counter()
+        O.eval(phi)
+        full.append(time.perf_counter() - t0)
+    t_full = float(np.median(full))
+    n_cg_c = O.last_cg_iters
+    ts_c, _ = _schur_seconds(O.mac, calib_N, 3.0)
+    factor = t_full / ((n_cg_c + 2) * ts_c)
+    del O
+    mac = MAC(cfg.N, cfg.lo, cfg.hi, cfg.pde, cfg.mu, cfg.lam, workers=workers)
+    t, reps = _schur_seconds(mac, cfg.N, 10.0)
+    extrap = t * (n_cg + 2)
+    return {"value": 1.0 / (extrap * factor), "unit": "evals/s", "cores": workers, "kind": "oracle",
+            "host": _host_model(),
+            "sample": f"{reps} oracle Schur-complement applications at {cfg.N}^3 ({t:.3f} s each, scipy.fft "
+                      f"workers={workers}) x (oracle CG count {n_cg} + 2) = {extrap:.2f} s, times the "
+                      f"calibration factor {factor:.2f} = complete oracle K phi at {calib_N}^3 (median of 3: "
+                      f"{t_full:.2f} s) / the same extrapolation at {calib_N}^3",
+            "extrapolated_value": 1.0 / extrap, "calibration": {"N": calib_N, "full_eval_s": t_full,
+                                                                "extrapolated_s": (n_cg_c + 2) * ts_c,
+                                                                "factor": factor}}
 
 
 def errs(out, ref):
@@ -196,7 +240,6 @@ def main():
               "described with the method); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
-    import kfbi_inputs as KI
     import paper_2303_04992_amd as K
 
     if args.all_configs:

@@ -22,7 +22,9 @@ def test_more_than_one_gpu_is_refused():
 
 def test_cpu_baseline_fields():
     import bench
-    cb = bench.cpu_baseline(KI.WORKLOADS["sphere32"], 20)
+    cb = bench.cpu_baseline(KI.WORKLOADS["sphere32"].with_N(16), 20, calib_N=16)
     assert cb["kind"] == "oracle" and cb["unit"] == "evals/s"
     assert cb["value"] > 0 and cb["cores"] >= 1
     assert "Schur-complement applications" in cb["sample"]
+    c = cb["calibration"]
+    assert c["factor"] > 0 and abs(cb["value"] * c["factor"] - cb["extrapolated_value"]) < 1e-9 * cb["extrapolated_value"]
