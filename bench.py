@@ -156,6 +156,32 @@ def run_form(K, KI, cfg, prec, rtol, inner, steps, warmup, refs, prof=None, trac
     return res
 
 
+def run_batch(K, KI, cfg, rtol, inner, nrhs, steps, refs):
+    """kfbi_eval_batch: nrhs densities (u_exact and random ones) per call, mixed form; time per
+    call and per right-hand side, and the errors of the u_exact right-hand side."""
+    import torch
+    op = K.Operator(cfg, K.MIXED_FP32, cg_rtol=rtol, inner_rtol=inner)
+    xyz, _ = op.points()
+    ue = KI.exact_u(cfg.solution, xyz[:, 0], xyz[:, 1], xyz[:, 2])
+    phis = torch.as_tensor(np.stack([ue] + [KI.random_density(op.n, seed=10 + i) for i in range(nrhs - 1)]),
+                           device="cuda")
+    out = op.eval_batch(phis)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = op.eval_batch(phis)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / steps
+    info = op.last_info
+    res = {"nrhs": nrhs, "ms_per_call": dt * 1e3, "ms_per_rhs": dt * 1e3 / nrhs, "evals_per_s": nrhs / dt,
+           "cg_iters_sum": info["cg_iters"], "model_bytes": info["model_bytes"],
+           "gb_s": info["model_bytes"] / (info["ms_total"] * 1e-3) / 1e9,
+           "err_uexact_rhs0": errs(out[0], refs.get("uexact")) if refs else None}
+    del op, phis, out
+    torch.cuda.empty_cache()
+    return res
+
+
 def copy_bandwidth(nbytes=1 << 30, reps=10):
     """Read+write bandwidth (GB/s) of a plain device-to-device copy of nbytes (larger than the
     256 MB last-level cache), timed with events on torch's current stream, where the copy runs."""
@@ -302,6 +328,10 @@ def main():
     if f64e is None:
         f64e = f64
 
+    say("[bench] batch of 4 right-hand sides (kfbi_eval_batch)")
+    bat = run_batch(K, KI, cfg, args.refine_rtol, args.inner_rtol, 4, max(3, args.steps // 4), refs["average"])
+    say(f"[bench] batch: {bat}")
+
     pr = mx["prof"]
     achieved = pr["bytes"] / (pr["avg_ms"] * 1e-3) / 1e9
     copy_gbs = copy_bandwidth()
@@ -347,6 +377,7 @@ def main():
                                          "cg_rtol")},
         "fp64_equal_accuracy": {k: f64e.get(k) for k in ("evals_per_s", "ms_per_eval", "err_uexact", "err_random",
                                                           "cg_iters", "cg_rtol")},
+        "batch": bat,
         "speedup_mixed_over_fp64": mx["evals_per_s"] / f64["evals_per_s"],
         "speedup_mixed_over_fp64_equal_accuracy": mx["evals_per_s"] / f64e["evals_per_s"],
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK, "unit": "GB/s",

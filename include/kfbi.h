@@ -151,6 +151,20 @@ kfbi_status kfbi_eval(kfbi_ctx* ctx, const double* phi_dev, double* out_dev, kfb
 #define KFBI_NOALLOC_MAX_BYTES (64ull << 20)
 kfbi_status kfbi_eval_noalloc(kfbi_ctx* ctx, const double* phi_dev, double* out_dev, kfbi_info* info);
 
+/* K phi for several densities in one call (Sec. 3: the second-kind equation is linear, so the
+ * densities of several boundary data, finite-difference directions or Krylov blocks can be
+ * evaluated together): out[r] = K phi[r] for r < nrhs (1 <= nrhs <= KFBI_BATCH_MAX),
+ * phi_dev and out_dev [nrhs][n][3] float64 device arrays.  The right-hand sides run in lockstep:
+ * every kernel serves all of them (the surface fit weights and jump maps are read once per
+ * group of four), their Schur CG and refinement scalars come back to the host in one copy per
+ * iteration, and each right-hand side stops by the same rule as its own kfbi_eval, so the
+ * results equal those of nrhs calls to rounding.  The context keeps nrhs work arenas (each the
+ * size of one evaluation's work buffers) for later batches; ENOMEM if they cannot be
+ * allocated.  info: CG iterations summed over the right-hand sides, the largest refinement
+ * count, the call's device time and model bytes. */
+#define KFBI_BATCH_MAX 64
+kfbi_status kfbi_eval_batch(kfbi_ctx* ctx, int32_t nrhs, const double* phi_dev, double* out_dev, kfbi_info* info);
+
 /* Transpose of kfbi_eval (in the context's trace form): out = K^T w (same shapes). */
 kfbi_status kfbi_eval_adjoint(kfbi_ctx* ctx, const double* w_dev, double* out_dev, kfbi_info* info);
 

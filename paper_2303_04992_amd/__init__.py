@@ -82,6 +82,7 @@ _sig = {
     "kfbi_eval": (C.c_int, [_P, _P, _P, C.POINTER(Info)]),
     "kfbi_eval_adjoint": (C.c_int, [_P, _P, _P, C.POINTER(Info)]),
     "kfbi_eval_noalloc": (C.c_int, [_P, _P, _P, C.POINTER(Info)]),
+    "kfbi_eval_batch": (C.c_int, [_P, C.c_int32, _P, _P, C.POINTER(Info)]),
     "kfbi_solve_bvp": (C.c_int, [_P, _P, VecFn, _P, _P, _P, _P, C.POINTER(Info)]),
     "kfbi_interface_solve": (C.c_int, [_P, _P, C.c_int32, _P, _P, C.POINTER(Info)]),
     "kfbi_set_probes": (C.c_int, [_P, _P, C.c_int64]),
@@ -215,6 +216,18 @@ class Operator:
         out = torch.empty_like(phi)
         info = Info()
         self._check(_lib.kfbi_eval(self._h, _ptr(phi), _ptr(out), C.byref(info)))
+        self.last_info = info.as_dict()
+        return out
+
+    def eval_batch(self, phis):
+        """K phi[r] for a stack of densities (nrhs, n, 3) in one call (kfbi_eval_batch)."""
+        torch = _torch()
+        phis = torch.as_tensor(phis, dtype=torch.float64, device=self.device)
+        nrhs = phis.shape[0] if phis.dim() == 3 else 1
+        phis = phis.reshape(nrhs, self.n, 3).contiguous()
+        out = torch.empty_like(phis)
+        info = Info()
+        self._check(_lib.kfbi_eval_batch(self._h, int(nrhs), _ptr(phis), _ptr(out), C.byref(info)))
         self.last_info = info.as_dict()
         return out
 

@@ -175,9 +175,22 @@ struct MacSolver {
   size_t prof_used = 0;
   int64_t prof_launches = 0;
   double prof_ms = 0;
-  // algorithmic HBM bytes of the launches issued (one read or write per N^3 field touched)
+  // algorithmic HBM bytes of the launches issued (one read or write per N^3 field touched, for
+  // each right-hand side the launch serves)
   double bytes = 0;
-  void count(double fields) { bytes += fields * (double)M * sizeof(T); }
+  int nact = 1;
+  void count(double fields) { bytes += fields * (double)M * sizeof(T) * nact; }
+  // Batches (several right-hand sides in lockstep, see Bat): bt describes the call's batch;
+  // act_live flags the right-hand sides a solve serves, act_cg those whose CG still iterates;
+  // cur is the descriptor the launches use (live or CG flags), nact its active count.
+  Bat bt, cur;
+  int* act_live = nullptr;
+  int* act_cg = nullptr;
+  int rr_cap = 1;  // right-hand sides host_rr has room for
+  template <class Q>
+  Q* at(Q* p, int r) const {
+    return p ? reinterpret_cast<Q*>(reinterpret_cast<uintptr_t>(p) + (uint64_t)r * (uint64_t)bt.A) : p;
+  }
 
   void init(int N_, double h, int pde_, double mu_, double c_, hipStream_t s_, std::vector<void*>& owned) {
     N = N_;
@@ -289,7 +302,7 @@ struct MacSolver {
   void pass(int kind, int axis, const T* in, T* out, bool acc = false) {
     count(acc ? 3 : 2);
     timed(kind == prof_kind && (prof_axis < 0 || axis == prof_axis) && !acc,
-          [&] { return launch_pass<T>(N, kind, axis, in, out, acc, tb, s); });
+          [&] { return launch_pass<T>(N, kind, axis, in, out, acc, tb, s, cur); });
   }
   // algorithmic HBM bytes of one launch of kernel id (one read and one write per field touched)
   double kernel_bytes(int id) const {
@@ -316,9 +329,9 @@ struct MacSolver {
   // v -= mean v; the sum of v is left in scal[keep] when keep >= 0
   void project_mean(T* v, int keep = -1) {
     count(3);
-    HIPCHK(launch_sum_partials<T>(M, v, partials, nparts_u, s));
-    HIPCHK(launch_reduce(partials, nparts_u, 1, scal, R_SUM, 1, M, s, keep >= 0 ? scal + keep : nullptr));
-    HIPCHK(launch_add_scalar<T>(M, v, scal, keep >= 0 ? keep : 5, -1.0 / (double)M, s));
+    HIPCHK(launch_sum_partials<T>(M, v, partials, nparts_u, s, cur));
+    HIPCHK(launch_reduce(partials, nparts_u, 1, scal, R_SUM, 1, M, s, keep >= 0 ? scal + keep : nullptr, cur));
+    HIPCHK(launch_add_scalar<T>(M, v, scal, keep >= 0 ? keep : 5, -1.0 / (double)M, s, cur));
   }
 
   // S p for the CG direction d (q = S d); the updates of x, r (previous iteration) and of
@@ -328,20 +341,20 @@ struct MacSolver {
   void zfwd(int mode = ZF_FUSED) {
     count(mode == ZF_FUSED ? 9 : mode == ZF_FIRST ? 4 : 3);
     timed(prof_kind == KFBI_K_ZFWD && mode == ZF_FUSED,
-          [&] { return launch_zfwd_cg<T>(N, mode, x, r, d, q, A, B, scal, rpart, tb, s); });
+          [&] { return launch_zfwd_cg<T>(N, mode, x, r, d, q, A, B, scal, rpart, tb, s, cur); });
   }
   void yfwd() {
     count(3);
-    timed(prof_kind == KFBI_K_YFWD, [&] { return launch_ypair<T>(N, false, A, A, A1, B2, tb, s); }); }
+    timed(prof_kind == KFBI_K_YFWD, [&] { return launch_ypair<T>(N, false, A, A, A1, B2, tb, s, cur); }); }
   void xmid() {
     count(6);
-    timed(prof_kind == KFBI_K_XMID, [&] { return launch_xmid<T>(N, A1, B2, B3, mu, tb, s); }); }
+    timed(prof_kind == KFBI_K_XMID, [&] { return launch_xmid<T>(N, A1, B2, B3, mu, tb, s, cur); }); }
   void yinv() {
     count(3);
-    timed(prof_kind == KFBI_K_YINV, [&] { return launch_ypair<T>(N, true, A1, B2, A, A, tb, s); }); }
+    timed(prof_kind == KFBI_K_YINV, [&] { return launch_ypair<T>(N, true, A1, B2, A, A, tb, s, cur); }); }
   void zinv() {
     count(4);
-    timed(prof_kind == KFBI_K_ZINV, [&] { return launch_zinv_cg<T>(N, A, B, q, d, c, partials, tb, s); });
+    timed(prof_kind == KFBI_K_ZINV, [&] { return launch_zinv_cg<T>(N, A, B, q, d, c, partials, tb, s, cur); });
   }
   void cg_iteration(bool first) {
     zfwd(first ? ZF_FIRST : ZF_FUSED);  // x, r of the last step; d = r + beta d; A = DST_z d; B = DCT_z d
@@ -356,13 +369,50 @@ struct MacSolver {
     yinv();                               // A = DST_y^T A1 + DCT_y^T B2 (components 0 and 1 share DST_z)
     pass(DST3, 1, B3, B);
     zinv();                // q = DST_z^T A + DCT_z^T B + c d, partial dots
-    HIPCHK(launch_cg_coef(rpart, nparts_z, partials, nparts_x, scal, 1, M, s));  // mean-zero iterates
+    HIPCHK(launch_cg_coef(rpart, nparts_z, partials, nparts_x, scal, 1, M, s, cur));  // mean-zero iterates
   }
 
   // Solve A_u u + G p = F_u, D u + c p = F_p (Stokes: D u = F_p - mean F_p, mean p = 0).
   // Fu: 3 fields (internal layout, face 0 ignored), Fp: 1 field.  Returns CG iterations or
   // -1 if maxit was reached.
-  int solve(const T* Fu, const T* Fp, T* u, T* p, double rtol, int maxit) {
+  // Batch set-up: right-hand sides r with live[r] != 0 take part (null: all); the flags go to
+  // the device before the solve's first launch (pageable source: copied at the call).
+  void set_live(const std::vector<char>* live, int& nlive) {
+    nlive = bt.nb;
+    if (bt.nb == 1) {
+      cur = bt;
+      nact = 1;
+      return;
+    }
+    std::vector<int> f(bt.nb, 1);
+    if (live) {
+      nlive = 0;
+      for (int r = 0; r < bt.nb; ++r) nlive += (f[r] = (*live)[r] ? 1 : 0);
+    }
+    HIPCHK(hipMemcpyAsync(act_live, f.data(), bt.nb * sizeof(int), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(act_cg, f.data(), bt.nb * sizeof(int), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));  // the pageable source is read before f goes out of scope
+  }
+  Bat with_act(const int* act) const {
+    Bat b = bt;
+    b.act = bt.nb > 1 ? act : nullptr;
+    return b;
+  }
+
+  // Solve A_u u + G p = F_u, D u + c p = F_p (Stokes: D u = F_p - mean F_p, mean p = 0).
+  // Fu: 3 fields (internal layout, face 0 ignored), Fp: 1 field.  Returns the CG iterations
+  // (the largest over a batch) or -1 if maxit was reached.  Batches (bt.nb > 1) solve every
+  // live right-hand side in lockstep; each stops by the same rule, at the same iteration, as
+  // its own solve would (its flag in act_cg then skips it), and its iteration count goes to
+  // its[r].
+  int solve(const T* Fu, const T* Fp, T* u, T* p, double rtol, int maxit, const std::vector<char>* live = nullptr,
+            std::vector<int>* its = nullptr) {
+    const int NB = bt.nb;
+    int nlive = 1;
+    set_live(live, nlive);
+    auto is_live = [&](int r) { return !live || (*live)[r]; };
+    cur = with_act(act_live);
+    nact = nlive;
     // 1.-2. b = P(F_p - sum_m C_m^T [sigma/Lambda_m] T_m F_m).  Per component: T_m along z and
     // y, then the fused x pass keeps Fh[m] = T_m F_m and leaves C_m,x^T of the weighted
     // spectrum; the y and z inverses of the three components are shared as in the matvec.
@@ -371,12 +421,12 @@ struct MacSolver {
     for (int m = 0; m < 3; ++m) {
       pass(m == 2 ? DST1 : DST2, 2, Fu + m * M, Fh[m]);
       pass(m == 1 ? DST1 : DST2, 1, Fh[m], Fh[m]);
-      HIPCHK(launch_xfuse<T>(N, m, false, Fh[m], Fh[m], H[m], mu, tb, s));
+      HIPCHK(launch_xfuse<T>(N, m, false, Fh[m], Fh[m], H[m], mu, tb, s, cur));
       count(3);
     }
-    HIPCHK(launch_ypair<T>(N, true, A1, B2, A, A, tb, s));       // A = DST_y^T H0 + DCT_y^T H1
-    pass(DST3, 1, B3, B);                                        // B = DST_y^T H2
-    HIPCHK(launch_zinv_cg<T>(N, A, B, b, Fp, 1.0, partials, tb, s));  // b = DST_z^T A + DCT_z^T B + F_p
+    HIPCHK(launch_ypair<T>(N, true, A1, B2, A, A, tb, s, cur));       // A = DST_y^T H0 + DCT_y^T H1
+    pass(DST3, 1, B3, B);                                             // B = DST_y^T H2
+    HIPCHK(launch_zinv_cg<T>(N, A, B, b, Fp, 1.0, partials, tb, s, cur));  // b = DST_z^T A + DCT_z^T B + F_p
     count(3 + 4);
     // Both PDEs iterate on mean-zero pressures.  S = S_0 + cI with S_0 1 = 0 (G annihilates
     // constants, sigma_0 = 0) and S_0 symmetric, so the mean of S p is c mean(p): for Navier
@@ -391,79 +441,117 @@ struct MacSolver {
     // first check (no synchronisation before the first iterations are queued; b = 0 converges
     // at that check with x = 0).
     mark(ST_CG);
-    HIPCHK(launch_fill<T>(M, x, T(0), s));
+    HIPCHK(launch_fill<T>(M, x, T(0), s, cur));
     count(1);
     std::swap(r, b);
     // Stop test.  Iteration k leaves in scal[7] the r_k.r_k that its forward z pass summed over
     // the updated residual r_k, and in scal[0] the recurrence estimate of |r_{k+1}|^2 (used
     // for beta only: it assumes the conjugacy of d_k and d_{k-1}).  With one iteration of
-    // look-ahead, iteration k+1 is queued before the values of k are read.  The solve has
+    // look-ahead, iteration k+1 is queued before the values of k are read.  A solve has
     // converged when the summed r_k.r_k is below the threshold, or when the estimate of
     // |r_{k+1}|^2 is and the r_{k+1}.r_{k+1} that the queued iteration k+1 sums confirms it
-    // (a non-positive or drifted estimate alone never stops the solve).
-    auto slot = [&](int i) { return host_rr + 8 * (i & 1); };
-    double bb = 0.0;
-    int it = 0;
-    bool conv = false;
+    // (a non-positive or drifted estimate alone never stops the solve).  Its pending
+    // x += alpha d (alpha of the queued iteration) is issued right then.
+    // host_rr: two look-ahead slots, each 8 scalars per right-hand side
+    auto slot = [&](int i, int rhs) { return host_rr + 8 * ((i & 1) * NB + rhs); };
+    std::vector<double> bb(NB, 0.0);
+    std::vector<char> done(NB, 0);
+    int it = 0, ndone = 0;
+    for (int rr = 0; rr < NB; ++rr)
+      if (!is_live(rr)) done[rr] = 1, ++ndone;
+    cur = with_act(act_cg);
     auto nan_check = [&](double v) {
       if (std::isnan(v)) throw DevErr{"NaN in the Schur CG residual"};
     };
-    while (!conv && it < maxit) {
+    auto finish = [&](int rr) {  // right-hand side rr has converged: its pending update, and out
+      done[rr] = 1;
+      ++ndone;
+      --nact;
+      if (its) (*its)[rr] = it;
+      Bat one = bt;
+      one.nb = 1;
+      one.act = nullptr;
+      HIPCHK(launch_axpy_scal<T>(M, at(x, rr), at(d, rr), at(scal, rr), 1, s, one));  // x += alpha d
+      bytes += 3.0 * M * sizeof(T);
+      if (NB > 1) HIPCHK(launch_fill<int>(1, act_cg + rr, 0, s));
+    };
+    auto copy_slots = [&](int i) {
+      HIPCHK(hipMemcpy2DAsync(slot(i, 0), 8 * sizeof(double), scal, NB > 1 ? (size_t)bt.A : 8 * sizeof(double),
+                              8 * sizeof(double), NB, hipMemcpyDeviceToHost, s));
+    };
+    while (ndone < NB && it < maxit) {
       cg_iteration(it == 0);
-      HIPCHK(hipMemcpyAsync(slot(it), scal, 8 * sizeof(double), hipMemcpyDeviceToHost, s));
+      copy_slots(it);
       HIPCHK(hipEventRecord(ev[it & 1], s));
       ++it;
       if (it >= 2) {
         const int k = it - 2;
         HIPCHK(hipEventSynchronize(ev[k & 1]));
-        if (k == 0) bb = slot(0)[7];
-        const double thr = rtol * rtol * bb, est = slot(k)[0], tru = slot(k)[7];
-        nan_check(est);
-        nan_check(tru);
-        if (!(tru > thr)) {
-          conv = true;
-        } else if (!(est > thr)) {
-          HIPCHK(hipEventSynchronize(ev[(k + 1) & 1]));
-          nan_check(slot(k + 1)[7]);
-          if (!(slot(k + 1)[7] > thr)) conv = true;
+        std::vector<int> confirm, conv_now;
+        for (int rr = 0; rr < NB; ++rr) {
+          if (done[rr]) continue;
+          if (k == 0) bb[rr] = slot(0, rr)[7];
+          const double thr = rtol * rtol * bb[rr], est = slot(k, rr)[0], tru = slot(k, rr)[7];
+          nan_check(est);
+          nan_check(tru);
+          if (!(tru > thr))
+            conv_now.push_back(rr);
+          else if (!(est > thr))
+            confirm.push_back(rr);
         }
+        if (!confirm.empty()) {
+          HIPCHK(hipEventSynchronize(ev[(k + 1) & 1]));
+          for (int rr : confirm) {
+            nan_check(slot(k + 1, rr)[7]);
+            if (!(slot(k + 1, rr)[7] > rtol * rtol * bb[rr])) conv_now.push_back(rr);
+          }
+        }
+        for (int rr : conv_now) finish(rr);
       }
     }
-    if (it > 0) {
-      HIPCHK(launch_axpy_scal<T>(M, x, d, scal, 1, s));  // the pending x += alpha d
-      count(3);
-    }
+    bool conv = ndone == NB;
     if (!conv && it > 0) {  // maxit reached: the last iteration's summed residual decides
       HIPCHK(hipEventSynchronize(ev[(it - 1) & 1]));
-      if (it == 1) bb = slot(0)[7];
-      nan_check(slot(it - 1)[7]);
-      if (!(slot(it - 1)[7] > rtol * rtol * bb)) conv = true;
+      conv = true;
+      for (int rr = 0; rr < NB; ++rr) {
+        if (done[rr]) continue;
+        if (it == 1) bb[rr] = slot(0, rr)[7];
+        nan_check(slot(it - 1, rr)[7]);
+        const bool ok = !(slot(it - 1, rr)[7] > rtol * rtol * bb[rr]);
+        finish(rr);
+        conv = conv && ok;
+      }
     }
+    cur = with_act(act_live);
+    nact = nlive;
     project_mean(x);
     if (c > 0) {
-      HIPCHK(launch_add_scalar<T>(M, x, scal, 9, 1.0 / ((double)M * c), s));  // + mean(b) / c
+      HIPCHK(launch_add_scalar<T>(M, x, scal, 9, 1.0 / ((double)M * c), s, cur));  // + mean(b) / c
       count(2);
     }
     // 4. velocity back-substitution u_m = T_m^T [(T_m F_m + sigma C_m p) / Lambda_m]: C_m p along
     // z and y shared as in the matvec, then per component the fused x pass and the y, z inverses
     // A = DST_z p, B = DCT_z p
     mark(ST_BACKSUB);
-    HIPCHK(launch_zfwd_cg<T>(N, ZF_PLAIN, nullptr, x, nullptr, nullptr, A, B, nullptr, nullptr, tb, s));
+    HIPCHK(launch_zfwd_cg<T>(N, ZF_PLAIN, nullptr, x, nullptr, nullptr, A, B, nullptr, nullptr, tb, s, cur));
     if (sizeof(T) == 4) pass(DST2, 1, B, B3);                         // C_2 along y (order as in the matvec)
-    HIPCHK(launch_ypair<T>(N, false, A, A, A1, B2, tb, s));          // C_0, C_1 along y
+    HIPCHK(launch_ypair<T>(N, false, A, A, A1, B2, tb, s, cur));     // C_0, C_1 along y
     count(3 + 3);
     if (sizeof(T) != 4) pass(DST2, 1, B, B3);
     for (int m = 0; m < 3; ++m) {
       T* um = u + m * M;
-      HIPCHK(launch_xfuse<T>(N, m, true, H[m], Fh[m], um, mu, tb, s));
+      HIPCHK(launch_xfuse<T>(N, m, true, H[m], Fh[m], um, mu, tb, s, cur));
       count(3);
       pass(m == 1 ? DST1 : DST3, 1, um, um);
       pass(m == 2 ? DST1 : DST3, 2, um, um);
     }
     if (p) {
-      HIPCHK(hipMemcpyAsync(p, x, M * sizeof(T), hipMemcpyDeviceToDevice, s));
+      for (int rr = 0; rr < NB; ++rr)
+        if (is_live(rr)) HIPCHK(hipMemcpyAsync(at(p, rr), at(x, rr), M * sizeof(T), hipMemcpyDeviceToDevice, s));
       count(2);
     }
+    cur = bt;
+    nact = 1;
     if (prof_used) {
       HIPCHK(hipStreamSynchronize(s));
       prof_collect();
@@ -541,9 +629,18 @@ struct kfbi_ctx {
   double* hpin = nullptr;
   int* hflag = nullptr;
   StageClock clock;
+  // batched evaluations (kfbi_eval_batch): the current batch of the context-level launches, the
+  // per-right-hand-side work arenas (bat_A bytes each) and their flags
+  Bat bt;
+  char* bat_base = nullptr;
+  int64_t bat_A = 0;
+  int bat_cap = 0, bat_clean = 0;
+  int* bat_act = nullptr;  // 3 x bat_cap flags: the solver's live and CG flags, the refinement's
+  double* hpin_bat = nullptr;  // pinned: |F| and |r| of each right-hand side (2 x bat_cap)
   ~kfbi_ctx() {
     if (hpin) (void)hipHostFree(hpin);
     if (hflag) (void)hipHostFree(hflag);
+    if (hpin_bat) (void)hipHostFree(hpin_bat);
     clock.release();
     s64.release();
     s32.release();
@@ -766,15 +863,17 @@ void assemble_rhs(kfbi_ctx* C, const double* phi, bool vol) {
   hipStream_t s = C->s;
   const bool force = vol && C->has_force;
   const double* Fj = force ? C->Fj : nullptr;
+  const Bat& bt = C->bt;
+  const double nb = bt.nb;
   C->clock.mark(ST_JUMPS, s);
   HIPCHK(launch_fit_jump(S.T, C->nb_ptr, C->nb_idx, C->fitw, C->jmap, C->jfmap, Fj, phi, C->cp_of, C->jumps,
-                         C->fitvals, s));
-  HIPCHK(launch_interp_jump(S.n, C->cp_target, C->fitvals, C->emap, C->efmap, Fj, C->ejump, s));
+                         C->fitvals, s, bt));
+  HIPCHK(launch_interp_jump(S.n, C->cp_target, C->fitvals, C->emap, C->efmap, Fj, C->ejump, s, bt));
   C->clock.mark(ST_CORRECT, s);
-  C->bytes_extra += C->bytes_jumps + C->bytes_correct;
+  C->bytes_extra += C->bytes_jumps * nb + C->bytes_correct * nb;
   if (!C->f_clean) {
-    HIPCHK(launch_fill<double>(4 * S.M, C->F, 0.0, s));
-    C->bytes_extra += 32.0 * (double)S.M;
+    HIPCHK(launch_fill<double>(4 * S.M, C->F, 0.0, s, bt));
+    C->bytes_extra += 32.0 * (double)S.M * nb;
   }
   const bool sparse = !(force && C->nvol);
   const int64_t nirr = (int64_t)S.irr_node.size();
@@ -782,15 +881,16 @@ void assemble_rhs(kfbi_ctx* C, const double* phi, bool vol) {
     // F is the corrections alone: the float32 right-hand side of the first refinement round
     // and its norm partials come from the correction pass (no dense pass over F)
     if (!C->r32_clean) {
-      HIPCHK(launch_fill<float>(4 * S.M, C->r32, 0.0f, s));
-      C->bytes_extra += 16.0 * (double)S.M;
+      HIPCHK(launch_fill<float>(4 * S.M, C->r32, 0.0f, s, bt));
+      C->bytes_extra += 16.0 * (double)S.M * nb;
     }
     HIPCHK(launch_correct(nirr, C->irr_node, C->irr_ptr, C->arm_t, C->arm_o, C->arm_a, C->jumps, C->F, s, C->r32,
-                          S.M, C->rpart, kRefineParts));
+                          S.M, C->rpart, kRefineParts, bt));
     C->r32_clean = true;
     C->r32_ready = true;
   } else {
-    HIPCHK(launch_correct(nirr, C->irr_node, C->irr_ptr, C->arm_t, C->arm_o, C->arm_a, C->jumps, C->F, s));
+    HIPCHK(launch_correct(nirr, C->irr_node, C->irr_ptr, C->arm_t, C->arm_o, C->arm_a, C->jumps, C->F, s, nullptr, 0,
+                          nullptr, 0, bt));
     C->r32_ready = false;
   }
   C->f_clean = true;
@@ -806,11 +906,19 @@ int mac_solve(kfbi_ctx* C, const double* F, double* u, double* p, kfbi_info* inf
   const Setup& S = C->S;
   const int64_t M = S.M;
   hipStream_t s = C->s;
+  const Bat& bt = C->bt;
+  const int NB = bt.nb;
+  std::vector<int> its(NB, 0);
+  auto sum_its = [&] {
+    int t = 0;
+    for (int v : its) t += v;
+    return t;
+  };
   if (!C->mixed) {
-    int it = C->s64.solve(F, F + 3 * M, u, p, C->cfg.cg_rtol, C->cfg.cg_maxit);
+    int it = C->s64.solve(F, F + 3 * M, u, p, C->cfg.cg_rtol, C->cfg.cg_maxit, nullptr, &its);
     if (it < 0) throw std::runtime_error("ENOCONV: Schur CG reached cg_maxit");
     if (info) {
-      info->cg_iters += it;
+      info->cg_iters += NB == 1 ? it : sum_its();
       info->refine_rounds = 0;
     }
     return it;
@@ -818,60 +926,88 @@ int mac_solve(kfbi_ctx* C, const double* F, double* u, double* p, kfbi_info* inf
   // mixed: float32 inner solves inside float64 residual refinement of the full system.
   // Round k: x32 = (float32 MAC solve of r32); (u, p) += x32 and r32 = F - A(u, p), formed in
   // float64 in one fused pass; stop when |r| <= cg_rtol |F| (Stokes: pressure parts taken
-  // modulo constants, which the inner solve projects out).
+  // modulo constants, which the inner solve projects out).  In a batch every right-hand side
+  // leaves the rounds when its own residual meets the tolerance.
   const bool stokes = S.pde == KFBI_STOKES;
   const double c = stokes ? 0.0 : 1.0 / (S.lam + S.mu);
   const double Md = (double)M;
   constexpr int NP = kRefineParts;
-  // |F| is copied to pinned memory and read with the first residual norm: the first inner
-  // solve is queued without a synchronisation (F = 0 gives x32 = 0 and a zero residual)
+  Bat bref = bt;  // the refinement's launches: the right-hand sides still refining
+  if (NB > 1) bref.act = C->bat_act + 2 * C->bat_cap;
+  std::vector<char> live(NB, 1);
+  if (NB > 1) {
+    std::vector<int> ones(NB, 1);
+    HIPCHK(hipMemcpyAsync(const_cast<int*>(bref.act), ones.data(), NB * sizeof(int), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  // |F| and |r| of every right-hand side in pinned host memory (f0 read with the first residual)
+  double* hf0 = NB > 1 ? C->hpin_bat : C->hpin + 1;
+  double* hrn = NB > 1 ? C->hpin_bat + NB : C->hpin;
+  auto scal_to_host = [&](double* dst) {  // rscal[5] of every right-hand side
+    HIPCHK(hipMemcpy2DAsync(dst, sizeof(double), C->rscal + 5, NB > 1 ? (size_t)bt.A : sizeof(double), sizeof(double),
+                            NB, hipMemcpyDeviceToHost, s));
+  };
+  // the first inner solve is queued without a synchronisation (F = 0 gives x32 = 0 and a zero
+  // residual)
   if (!(C->r32_ready && C->f_clean && F == C->F)) {
-    HIPCHK(launch_refine_prep(M, F, C->r32, C->rpart, NP, s));
-    C->bytes_extra += 48.0 * Md;
+    HIPCHK(launch_refine_prep(M, F, C->r32, C->rpart, NP, s, bt));
+    C->bytes_extra += 48.0 * Md * NB;
     C->r32_clean = false;
   }
   C->r32_ready = false;
-  HIPCHK(launch_reduce(C->rpart, NP, 3, C->rscal, R_RESNORM0, stokes, M, s));
-  HIPCHK(hipMemcpyAsync(C->hpin + 1, C->rscal + 5, sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(launch_reduce(C->rpart, NP, 3, C->rscal, R_RESNORM0, stokes, M, s, nullptr, bt));
+  scal_to_host(hf0);
   const double* shift = stokes ? C->rscal + 6 : nullptr;  // mean of F_p (Stokes)
   // the iterate alternates between (u, p) and the spare float64 fields (neighbour values of
-  // the old iterate are read while the new one is written)
+  // the old iterate are read while the new one is written); in_ru[r]: where right-hand side r
+  // left its final iterate
   double* cu = u;
   double* cp = p;
-  int total = 0, rounds = 0;
-  double rn = 1.0, f0 = 0.0;
-  while (rounds == 0 || rn > C->cfg.cg_rtol * f0) {
+  std::vector<char> in_ru(NB, 0);
+  int total = 0, rounds = 0, nlive = NB;
+  while (nlive > 0) {
     if (rounds >= 30) throw std::runtime_error("ENOCONV: mixed refinement did not converge");
     const float* rin = (rounds == 0) ? C->r32 : C->r32b;
-    int it = C->s32.solve(rin, rin + 3 * M, C->x32, C->x32 + 3 * M, C->cfg.inner_rtol, C->cfg.cg_maxit);
+    std::fill(its.begin(), its.end(), 0);
+    int it = C->s32.solve(rin, rin + 3 * M, C->x32, C->x32 + 3 * M, C->cfg.inner_rtol, C->cfg.cg_maxit, &live, &its);
     if (it < 0) throw std::runtime_error("ENOCONV: inner float32 CG reached cg_maxit");
-    total += it;
+    total += NB == 1 ? it : sum_its();
     double* nu = (rounds == 0 || cu != u) ? u : C->ru;
     double* np = (rounds == 0 || cu != u) ? p : C->ru + 3 * M;
     C->clock.mark(ST_CG, s);
     HIPCHK(launch_refine_residual(rounds == 0, S.N, S.h, S.mu, c, cu, cp, C->x32, F, shift, nu, np, C->r32b, C->rpart,
-                                  NP, s));
-    C->bytes_extra += (rounds == 0 ? 96.0 : 128.0) * Md;
+                                  NP, s, bref));
+    C->bytes_extra += (rounds == 0 ? 96.0 : 128.0) * Md * nlive;
     cu = nu;
     cp = np;
-    HIPCHK(launch_reduce(C->rpart, NP, 3, C->rscal, R_RESNORM, stokes, M, s));
-    HIPCHK(hipMemcpyAsync(C->hpin, C->rscal + 5, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(launch_reduce(C->rpart, NP, 3, C->rscal, R_RESNORM, stokes, M, s, nullptr, bref));
+    scal_to_host(hrn);
     HIPCHK(hipStreamSynchronize(s));
-    rn = std::sqrt(std::max(C->hpin[0], 0.0));
-    f0 = std::sqrt(std::max(C->hpin[1], 0.0));
-    if (std::isnan(rn) || std::isnan(f0)) throw DevErr{"NaN in the refinement residual"};
     ++rounds;
+    for (int r = 0; r < NB; ++r) {
+      if (!live[r]) continue;
+      const double rn = std::sqrt(std::max(hrn[r], 0.0)), f0 = std::sqrt(std::max(hf0[r], 0.0));
+      if (std::isnan(rn) || std::isnan(f0)) throw DevErr{"NaN in the refinement residual"};
+      if (!(rn > C->cfg.cg_rtol * f0)) {
+        live[r] = 0;
+        --nlive;
+        in_ru[r] = nu != u;
+        if (NB > 1) HIPCHK(launch_fill<int>(1, const_cast<int*>(bref.act) + r, 0, s));
+      }
+    }
   }
-  if (cu != u) {
-    HIPCHK(hipMemcpyAsync(u, cu, 3 * M * sizeof(double), hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipMemcpyAsync(p, cp, M * sizeof(double), hipMemcpyDeviceToDevice, s));
-    C->bytes_extra += 64.0 * Md;
-  }
+  for (int r = 0; r < NB; ++r)
+    if (in_ru[r]) {
+      HIPCHK(hipMemcpyAsync(C->s32.at(u, r), C->s32.at(C->ru, r), 3 * M * sizeof(double), hipMemcpyDeviceToDevice, s));
+      HIPCHK(hipMemcpyAsync(C->s32.at(p, r), C->s32.at(C->ru + 3 * M, r), M * sizeof(double), hipMemcpyDeviceToDevice,
+                            s));
+      C->bytes_extra += 64.0 * Md;
+    }
   if (stokes) {
-    HIPCHK(launch_sum_partials<double>(M, p, C->rpart, NP, s));
-    HIPCHK(launch_reduce(C->rpart, NP, 1, C->rscal, R_SUM, 1, M, s));
-    HIPCHK(launch_add_scalar<double>(M, p, C->rscal, 5, -1.0 / (double)M, s));
-    C->bytes_extra += 24.0 * Md;
+    HIPCHK(launch_sum_partials<double>(M, p, C->rpart, NP, s, bt));
+    HIPCHK(launch_reduce(C->rpart, NP, 1, C->rscal, R_SUM, 1, M, s, nullptr, bt));
+    HIPCHK(launch_add_scalar<double>(M, p, C->rscal, 5, -1.0 / (double)M, s, bt));
+    C->bytes_extra += 24.0 * Md * NB;
   }
   if (info) {
     info->cg_iters += total;
@@ -894,10 +1030,10 @@ void eval_impl(kfbi_ctx* C, const double* phi, double* out, bool vol, kfbi_info*
   assemble_rhs(C, phi, vol);
   mac_solve(C, C->F, C->u, C->p, info);
   C->clock.mark(ST_INTERP, s);
-  HIPCHK(launch_interp(S.n, C->itp_idx, C->itp_w, C->u, C->ejump, out, s));
+  HIPCHK(launch_interp(S.n, C->itp_idx, C->itp_w, C->u, C->ejump, out, s, C->bt));
   if (C->cfg.trace == KFBI_TRACE_AVERAGE)
-    HIPCHK(launch_stab(S.n, C->sv_ptr, C->sv_idx, C->sv_w, C->stab_a, phi, out, s));
-  C->bytes_extra += C->bytes_interp;
+    HIPCHK(launch_stab(S.n, C->sv_ptr, C->sv_idx, C->sv_w, C->stab_a, phi, out, s, C->bt));
+  C->bytes_extra += C->bytes_interp * C->bt.nb;
   C->clock.mark(ST_END, s);
   HIPCHK(hipStreamSynchronize(s));
   C->clock.collect(info);
@@ -1049,6 +1185,41 @@ size_t noalloc_bytes(const kfbi_ctx* C) {
   Arena a;
   (void)carve_work(C, a);
   return a.used;
+}
+
+// Work arenas of a batch of nrhs right-hand sides (each carved like the context's own work
+// buffers, bat_A bytes apart), their flags and the pinned host slots of their scalars.
+void ensure_batch(kfbi_ctx* C, int nrhs) {
+  if (nrhs <= C->bat_cap) return;
+  const int64_t A = ((int64_t)noalloc_bytes(C) + 4095) / 4096 * 4096;
+  dfree(C->bat_base, C->owned);
+  dfree(C->bat_act, C->owned);
+  C->bat_base = nullptr;
+  C->bat_act = nullptr;
+  C->bat_cap = C->bat_clean = 0;
+  void* base = nullptr;
+  if (hipMalloc(&base, (size_t)A * nrhs) != hipSuccess) {
+    (void)hipGetLastError();
+    throw std::bad_alloc();
+  }
+  C->owned.push_back(base);
+  C->bat_base = static_cast<char*>(base);
+  C->bat_A = A;
+  C->bat_act = dalloc<int>(3 * nrhs, C->owned);
+  if (C->hpin_bat) (void)hipHostFree(C->hpin_bat);
+  C->hpin_bat = nullptr;
+  HIPCHK(hipHostMalloc((void**)&C->hpin_bat, 2 * nrhs * sizeof(double), hipHostMallocDefault));
+  auto grow_rr = [&](auto& sv) {
+    if (sv.host_rr) (void)hipHostFree(sv.host_rr);
+    sv.host_rr = nullptr;
+    HIPCHK(hipHostMalloc((void**)&sv.host_rr, 16 * nrhs * sizeof(double), hipHostMallocDefault));
+    sv.rr_cap = nrhs;
+  };
+  if (C->mixed)
+    grow_rr(C->s32);
+  else
+    grow_rr(C->s64);
+  C->bat_cap = nrhs;
 }
 
 // transpose of density -> probe values of the unified interface solve (the affine body-force
@@ -1274,6 +1445,47 @@ kfbi_status kfbi_eval_noalloc(kfbi_ctx* C, const double* phi, double* out, kfbi_
     check_finite(C, phi, 3 * C->S.n);
     eval_impl(C, phi, out, false, info);
     finish_input_check(C);
+  });
+}
+
+kfbi_status kfbi_eval_batch(kfbi_ctx* C, int32_t nrhs, const double* phi, double* out, kfbi_info* info) {
+  if (!C || !phi || !out || nrhs < 1 || nrhs > KFBI_BATCH_MAX) return KFBI_EINVAL;
+  if (info) std::memset(info, 0, sizeof(*info));
+  return guarded(C, [&] {
+    const int64_t n3 = 3 * C->S.n;
+    check_finite(C, phi, nrhs * n3);
+    ensure_batch(C, nrhs);
+    const bool clean = nrhs <= C->bat_clean;
+    const int clean_before = C->bat_clean;
+    C->bat_clean = 0;
+    const WorkSet own = get_work(C);
+    Arena a{C->bat_base, (size_t)C->bat_A, 0};
+    WorkSet w = carve_work(C, a);
+    w.f_clean = w.r32_clean = clean;
+    w.prof32 = own.prof32;
+    w.prof64 = own.prof64;
+    set_work(C, w);
+    const Bat bt{C->bat_A, n3, nullptr, nrhs};
+    auto attach = [&](auto& sv) {
+      sv.bt = sv.cur = bt;
+      sv.act_live = C->bat_act;
+      sv.act_cg = C->bat_act + C->bat_cap;
+    };
+    C->bt = bt;
+    attach(C->s32);
+    attach(C->s64);
+    struct Restore {
+      kfbi_ctx* C;
+      const WorkSet& w;
+      ~Restore() {
+        set_work(C, w);
+        C->bt = C->s32.bt = C->s32.cur = C->s64.bt = C->s64.cur = Bat();
+        C->s32.act_live = C->s32.act_cg = C->s64.act_live = C->s64.act_cg = nullptr;
+      }
+    } restore{C, own};
+    eval_impl(C, phi, out, false, info);
+    finish_input_check(C);
+    C->bat_clean = std::max(clean_before, (int)nrhs);
   });
 }
 

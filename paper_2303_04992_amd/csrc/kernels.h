@@ -10,6 +10,19 @@ namespace kfbi {
 template <typename T>
 struct SpecTab;  // device tables of one precision (defined in kernels.hip)
 
+// Several right-hand sides in one launch (lockstep batches): blockIdx.z is the right-hand side
+// r < nb; every work-buffer pointer a kernel receives is that of right-hand side 0, and the one
+// of right-hand side r lies r * A bytes further (each right-hand side owns one arena of A bytes,
+// carved identically); caller arrays of densities and results ([n][3] each) lie r * U doubles
+// apart; act[r] == 0 skips right-hand side r (act NULL: all run).  The default is one
+// right-hand side.
+struct Bat {
+  int64_t A = 0;
+  int64_t U = 0;
+  const int* act = nullptr;
+  int nb = 1;
+};
+
 // device tables for one precision and grid size
 template <typename T>
 struct DevTables {
@@ -29,10 +42,11 @@ enum WeightKind { W_SCHUR = 0, W_RHS = 1 };
 // ---- transforms
 template <typename T>
 hipError_t launch_pass(int N, int kind, int axis, const T* in, T* out, bool accumulate, const DevTables<T>& tb,
-                       hipStream_t s);
+                       hipStream_t s, const Bat& bt = Bat());
 // fused x-pass of the Schur operator for the three components (fwd x, weight, inverse x)
 template <typename T>
-hipError_t launch_xmid(int N, T* A0, T* A1, T* A2, double mu, const DevTables<T>& tb, hipStream_t s);
+hipError_t launch_xmid(int N, T* A0, T* A1, T* A2, double mu, const DevTables<T>& tb, hipStream_t s,
+                       const Bat& bt = Bat());
 // Forward z pass of the Schur matvec (A = DST-II_z v, B = DCT-II_z v) with the CG updates folded in:
 //   ZF_PLAIN  v = r (x, d, q, scal, rpart unused)
 //   ZF_FIRST  d = r, v = d; rpart[block] = partial r.r
@@ -42,83 +56,94 @@ hipError_t launch_xmid(int N, T* A0, T* A1, T* A2, double mu, const DevTables<T>
 enum ZfwdMode { ZF_PLAIN = 0, ZF_FIRST = 1, ZF_FUSED = 2 };
 template <typename T>
 hipError_t launch_zfwd_cg(int N, int mode, T* x, T* r, T* d, const T* q, T* A, T* B, const double* scal,
-                          double* rpart, const DevTables<T>& tb, hipStream_t s);
+                          double* rpart, const DevTables<T>& tb, hipStream_t s, const Bat& bt = Bat());
 int zfwd_blocks(int N, int elem_size);
 // q = DST-III_z(A) + DCT-III_z(B) + c d; per-block partial sums (d.q, q, d, q.q), 4 per block
 template <typename T>
 hipError_t launch_zinv_cg(int N, const T* A, const T* B, T* q, const T* d, double c, double* partials,
-                          const DevTables<T>& tb, hipStream_t s);
+                          const DevTables<T>& tb, hipStream_t s, const Bat& bt = Bat());
 // fused x pass of component m: right-hand side (fh = T_m,x in; out = C_m,x^T (-sigma/(mu Lambda)) fh)
 // or back-substitution (out = T_m,x^T ((fh + sigma C_m,x in) / (mu Lambda)))
 template <typename T>
 hipError_t launch_xfuse(int N, int m, bool backsub, const T* in, T* fh, T* out, double mu, const DevTables<T>& tb,
-                        hipStream_t s);
+                        hipStream_t s, const Bat& bt = Bat());
 // y passes with two transforms per block: forward (out0 = DST-II_y(in0), out1 = DCT-II_y(in0)),
 // inverse (out0 = DST-III_y(in0) + DCT-III_y(in1))
 template <typename T>
 hipError_t launch_ypair(int N, bool inverse, const T* in0, const T* in1, T* out0, T* out1, const DevTables<T>& tb,
-                        hipStream_t s);
+                        hipStream_t s, const Bat& bt = Bat());
 int zinv_blocks(int N, int elem_size);
 // x += scal[idx] d
 template <typename T>
-hipError_t launch_axpy_scal(int64_t M, T* x, const T* d, const double* scal, int idx, hipStream_t s);
+hipError_t launch_axpy_scal(int64_t M, T* x, const T* d, const double* scal, int idx, hipStream_t s,
+                            const Bat& bt = Bat());
 // CG coefficients from the partial sums of the forward z pass (r.r, nr blocks) and of the
 // inverse z pass (nz blocks of 4): scal[0] = |r_next|^2 (recurrence), [1] alpha, [2] beta,
 // [3] mean q (Stokes), [7] r.r
 hipError_t launch_cg_coef(const double* rpart, int nr, const double* zpart, int nz, double* scal, int stokes,
-                          int64_t M, hipStream_t s);
+                          int64_t M, hipStream_t s, const Bat& bt = Bat());
 
 // ---- reductions (float64, deterministic)
 // scal layout: [0] |r_next|^2, [1] alpha, [2] beta, [3] mean q, [5] scratch sum, [6] aux, [7] r.r,
 // [9] sum of the right-hand side
 enum ReduceOp { R_SUM = 2, R_RESNORM = 4, R_RESNORM0 = 5 };
+// (out, when given, is a work buffer like scal: it moves with the right-hand side in a batch)
 hipError_t launch_reduce(const double* partials, int nparts, int nper, double* scal, int op, int stokes,
-                         int64_t M, hipStream_t s, double* out = nullptr);  // R_SUM: *out (or scal[5])
+                         int64_t M, hipStream_t s, double* out = nullptr,
+                         const Bat& bt = Bat());  // R_SUM: *out (or scal[5])
 template <typename T>
 hipError_t launch_dot_partials(int64_t M, const T* a, const T* b, double* partials, int nblocks, hipStream_t s);
 template <typename T>
-hipError_t launch_sum_partials(int64_t M, const T* a, double* partials, int nblocks, hipStream_t s);
+hipError_t launch_sum_partials(int64_t M, const T* a, double* partials, int nblocks, hipStream_t s,
+                               const Bat& bt = Bat());
 template <typename T>
-hipError_t launch_add_scalar(int64_t M, T* a, const double* scal, int idx, double factor, hipStream_t s);
+hipError_t launch_add_scalar(int64_t M, T* a, const double* scal, int idx, double factor, hipStream_t s,
+                             const Bat& bt = Bat());
 
 // ---- elementwise
 template <typename T>
-hipError_t launch_fill(int64_t n, T* a, T v, hipStream_t s);
+hipError_t launch_fill(int64_t n, T* a, T v, hipStream_t s, const Bat& bt = Bat());
 template <typename T>
 hipError_t launch_axpby(int64_t n, T* y, double a, const T* x, double b, hipStream_t s);  // y = a x + b y
 
 // ---- full-system residual of the MAC scheme (float64)
 // r_u = F_u - (-mu lap u + G p), r_p = F_p - (D u + c p), internal layout
 // mixed refinement: r32 = (float) F and partial sums of F (3 per block, nparts blocks)
-hipError_t launch_refine_prep(int64_t M, const double* F, float* r32, double* partials, int nparts, hipStream_t s);
+hipError_t launch_refine_prep(int64_t M, const double* F, float* r32, double* partials, int nparts, hipStream_t s,
+                              const Bat& bt = Bat());
 // un, pn = u, p (+ 0 if first) + x32; r32 = float32 of the float64 residual F - A(un, pn) (pressure
 // part minus *shift); partial sums
 hipError_t launch_refine_residual(bool first, int N, double h, double mu, double c, const double* u, const double* p,
                                   const float* x32, const double* F, const double* shift, double* un, double* pn,
-                                  float* r32, double* partials, int nparts, hipStream_t s);
+                                  float* r32, double* partials, int nparts, hipStream_t s, const Bat& bt = Bat());
 
 // ---- surface stages (float64)
 // jumps of every crossing (jmap component-major: jmap[(r * 18 + c) * T + t]) and the fit
-// values of the control points (fitvals[18 cp + c])
+// values of the control points (fitvals[18 cp + c]).  In a batch one thread group serves up to
+// FJ_RHS right-hand sides, so the fit weights and jump maps are read once for all of them.
+constexpr int FJ_RHS = 4;
 hipError_t launch_fit_jump(int64_t T, const int64_t* nb_ptr, const int32_t* nb_idx, const double* fitw,
                            const double* jmap, const double* jfmap, const double* Fj, const double* phi,
-                           const int64_t* cp_of, double* jumps, double* fitvals, hipStream_t s);
+                           const int64_t* cp_of, double* jumps, double* fitvals, hipStream_t s,
+                           const Bat& bt = Bat());
 hipError_t launch_interp_jump(int64_t n, const int64_t* cp_target, const double* fitvals, const double* emap,
-                              const double* efmap, const double* Fj, double* ejump, hipStream_t s);
+                              const double* efmap, const double* Fj, double* ejump, hipStream_t s,
+                              const Bat& bt = Bat());
 // F[irr_node[r]] = correction of node r (assigned: each node appears once; F elsewhere untouched);
 // with r32 != nullptr also r32[irr_node[r]] = (float) the same value and, over nparts blocks,
 // partial sums (F_u.F_u, sum F_p, F_p.F_p) of the corrections (M = N^3 splits F_u from F_p)
 hipError_t launch_correct(int64_t nirr, const int64_t* irr_node, const int64_t* irr_ptr, const int32_t* arm_t,
                           const int8_t* arm_o, const double* arm_a, const double* jumps, double* F, hipStream_t s,
-                          float* r32 = nullptr, int64_t M = 0, double* partials = nullptr, int nparts = 0);
+                          float* r32 = nullptr, int64_t M = 0, double* partials = nullptr, int nparts = 0,
+                          const Bat& bt = Bat());
 // probes: out[r] = sum_{q<8} w[8r+q] u[idx[8r+q]], r < 3 m (trilinear)
 hipError_t launch_interp8(int64_t m, const int64_t* idx, const double* w, const double* u, double* out, hipStream_t s);
 hipError_t launch_stab(int64_t n, const int64_t* ptr, const int32_t* idx, const double* sw, const double* a,
-                       const double* phi, double* out, hipStream_t s);
+                       const double* phi, double* out, hipStream_t s, const Bat& bt = Bat());
 hipError_t launch_stab_T(int64_t n, const int64_t* ptr, const int32_t* row, const double* sw, const double* a,
                          const double* w, double* out, hipStream_t s);
 hipError_t launch_interp(int64_t n, const int64_t* idx, const double* w, const double* u, const double* ejump,
-                         double* out, hipStream_t s);
+                         double* out, hipStream_t s, const Bat& bt = Bat());
 // adjoint
 hipError_t launch_interp_T(int64_t nnode, const int64_t* ptr, const int64_t* node, const int32_t* row,
                            const double* w, const double* wbar, double* ubar, hipStream_t s);

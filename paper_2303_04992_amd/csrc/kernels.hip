@@ -35,6 +35,19 @@ static Tab<T> tab_of(const DevTables<T>& d) {
   return t;
 }
 
+// Batched launches (see Bat): the right-hand side of a block is blockIdx.z; its work buffers lie
+// blockIdx.z * A bytes after those of right-hand side 0, its caller arrays blockIdx.z * U
+// elements further; null pointers stay null.
+__device__ __forceinline__ bool rhs_skipped(const Bat& b) { return b.act != nullptr && b.act[blockIdx.z] == 0; }
+template <typename P>
+__device__ __forceinline__ P wb(P p, const Bat& b) {
+  return p ? reinterpret_cast<P>(reinterpret_cast<uintptr_t>(p) + (uint64_t)blockIdx.z * (uint64_t)b.A) : p;
+}
+template <typename P>
+__device__ __forceinline__ P ub(P p, const Bat& b) {
+  return p ? p + (int64_t)blockIdx.z * b.U : p;
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
@@ -171,8 +184,11 @@ __device__ __forceinline__ void stage_xy(T* lds, const C2<T> (&raw)[PipeCfg<T, N
 }
 
 template <typename T, int N, int KIND>
-__global__ __launch_bounds__(256) void k_pass_pipe(const T* in, T* out, int axis, int ntiles, Tab<T> tg) {
+__global__ __launch_bounds__(256) void k_pass_pipe(const T* in, T* out, int axis, int ntiles, Tab<T> tg, Bat bt) {
   extern __shared__ __align__(16) unsigned char smem[];
+  if (rhs_skipped(bt)) return;
+  in = wb(in, bt);
+  out = wb(out, bt);
   T* lds = reinterpret_cast<T*>(smem);
   using S = TileCfg<T, N, KIND>;
   constexpr int W = S::W;
@@ -220,8 +236,11 @@ static int persistent_blocks(K kernel, int threads, size_t lds_bytes, int ntiles
 // ---------------------------------------------------------------------------------------
 // (in may equal out: a block reads its whole tile before it writes any output)
 template <typename T, int N, int KIND, bool ACC>
-__global__ __launch_bounds__(256) void k_pass(const T* in, T* out, int axis, Tab<T> tb) {
+__global__ __launch_bounds__(256) void k_pass(const T* in, T* out, int axis, Tab<T> tb, Bat bt) {
   extern __shared__ __align__(16) unsigned char smem[];
+  if (rhs_skipped(bt)) return;
+  in = wb(in, bt);
+  out = wb(out, bt);
   T* lds = reinterpret_cast<T*>(smem);
   using S = TileCfg<T, N, KIND>;
   using O = OutItems<T, N, KIND>;
@@ -536,8 +555,12 @@ __device__ __forceinline__ void store_xy_outputs(const T* lds, const Tab<T>& tb,
 // ---------------------------------------------------------------------------------------
 template <typename T, int N, int KF, int KI, bool BACKSUB>
 __global__ __launch_bounds__(256) void k_xfuse(const T* __restrict__ in, T* __restrict__ fh, T* __restrict__ out,
-                                              int m, double mu, Tab<T> tb) {
+                                              int m, double mu, Tab<T> tb, Bat bt) {
   extern __shared__ __align__(16) unsigned char smem[];
+  if (rhs_skipped(bt)) return;
+  in = wb(in, bt);
+  fh = wb(fh, bt);
+  out = wb(out, bt);
   T* lds = reinterpret_cast<T*>(smem);
   using SF = TileCfg<T, N, KF>;
   using OF = OutItems<T, N, KF>;
@@ -624,8 +647,12 @@ __device__ void xmid_body(T* lds, T* field, int mc, double mu, const Tab<T>& tb)
 }
 
 template <typename T, int N>
-__global__ __launch_bounds__(256) void k_xmid(T* A0, T* A1, T* A2, double mu, Tab<T> tb) {
+__global__ __launch_bounds__(256) void k_xmid(T* A0, T* A1, T* A2, double mu, Tab<T> tb, Bat bt) {
   extern __shared__ __align__(16) unsigned char smem[];
+  if (rhs_skipped(bt)) return;
+  A0 = wb(A0, bt);
+  A1 = wb(A1, bt);
+  A2 = wb(A2, bt);
   T* lds = reinterpret_cast<T*>(smem);
   // float64: the component written last by the y passes (2) first, while it is still in the
   // last-level cache (27.6 -> 26.9 ms per float64 evaluation at 256^3, the following inverse y
@@ -672,9 +699,18 @@ template <typename T, int N, int MODE>
 __global__ __launch_bounds__(256) void k_zfwd_cg(T* __restrict__ x, T* __restrict__ r, T* __restrict__ d,
                                                 const T* __restrict__ q, T* __restrict__ A, T* __restrict__ B,
                                                 const double* __restrict__ scal, double* __restrict__ rpart,
-                                                Tab<T> tb) {
+                                                Tab<T> tb, Bat bt) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red[4];
+  if (rhs_skipped(bt)) return;
+  x = wb(x, bt);
+  r = wb(r, bt);
+  d = wb(d, bt);
+  q = wb(q, bt);
+  A = wb(A, bt);
+  B = wb(B, bt);
+  scal = wb(scal, bt);
+  rpart = wb(rpart, bt);
   T* lds = reinterpret_cast<T*>(smem);
   using S = TileCfg<T, N, DST2>;
   constexpr int W = S::W, RS = N + 1, NT = S::NT, VEC = V16<T>::n;
@@ -744,9 +780,15 @@ __global__ __launch_bounds__(256) void k_zfwd_cg(T* __restrict__ x, T* __restric
 template <typename T, int N>
 __global__ __launch_bounds__(256) void k_zinv_cg(const T* __restrict__ A, const T* __restrict__ B,
                                                 T* __restrict__ q, const T* __restrict__ d, double c,
-                                                double* __restrict__ partials, Tab<T> tb) {
+                                                double* __restrict__ partials, Tab<T> tb, Bat bt) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red[16];  // 4 sums x up to 4 wavefronts
+  if (rhs_skipped(bt)) return;
+  A = wb(A, bt);
+  B = wb(B, bt);
+  q = wb(q, bt);
+  d = wb(d, bt);
+  partials = wb(partials, bt);
   T* lds = reinterpret_cast<T*>(smem);
   using S = TileCfg<T, N, DCT3>;
   using O = OutItems<T, N, DCT3>;
@@ -830,8 +872,12 @@ __global__ __launch_bounds__(256) void k_zinv_cg(const T* __restrict__ A, const 
 // the reordered pencil negated: one gather serves both transforms, A is read once.
 template <typename T, int N>
 __global__ __launch_bounds__(256) void k_ypair_fwd(const T* __restrict__ A, T* __restrict__ A1, T* __restrict__ B2,
-                                                  Tab<T> tb) {
+                                                  Tab<T> tb, Bat bt) {
   extern __shared__ __align__(16) unsigned char smem[];
+  if (rhs_skipped(bt)) return;
+  A = wb(A, bt);
+  A1 = wb(A1, bt);
+  B2 = wb(B2, bt);
   T* lds = reinterpret_cast<T*>(smem);
   using S = TileCfg<T, N, DCT2>;
   static_assert(S::R1 == TileCfg<T, N, DST2>::R1 && S::R2 == TileCfg<T, N, DST2>::R2, "one gather for both kinds");
@@ -857,8 +903,12 @@ __global__ __launch_bounds__(256) void k_ypair_fwd(const T* __restrict__ A, T* _
 
 template <typename T, int N>
 __global__ __launch_bounds__(256) void k_ypair_inv(const T* __restrict__ A1, const T* __restrict__ B2,
-                                                  T* __restrict__ A, Tab<T> tb) {
+                                                  T* __restrict__ A, Tab<T> tb, Bat bt) {
   extern __shared__ __align__(16) unsigned char smem[];
+  if (rhs_skipped(bt)) return;
+  A1 = wb(A1, bt);
+  B2 = wb(B2, bt);
+  A = wb(A, bt);
   T* lds = reinterpret_cast<T*>(smem);
   using O = OutItems<T, N, DST3>;
   constexpr int W = TileCfg<T, N, DST3>::W;
@@ -895,8 +945,12 @@ __global__ __launch_bounds__(256) void k_ypair_inv(const T* __restrict__ A1, con
 constexpr int CG_NT = 1024;  // threads of the coefficient kernel (its loads are latency-bound)
 __global__ __launch_bounds__(CG_NT) void k_cg_coef(const double* __restrict__ rpart, int nr,
                                                 const double* __restrict__ zpart, int nz, double* __restrict__ scal,
-                                                int stokes, int64_t M) {
+                                                int stokes, int64_t M, Bat bt) {
   __shared__ double red[CG_NT / 64];
+  if (rhs_skipped(bt)) return;
+  rpart = wb(rpart, bt);
+  zpart = wb(zpart, bt);
+  scal = wb(scal, bt);
   double acc[5] = {0, 0, 0, 0, 0};
 #pragma unroll 2
   for (int i = threadIdx.x; i < nr; i += CG_NT) acc[0] += rpart[i];
@@ -932,7 +986,11 @@ __global__ __launch_bounds__(CG_NT) void k_cg_coef(const double* __restrict__ rp
 // x += scal[idx] d
 template <typename T>
 __global__ __launch_bounds__(EW_NT) void k_axpy_scal(int64_t M, T* __restrict__ x, const T* __restrict__ d,
-                                                  const double* __restrict__ scal, int idx) {
+                                                  const double* __restrict__ scal, int idx, Bat bt) {
+  if (rhs_skipped(bt)) return;
+  x = wb(x, bt);
+  d = wb(d, bt);
+  scal = wb(scal, bt);
   const T a = T(scal[idx]);
   for (int64_t i = (int64_t)blockIdx.x * EW_NT + threadIdx.x; i < M; i += (int64_t)gridDim.x * EW_NT)
     x[i] += a * d[i];
@@ -950,8 +1008,12 @@ __global__ __launch_bounds__(EW_NT) void k_dot_partials(int64_t M, const T* __re
 }
 
 template <typename T>
-__global__ __launch_bounds__(EW_NT) void k_sum_partials(int64_t M, const T* __restrict__ a, double* __restrict__ partials) {
+__global__ __launch_bounds__(EW_NT) void k_sum_partials(int64_t M, const T* __restrict__ a, double* __restrict__ partials,
+                                                     Bat bt) {
   __shared__ double red[EW_NT / 64];
+  if (rhs_skipped(bt)) return;
+  a = wb(a, bt);
+  partials = wb(partials, bt);
   double s = 0;
   for (int64_t i = (int64_t)blockIdx.x * EW_NT + threadIdx.x; i < M; i += (int64_t)gridDim.x * EW_NT) s += (double)a[i];
   double t = block_sum(s, red);
@@ -960,8 +1022,12 @@ __global__ __launch_bounds__(EW_NT) void k_sum_partials(int64_t M, const T* __re
 
 __global__ __launch_bounds__(EW_NT) void k_reduce(const double* __restrict__ partials, int nparts, int nper,
                                                double* __restrict__ scal, int op, int stokes, int64_t M,
-                                               double* __restrict__ out) {
+                                               double* __restrict__ out, Bat bt) {
   __shared__ double red[EW_NT / 64];
+  if (rhs_skipped(bt)) return;
+  partials = wb(partials, bt);
+  scal = wb(scal, bt);
+  out = wb(out, bt);
   double acc[3] = {0, 0, 0};
   for (int i = threadIdx.x; i < nparts; i += EW_NT)
     for (int c = 0; c < nper; ++c) acc[c] += partials[(int64_t)i * nper + c];
@@ -983,7 +1049,10 @@ __global__ __launch_bounds__(EW_NT) void k_reduce(const double* __restrict__ par
 }
 
 template <typename T>
-__global__ void k_add_scalar(int64_t M, T* a, const double* scal, int idx, double factor) {
+__global__ void k_add_scalar(int64_t M, T* a, const double* scal, int idx, double factor, Bat bt) {
+  if (rhs_skipped(bt)) return;
+  a = wb(a, bt);
+  scal = wb(scal, bt);
   const T v = T(scal[idx] * factor);
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < M; i += (int64_t)gridDim.x * blockDim.x)
     a[i] += v;
@@ -994,7 +1063,9 @@ __global__ void k_add_scalar(int64_t M, T* a, const double* scal, int idx, doubl
 // elementwise
 // ---------------------------------------------------------------------------------------
 template <typename T>
-__global__ void k_fill(int64_t n, T* a, T v) {
+__global__ void k_fill(int64_t n, T* a, T v, Bat bt) {
+  if (rhs_skipped(bt)) return;
+  a = wb(a, bt);
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     a[i] = v;
 }
@@ -1016,8 +1087,13 @@ __global__ void k_axpby(int64_t n, T* y, double a, const T* x, double b) {
 // pressure right-hand side itself, and F_p is not small against its mean); per-block partial
 // sums of F_u.F_u, sum F_p, F_p.F_p
 __global__ __launch_bounds__(EW_NT) void k_refine_prep(int64_t M, const double* __restrict__ F,
-                                                    float* __restrict__ r32, double* __restrict__ partials) {
+                                                    float* __restrict__ r32, double* __restrict__ partials,
+                                                    Bat bt) {
   __shared__ double red[EW_NT / 64];
+  if (rhs_skipped(bt)) return;
+  F = wb(F, bt);
+  r32 = wb(r32, bt);
+  partials = wb(partials, bt);
   double su = 0, sp = 0, spp = 0;
   // the four fields as one flat array, four values per thread (M is a multiple of 4): 32-byte
   // loads, 16-byte stores, one stream at a time instead of four 2^k-apart streams
@@ -1057,8 +1133,18 @@ __global__ __launch_bounds__(EW_NT) void k_refine_residual(int N, double h, doub
                                                         const float* __restrict__ x32, const double* __restrict__ F,
                                                         const double* __restrict__ shift, double* __restrict__ un,
                                                         double* __restrict__ pn, float* __restrict__ r32,
-                                                        double* __restrict__ partials) {
+                                                        double* __restrict__ partials, Bat bt) {
   __shared__ double red[EW_NT / 64];
+  if (rhs_skipped(bt)) return;
+  u = wb(u, bt);
+  p = wb(p, bt);
+  x32 = wb(x32, bt);
+  F = wb(F, bt);
+  shift = wb(shift, bt);
+  un = wb(un, bt);
+  pn = wb(pn, bt);
+  r32 = wb(r32, bt);
+  partials = wb(partials, bt);
   const double sh = shift ? *shift : 0.0;
   // N is a power of two and N^3 < 2^31 (N <= 512): 32-bit indices, shifts and masks
   const int lg = __builtin_ctz(N), mask = N - 1;
@@ -1136,54 +1222,86 @@ __global__ __launch_bounds__(EW_NT) void k_refine_residual(int N, double h, doub
 // jmap[(r * 18 + c) * T + t]; fit values are kept only for the control points
 // (fitvals[18 cp + c]), which the interpolation jump needs.
 constexpr int FJ_LANES = 8;
+// work buffer of right-hand side r (batched launches serve several per block)
+template <typename P>
+__device__ __forceinline__ P wbr(P p, const Bat& b, int r) {
+  return reinterpret_cast<P>(reinterpret_cast<uintptr_t>(p) + (uint64_t)r * (uint64_t)b.A);
+}
 __global__ __launch_bounds__(256) void k_fit_jump(int64_t T, const int64_t* __restrict__ nb_ptr,
                                                  const int32_t* __restrict__ nb_idx, const double* __restrict__ fitw,
                                                  const double* __restrict__ jmap, const double* __restrict__ jfmap,
                                                  const double* __restrict__ Fj, const double* __restrict__ phi,
                                                  const int64_t* __restrict__ cp_of, double* __restrict__ jumps,
-                                                 double* __restrict__ fitvals) {
+                                                 double* __restrict__ fitvals, Bat bt) {
   const int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / FJ_LANES;
   const int q = threadIdx.x % FJ_LANES;
   const bool live = t < T;  // all lanes stay for the shuffles
-  double fv[3] = {0.0, 0.0, 0.0};
+  // right-hand sides r0 .. r0 + nr - 1 of this group (nr is uniform over the block)
+  const int r0 = FJ_RHS * (int)blockIdx.z;
+  const int nr = min(FJ_RHS, bt.nb - r0);
+  double fv[FJ_RHS][3];
+#pragma unroll
+  for (int rr = 0; rr < FJ_RHS; ++rr) fv[rr][0] = fv[rr][1] = fv[rr][2] = 0.0;
   if (live && q < 6) {
     for (int64_t e = nb_ptr[t]; e < nb_ptr[t + 1]; ++e) {
       const int64_t cp = nb_idx[e];
       const double w = fitw[6 * e + q];
-      fv[0] += w * phi[3 * cp];
-      fv[1] += w * phi[3 * cp + 1];
-      fv[2] += w * phi[3 * cp + 2];
+#pragma unroll
+      for (int rr = 0; rr < FJ_RHS; ++rr)
+        if (rr < nr) {
+          const double* ph = phi + (int64_t)(r0 + rr) * bt.U;
+          fv[rr][0] += w * ph[3 * cp];
+          fv[rr][1] += w * ph[3 * cp + 1];
+          fv[rr][2] += w * ph[3 * cp + 2];
+        }
     }
     const int64_t cp = cp_of[t];
     if (cp >= 0)
-      for (int i = 0; i < 3; ++i) fitvals[18 * cp + 3 * q + i] = fv[i];
+#pragma unroll
+      for (int rr = 0; rr < FJ_RHS; ++rr)
+        if (rr < nr)
+          for (int i = 0; i < 3; ++i) wbr(fitvals, bt, r0 + rr)[18 * cp + 3 * q + i] = fv[rr][i];
   }
-  double part[5];
+  double part[FJ_RHS][5];
 #pragma unroll
   for (int r = 0; r < 5; ++r) {
-    double s = 0.0;
+    double jm[3] = {0.0, 0.0, 0.0};
     if (live && q < 6)
-      for (int i = 0; i < 3; ++i) s += jmap[(int64_t)(r * 18 + 3 * q + i) * T + t] * fv[i];
+      for (int i = 0; i < 3; ++i) jm[i] = jmap[(int64_t)(r * 18 + 3 * q + i) * T + t];
 #pragma unroll
-    for (int o = 1; o < FJ_LANES; o <<= 1) s += __shfl_xor(s, o, FJ_LANES);
-    part[r] = s;
+    for (int rr = 0; rr < FJ_RHS; ++rr) {
+      part[rr][r] = 0.0;
+      if (rr < nr) {
+        double s = jm[0] * fv[rr][0] + jm[1] * fv[rr][1] + jm[2] * fv[rr][2];
+#pragma unroll
+        for (int o = 1; o < FJ_LANES; o <<= 1) s += __shfl_xor(s, o, FJ_LANES);
+        part[rr][r] = s;
+      }
+    }
   }
   if (live && q < 5) {
-    double s = part[0];
 #pragma unroll
-    for (int r = 1; r < 5; ++r)
-      if (q == r) s = part[r];
-    if (Fj) {
-      const double* Fr = jfmap + (t * 5 + q) * 3;
-      s += Fr[0] * Fj[3 * t] + Fr[1] * Fj[3 * t + 1] + Fr[2] * Fj[3 * t + 2];
-    }
-    jumps[5 * t + q] = s;
+    for (int rr = 0; rr < FJ_RHS; ++rr)
+      if (rr < nr) {
+        double s = part[rr][0];
+#pragma unroll
+        for (int r = 1; r < 5; ++r)
+          if (q == r) s = part[rr][r];
+        if (Fj) {
+          const double* Fr = jfmap + (t * 5 + q) * 3;
+          s += Fr[0] * Fj[3 * t] + Fr[1] * Fj[3 * t + 1] + Fr[2] * Fj[3 * t + 2];
+        }
+        wbr(jumps, bt, r0 + rr)[5 * t + q] = s;
+      }
   }
 }
 
 __global__ void k_interp_jump(int64_t n, const int64_t* __restrict__ cp_target, const double* __restrict__ fitvals,
                               const double* __restrict__ emap, const double* __restrict__ efmap,
-                              const double* __restrict__ Fj, double* __restrict__ ejump) {
+                              const double* __restrict__ Fj, double* __restrict__ ejump, Bat bt) {
+  if (rhs_skipped(bt)) return;
+  fitvals = wb(fitvals, bt);
+  ejump = wb(ejump, bt);
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= 3 * n) return;
   const int64_t c = r / 3;
@@ -1204,8 +1322,13 @@ __global__ __launch_bounds__(EW_NT) void k_correct(int64_t nirr, const int64_t* 
                                                 const int32_t* __restrict__ arm_t, const int8_t* __restrict__ arm_o,
                                                 const double* __restrict__ arm_a, const double* __restrict__ jumps,
                                                 double* __restrict__ F, float* __restrict__ r32, int64_t M,
-                                                double* __restrict__ partials) {
+                                                double* __restrict__ partials, Bat bt) {
   __shared__ double red[EW_NT / 64];
+  if (rhs_skipped(bt)) return;
+  jumps = wb(jumps, bt);
+  F = wb(F, bt);
+  r32 = wb(r32, bt);
+  partials = wb(partials, bt);
   double su = 0, sp = 0, spp = 0;
   for (int64_t r = (int64_t)blockIdx.x * EW_NT + threadIdx.x; r < nirr; r += (int64_t)gridDim.x * EW_NT) {
     double v = 0;
@@ -1238,7 +1361,12 @@ __global__ __launch_bounds__(EW_NT) void k_correct(int64_t nirr, const int64_t* 
 }
 
 __global__ void k_interp(int64_t n, const int64_t* __restrict__ idx, const double* __restrict__ w,
-                         const double* __restrict__ u, const double* __restrict__ ejump, double* __restrict__ out) {
+                         const double* __restrict__ u, const double* __restrict__ ejump, double* __restrict__ out,
+                         Bat bt) {
+  if (rhs_skipped(bt)) return;
+  u = wb(u, bt);
+  ejump = wb(ejump, bt);
+  out = ub(out, bt);
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= 3 * n) return;
   double s = ejump[r];
@@ -1251,7 +1379,10 @@ __global__ void k_interp(int64_t n, const int64_t* __restrict__ idx, const doubl
 //   out[r] += a[r] (phi[r] - sum_e sw[e] phi[3 idx[e] + m]),  a = 1/2 - exterior weight fraction
 __global__ void k_stab(int64_t n, const int64_t* __restrict__ ptr, const int32_t* __restrict__ idx,
                        const double* __restrict__ sw, const double* __restrict__ a, const double* __restrict__ phi,
-                       double* __restrict__ out) {
+                       double* __restrict__ out, Bat bt) {
+  if (rhs_skipped(bt)) return;
+  phi = ub(phi, bt);
+  out = ub(out, bt);
   const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= 3 * n) return;
   const int64_t c = r / 3;
@@ -1411,7 +1542,7 @@ static void ensure_lds(K kernel, size_t bytes) {
   }
 
 template <typename T, int N, int KIND, bool ACC>
-static hipError_t pass_n(int axis, const T* in, T* out, const Tab<T>& tb, hipStream_t s) {
+static hipError_t pass_n(int axis, const T* in, T* out, const Tab<T>& tb, hipStream_t s, const Bat& bt) {
   using S = TileCfg<T, N, KIND>;
   const size_t lds = S::BYTES;
   const int blocks = N * N / S::W;
@@ -1423,20 +1554,22 @@ static hipError_t pass_n(int axis, const T* in, T* out, const Tab<T>& tb, hipStr
       ensure_lds(k_pass_pipe<T, N, KIND>, P::BYTES);
       static std::atomic<int> per_cu{0};
       const int pb = persistent_blocks(k_pass_pipe<T, N, KIND>, S::NT, P::BYTES, blocks, per_cu);
-      hipLaunchKernelGGL((k_pass_pipe<T, N, KIND>), dim3(pb), dim3(S::NT), P::BYTES, s, in, out, axis, blocks, tb);
+      hipLaunchKernelGGL((k_pass_pipe<T, N, KIND>), dim3(pb, 1, bt.nb), dim3(S::NT), P::BYTES, s, in, out, axis, blocks,
+                         tb, bt);
       return hipGetLastError();
     }
   }
   ensure_lds(k_pass<T, N, KIND, ACC>, lds);
-  hipLaunchKernelGGL((k_pass<T, N, KIND, ACC>), dim3(blocks), dim3(S::NT), lds, s, in, out, axis, tb);
+  hipLaunchKernelGGL((k_pass<T, N, KIND, ACC>), dim3(blocks, 1, bt.nb), dim3(S::NT), lds, s, in, out, axis, tb, bt);
   return hipGetLastError();
 }
 
 template <typename T, int N>
-static hipError_t pass_kind(int kind, int axis, const T* in, T* out, bool acc, const Tab<T>& tb, hipStream_t s) {
+static hipError_t pass_kind(int kind, int axis, const T* in, T* out, bool acc, const Tab<T>& tb, hipStream_t s,
+                            const Bat& bt) {
 #define KFBI_K(KD)                                                                            \
   case KD:                                                                                    \
-    return acc ? pass_n<T, N, KD, true>(axis, in, out, tb, s) : pass_n<T, N, KD, false>(axis, in, out, tb, s);
+    return acc ? pass_n<T, N, KD, true>(axis, in, out, tb, s, bt) : pass_n<T, N, KD, false>(axis, in, out, tb, s, bt);
   switch (kind) {
     KFBI_K(DCT2)
     KFBI_K(DST2)
@@ -1450,9 +1583,9 @@ static hipError_t pass_kind(int kind, int axis, const T* in, T* out, bool acc, c
 
 template <typename T>
 hipError_t launch_pass(int N, int kind, int axis, const T* in, T* out, bool accumulate, const DevTables<T>& tb,
-                       hipStream_t s) {
+                       hipStream_t s, const Bat& bt) {
   const Tab<T> t = tab_of(tb);
-#define KFBI_M(NN) return pass_kind<T, NN>(kind, axis, in, out, accumulate, t, s)
+#define KFBI_M(NN) return pass_kind<T, NN>(kind, axis, in, out, accumulate, t, s, bt)
   KFBI_DISPATCH_N(N, KFBI_M)
 #undef KFBI_M
   return hipErrorInvalidValue;
@@ -1460,7 +1593,7 @@ hipError_t launch_pass(int N, int kind, int axis, const T* in, T* out, bool accu
 
 
 template <typename T>
-hipError_t launch_xmid(int N, T* A0, T* A1, T* A2, double mu, const DevTables<T>& tb, hipStream_t s) {
+hipError_t launch_xmid(int N, T* A0, T* A1, T* A2, double mu, const DevTables<T>& tb, hipStream_t s, const Bat& bt) {
   const Tab<T> t = tab_of(tb);
 #define KFBI_M(NN)                                                                                              \
   {                                                                                                             \
@@ -1468,7 +1601,7 @@ hipError_t launch_xmid(int N, T* A0, T* A1, T* A2, double mu, const DevTables<T>
     const int blocks = NN * NN / S::W;                                                                          \
     const size_t lds = S::BYTES;                                                                                \
     ensure_lds(k_xmid<T, NN>, lds);                                                                             \
-    hipLaunchKernelGGL((k_xmid<T, NN>), dim3(blocks, 3), dim3(S::NT), lds, s, A0, A1, A2, mu, t);               \
+    hipLaunchKernelGGL((k_xmid<T, NN>), dim3(blocks, 3, bt.nb), dim3(S::NT), lds, s, A0, A1, A2, mu, t, bt);    \
   }
   KFBI_DISPATCH_N(N, KFBI_M)
 #undef KFBI_M
@@ -1477,7 +1610,7 @@ hipError_t launch_xmid(int N, T* A0, T* A1, T* A2, double mu, const DevTables<T>
 
 template <typename T>
 hipError_t launch_zfwd_cg(int N, int mode, T* x, T* r, T* d, const T* q, T* A, T* B, const double* scal,
-                          double* rpart, const DevTables<T>& tb, hipStream_t s) {
+                          double* rpart, const DevTables<T>& tb, hipStream_t s, const Bat& bt) {
   const Tab<T> t = tab_of(tb);
 #define KFBI_ZF(NN, MODE)                                                                                  \
   {                                                                                                        \
@@ -1485,8 +1618,8 @@ hipError_t launch_zfwd_cg(int N, int mode, T* x, T* r, T* d, const T* q, T* A, T
     const int blocks = NN * NN / S::W;                                                                     \
     const size_t lds = S::BYTES;                                                                           \
     ensure_lds(k_zfwd_cg<T, NN, MODE>, lds);                                                               \
-    hipLaunchKernelGGL((k_zfwd_cg<T, NN, MODE>), dim3(blocks), dim3(S::NT), lds, s, x, r, d, q, A, B, scal, \
-                       rpart, t);                                                                          \
+    hipLaunchKernelGGL((k_zfwd_cg<T, NN, MODE>), dim3(blocks, 1, bt.nb), dim3(S::NT), lds, s, x, r, d, q, A, B, \
+                       scal, rpart, t, bt);                                                                \
   }
 #define KFBI_M(NN)            \
   {                           \
@@ -1508,7 +1641,7 @@ int zinv_blocks(int N, int elem_size) { return N * N / std::min(128 / elem_size,
 
 template <typename T>
 hipError_t launch_zinv_cg(int N, const T* A, const T* B, T* q, const T* d, double c, double* partials,
-                          const DevTables<T>& tb, hipStream_t s) {
+                          const DevTables<T>& tb, hipStream_t s, const Bat& bt) {
   const Tab<T> t = tab_of(tb);
 #define KFBI_M(NN)                                                                                         \
   {                                                                                                        \
@@ -1516,7 +1649,8 @@ hipError_t launch_zinv_cg(int N, const T* A, const T* B, T* q, const T* d, doubl
     const int blocks = NN * NN / S::W;                                                                     \
     const size_t lds = S::BYTES;                                                                           \
     ensure_lds(k_zinv_cg<T, NN>, lds);                                                                     \
-    hipLaunchKernelGGL((k_zinv_cg<T, NN>), dim3(blocks), dim3(S::NT), lds, s, A, B, q, d, c, partials, t); \
+    hipLaunchKernelGGL((k_zinv_cg<T, NN>), dim3(blocks, 1, bt.nb), dim3(S::NT), lds, s, A, B, q, d, c, partials, \
+                       t, bt);                                                                             \
   }
   KFBI_DISPATCH_N(N, KFBI_M)
 #undef KFBI_M
@@ -1524,27 +1658,29 @@ hipError_t launch_zinv_cg(int N, const T* A, const T* B, T* q, const T* d, doubl
 }
 
 template <typename T, int N, int KF, int KI, bool BS>
-static hipError_t xfuse_n(int m, const T* in, T* fh, T* out, double mu, const DevTables<T>& tb, hipStream_t s) {
+static hipError_t xfuse_n(int m, const T* in, T* fh, T* out, double mu, const DevTables<T>& tb, hipStream_t s,
+                          const Bat& bt) {
   using SF = TileCfg<T, N, KF>;
   using SI = TileCfg<T, N, KI>;
   const size_t lds = SF::BYTES > SI::BYTES ? SF::BYTES : SI::BYTES;
   const int nt = SF::NT > SI::NT ? SF::NT : SI::NT;
   const int blocks = N * N / SF::W;
   ensure_lds(k_xfuse<T, N, KF, KI, BS>, lds);
-  hipLaunchKernelGGL((k_xfuse<T, N, KF, KI, BS>), dim3(blocks), dim3(nt), lds, s, in, fh, out, m, mu, tab_of(tb));
+  hipLaunchKernelGGL((k_xfuse<T, N, KF, KI, BS>), dim3(blocks, 1, bt.nb), dim3(nt), lds, s, in, fh, out, m, mu,
+                     tab_of(tb), bt);
   return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_xfuse(int N, int m, bool backsub, const T* in, T* fh, T* out, double mu, const DevTables<T>& tb,
-                        hipStream_t s) {
+                        hipStream_t s, const Bat& bt) {
   if (m < 0 || m > 2) return hipErrorInvalidValue;
 #define KFBI_M(NN)                                                                            \
   if (backsub)                                                                                \
-    return m == 0 ? xfuse_n<T, NN, DCT2, DST1, true>(m, in, fh, out, mu, tb, s)               \
-                  : xfuse_n<T, NN, DST2, DST3, true>(m, in, fh, out, mu, tb, s);              \
-  return m == 0 ? xfuse_n<T, NN, DST1, DCT3, false>(m, in, fh, out, mu, tb, s)                \
-                : xfuse_n<T, NN, DST2, DST3, false>(m, in, fh, out, mu, tb, s);
+    return m == 0 ? xfuse_n<T, NN, DCT2, DST1, true>(m, in, fh, out, mu, tb, s, bt)           \
+                  : xfuse_n<T, NN, DST2, DST3, true>(m, in, fh, out, mu, tb, s, bt);          \
+  return m == 0 ? xfuse_n<T, NN, DST1, DCT3, false>(m, in, fh, out, mu, tb, s, bt)            \
+                : xfuse_n<T, NN, DST2, DST3, false>(m, in, fh, out, mu, tb, s, bt);
   KFBI_DISPATCH_N(N, KFBI_M)
 #undef KFBI_M
   return hipErrorInvalidValue;
@@ -1552,7 +1688,7 @@ hipError_t launch_xfuse(int N, int m, bool backsub, const T* in, T* fh, T* out, 
 
 template <typename T>
 hipError_t launch_ypair(int N, bool inverse, const T* in0, const T* in1, T* out0, T* out1, const DevTables<T>& tb,
-                        hipStream_t s) {
+                        hipStream_t s, const Bat& bt) {
   const Tab<T> t = tab_of(tb);
 #define KFBI_M(NN)                                                                                        \
   {                                                                                                       \
@@ -1561,10 +1697,10 @@ hipError_t launch_ypair(int N, bool inverse, const T* in0, const T* in1, T* out0
     const size_t lds = S::BYTES;                                                                          \
     if (inverse) {                                                                                        \
       ensure_lds(k_ypair_inv<T, NN>, lds);                                                                \
-      hipLaunchKernelGGL((k_ypair_inv<T, NN>), dim3(blocks), dim3(S::NT), lds, s, in0, in1, out0, t);     \
+      hipLaunchKernelGGL((k_ypair_inv<T, NN>), dim3(blocks, 1, bt.nb), dim3(S::NT), lds, s, in0, in1, out0, t, bt); \
     } else {                                                                                              \
       ensure_lds(k_ypair_fwd<T, NN>, lds);                                                                \
-      hipLaunchKernelGGL((k_ypair_fwd<T, NN>), dim3(blocks), dim3(S::NT), lds, s, in0, out0, out1, t);    \
+      hipLaunchKernelGGL((k_ypair_fwd<T, NN>), dim3(blocks, 1, bt.nb), dim3(S::NT), lds, s, in0, out0, out1, t, bt); \
     }                                                                                                     \
   }
   KFBI_DISPATCH_N(N, KFBI_M)
@@ -1573,20 +1709,21 @@ hipError_t launch_ypair(int N, bool inverse, const T* in0, const T* in1, T* out0
 }
 
 template <typename T>
-hipError_t launch_axpy_scal(int64_t M, T* x, const T* d, const double* scal, int idx, hipStream_t s) {
-  hipLaunchKernelGGL((k_axpy_scal<T>), dim3(1024), dim3(EW_NT), 0, s, M, x, d, scal, idx);
+hipError_t launch_axpy_scal(int64_t M, T* x, const T* d, const double* scal, int idx, hipStream_t s, const Bat& bt) {
+  hipLaunchKernelGGL((k_axpy_scal<T>), dim3(1024, 1, bt.nb), dim3(EW_NT), 0, s, M, x, d, scal, idx, bt);
   return hipGetLastError();
 }
 
 hipError_t launch_cg_coef(const double* rpart, int nr, const double* zpart, int nz, double* scal, int stokes,
-                          int64_t M, hipStream_t s) {
-  hipLaunchKernelGGL(k_cg_coef, dim3(1), dim3(CG_NT), 0, s, rpart, nr, zpart, nz, scal, stokes, M);
+                          int64_t M, hipStream_t s, const Bat& bt) {
+  hipLaunchKernelGGL(k_cg_coef, dim3(1, 1, bt.nb), dim3(CG_NT), 0, s, rpart, nr, zpart, nz, scal, stokes, M, bt);
   return hipGetLastError();
 }
 
 hipError_t launch_reduce(const double* partials, int nparts, int nper, double* scal, int op, int stokes, int64_t M,
-                         hipStream_t s, double* out) {
-  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(EW_NT), 0, s, partials, nparts, nper, scal, op, stokes, M, out);
+                         hipStream_t s, double* out, const Bat& bt) {
+  hipLaunchKernelGGL(k_reduce, dim3(1, 1, bt.nb), dim3(EW_NT), 0, s, partials, nparts, nper, scal, op, stokes, M, out,
+                     bt);
   return hipGetLastError();
 }
 
@@ -1596,18 +1733,19 @@ hipError_t launch_dot_partials(int64_t M, const T* a, const T* b, double* partia
   return hipGetLastError();
 }
 template <typename T>
-hipError_t launch_sum_partials(int64_t M, const T* a, double* partials, int nblocks, hipStream_t s) {
-  hipLaunchKernelGGL((k_sum_partials<T>), dim3(nblocks), dim3(EW_NT), 0, s, M, a, partials);
+hipError_t launch_sum_partials(int64_t M, const T* a, double* partials, int nblocks, hipStream_t s, const Bat& bt) {
+  hipLaunchKernelGGL((k_sum_partials<T>), dim3(nblocks, 1, bt.nb), dim3(EW_NT), 0, s, M, a, partials, bt);
   return hipGetLastError();
 }
 template <typename T>
-hipError_t launch_add_scalar(int64_t M, T* a, const double* scal, int idx, double factor, hipStream_t s) {
-  hipLaunchKernelGGL((k_add_scalar<T>), dim3(ew_blocks(M)), dim3(256), 0, s, M, a, scal, idx, factor);
+hipError_t launch_add_scalar(int64_t M, T* a, const double* scal, int idx, double factor, hipStream_t s,
+                             const Bat& bt) {
+  hipLaunchKernelGGL((k_add_scalar<T>), dim3(ew_blocks(M), 1, bt.nb), dim3(256), 0, s, M, a, scal, idx, factor, bt);
   return hipGetLastError();
 }
 template <typename T>
-hipError_t launch_fill(int64_t n, T* a, T v, hipStream_t s) {
-  hipLaunchKernelGGL((k_fill<T>), dim3(ew_blocks(n)), dim3(256), 0, s, n, a, v);
+hipError_t launch_fill(int64_t n, T* a, T v, hipStream_t s, const Bat& bt) {
+  hipLaunchKernelGGL((k_fill<T>), dim3(ew_blocks(n), 1, bt.nb), dim3(256), 0, s, n, a, v, bt);
   return hipGetLastError();
 }
 template <typename T>
@@ -1617,20 +1755,21 @@ hipError_t launch_axpby(int64_t n, T* y, double a, const T* x, double b, hipStre
 }
 
 
-hipError_t launch_refine_prep(int64_t M, const double* F, float* r32, double* partials, int nparts, hipStream_t s) {
-  hipLaunchKernelGGL(k_refine_prep, dim3(nparts), dim3(EW_NT), 0, s, M, F, r32, partials);
+hipError_t launch_refine_prep(int64_t M, const double* F, float* r32, double* partials, int nparts, hipStream_t s,
+                              const Bat& bt) {
+  hipLaunchKernelGGL(k_refine_prep, dim3(nparts, 1, bt.nb), dim3(EW_NT), 0, s, M, F, r32, partials, bt);
   return hipGetLastError();
 }
 hipError_t launch_refine_residual(bool first, int N, double h, double mu, double c, const double* u, const double* p,
                                   const float* x32, const double* F, const double* shift, double* un, double* pn,
-                                  float* r32, double* partials, int nparts, hipStream_t s) {
+                                  float* r32, double* partials, int nparts, hipStream_t s, const Bat& bt) {
   if (nparts % 8) return hipErrorInvalidValue;  // XCD-aware chunking needs a multiple of 8 blocks
   if (first)
-    hipLaunchKernelGGL(k_refine_residual<true>, dim3(nparts), dim3(EW_NT), 0, s, N, h, mu, c, u, p, x32, F, shift, un,
-                       pn, r32, partials);
+    hipLaunchKernelGGL(k_refine_residual<true>, dim3(nparts, 1, bt.nb), dim3(EW_NT), 0, s, N, h, mu, c, u, p, x32, F,
+                       shift, un, pn, r32, partials, bt);
   else
-    hipLaunchKernelGGL(k_refine_residual<false>, dim3(nparts), dim3(EW_NT), 0, s, N, h, mu, c, u, p, x32, F, shift,
-                       un, pn, r32, partials);
+    hipLaunchKernelGGL(k_refine_residual<false>, dim3(nparts, 1, bt.nb), dim3(EW_NT), 0, s, N, h, mu, c, u, p, x32, F,
+                       shift, un, pn, r32, partials, bt);
   return hipGetLastError();
 }
 
@@ -1638,33 +1777,35 @@ static inline int gb(int64_t n) { return (int)((n + 255) / 256 > 0 ? (n + 255) /
 
 hipError_t launch_fit_jump(int64_t T, const int64_t* nb_ptr, const int32_t* nb_idx, const double* fitw,
                            const double* jmap, const double* jfmap, const double* Fj, const double* phi,
-                           const int64_t* cp_of, double* jumps, double* fitvals, hipStream_t s) {
-  hipLaunchKernelGGL(k_fit_jump, dim3(gb(T * FJ_LANES)), dim3(256), 0, s, T, nb_ptr, nb_idx, fitw, jmap, jfmap, Fj,
-                     phi, cp_of, jumps, fitvals);
+                           const int64_t* cp_of, double* jumps, double* fitvals, hipStream_t s, const Bat& bt) {
+  if (bt.act) return hipErrorInvalidValue;  // every right-hand side of a batch takes part
+  hipLaunchKernelGGL(k_fit_jump, dim3(gb(T * FJ_LANES), 1, (bt.nb + FJ_RHS - 1) / FJ_RHS), dim3(256), 0, s, T, nb_ptr,
+                     nb_idx, fitw, jmap, jfmap, Fj, phi, cp_of, jumps, fitvals, bt);
   return hipGetLastError();
 }
 hipError_t launch_interp_jump(int64_t n, const int64_t* cp_target, const double* fitvals, const double* emap,
-                              const double* efmap, const double* Fj, double* ejump, hipStream_t s) {
-  hipLaunchKernelGGL(k_interp_jump, dim3(gb(3 * n)), dim3(256), 0, s, n, cp_target, fitvals, emap, efmap, Fj, ejump);
+                              const double* efmap, const double* Fj, double* ejump, hipStream_t s, const Bat& bt) {
+  hipLaunchKernelGGL(k_interp_jump, dim3(gb(3 * n), 1, bt.nb), dim3(256), 0, s, n, cp_target, fitvals, emap, efmap, Fj,
+                     ejump, bt);
   return hipGetLastError();
 }
 hipError_t launch_correct(int64_t nirr, const int64_t* irr_node, const int64_t* irr_ptr, const int32_t* arm_t,
                           const int8_t* arm_o, const double* arm_a, const double* jumps, double* F, hipStream_t s,
-                          float* r32, int64_t M, double* partials, int nparts) {
+                          float* r32, int64_t M, double* partials, int nparts, const Bat& bt) {
   const int blocks = r32 ? nparts : gb(nirr);
   if (r32 && (nparts < 1 || !partials)) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_correct, dim3(blocks), dim3(EW_NT), 0, s, nirr, irr_node, irr_ptr, arm_t, arm_o, arm_a, jumps,
-                     F, r32, M, partials);
+  hipLaunchKernelGGL(k_correct, dim3(blocks, 1, bt.nb), dim3(EW_NT), 0, s, nirr, irr_node, irr_ptr, arm_t, arm_o, arm_a,
+                     jumps, F, r32, M, partials, bt);
   return hipGetLastError();
 }
 hipError_t launch_interp(int64_t n, const int64_t* idx, const double* w, const double* u, const double* ejump,
-                         double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_interp, dim3(gb(3 * n)), dim3(256), 0, s, n, idx, w, u, ejump, out);
+                         double* out, hipStream_t s, const Bat& bt) {
+  hipLaunchKernelGGL(k_interp, dim3(gb(3 * n), 1, bt.nb), dim3(256), 0, s, n, idx, w, u, ejump, out, bt);
   return hipGetLastError();
 }
 hipError_t launch_stab(int64_t n, const int64_t* ptr, const int32_t* idx, const double* sw, const double* a,
-                       const double* phi, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_stab, dim3(gb(3 * n)), dim3(256), 0, s, n, ptr, idx, sw, a, phi, out);
+                       const double* phi, double* out, hipStream_t s, const Bat& bt) {
+  hipLaunchKernelGGL(k_stab, dim3(gb(3 * n), 1, bt.nb), dim3(256), 0, s, n, ptr, idx, sw, a, phi, out, bt);
   return hipGetLastError();
 }
 hipError_t launch_stab_T(int64_t n, const int64_t* ptr, const int32_t* row, const double* sw, const double* a,
@@ -1715,22 +1856,25 @@ hipError_t launch_check_finite(int64_t n, const double* a, int* flag, hipStream_
 
 // explicit instantiations
 #define KFBI_INST(T)                                                                                                 \
-  template hipError_t launch_pass<T>(int, int, int, const T*, T*, bool, const DevTables<T>&, hipStream_t);           \
-  template hipError_t launch_xmid<T>(int, T*, T*, T*, double, const DevTables<T>&, hipStream_t);                     \
+  template hipError_t launch_pass<T>(int, int, int, const T*, T*, bool, const DevTables<T>&, hipStream_t,          \
+                                     const Bat&);                                                                    \
+  template hipError_t launch_xmid<T>(int, T*, T*, T*, double, const DevTables<T>&, hipStream_t, const Bat&);         \
   template hipError_t launch_zfwd_cg<T>(int, int, T*, T*, T*, const T*, T*, T*, const double*, double*,               \
-                                        const DevTables<T>&, hipStream_t);                                           \
-  template hipError_t launch_ypair<T>(int, bool, const T*, const T*, T*, T*, const DevTables<T>&, hipStream_t);      \
-  template hipError_t launch_xfuse<T>(int, int, bool, const T*, T*, T*, double, const DevTables<T>&, hipStream_t);   \
+                                        const DevTables<T>&, hipStream_t, const Bat&);                               \
+  template hipError_t launch_ypair<T>(int, bool, const T*, const T*, T*, T*, const DevTables<T>&, hipStream_t,       \
+                                      const Bat&);                                                                   \
+  template hipError_t launch_xfuse<T>(int, int, bool, const T*, T*, T*, double, const DevTables<T>&, hipStream_t,    \
+                                      const Bat&);                                                                   \
   template hipError_t launch_zinv_cg<T>(int, const T*, const T*, T*, const T*, double, double*, const DevTables<T>&, \
-                                        hipStream_t);                                                                \
-  template hipError_t launch_axpy_scal<T>(int64_t, T*, const T*, const double*, int, hipStream_t);                   \
+                                        hipStream_t, const Bat&);                                                    \
+  template hipError_t launch_axpy_scal<T>(int64_t, T*, const T*, const double*, int, hipStream_t, const Bat&);       \
   template hipError_t launch_dot_partials<T>(int64_t, const T*, const T*, double*, int, hipStream_t);                \
-  template hipError_t launch_sum_partials<T>(int64_t, const T*, double*, int, hipStream_t);                          \
-  template hipError_t launch_add_scalar<T>(int64_t, T*, const double*, int, double, hipStream_t);                    \
-  template hipError_t launch_fill<T>(int64_t, T*, T, hipStream_t);                                                   \
+  template hipError_t launch_sum_partials<T>(int64_t, const T*, double*, int, hipStream_t, const Bat&);              \
+  template hipError_t launch_add_scalar<T>(int64_t, T*, const double*, int, double, hipStream_t, const Bat&);        \
+  template hipError_t launch_fill<T>(int64_t, T*, T, hipStream_t, const Bat&);                                       \
   template hipError_t launch_axpby<T>(int64_t, T*, double, const T*, double, hipStream_t);
 KFBI_INST(float)
 KFBI_INST(double)
-template hipError_t launch_fill<int>(int64_t, int*, int, hipStream_t);
+template hipError_t launch_fill<int>(int64_t, int*, int, hipStream_t, const Bat&);
 
 }  // namespace kfbi
