@@ -182,6 +182,26 @@ def run_batch(K, KI, cfg, rtol, inner, nrhs, steps, refs):
     return res
 
 
+def transforms_compare(K, KI, say, sizes=(128, 256, 512), reps=20):
+    """The DCT-II along x of one float32 field: the radix pass (k_pass) beside the split-bfloat16
+    matrix-core pass (k_gemm_x), mean launch time from HIP events (kfbi_time_pass), HBM rate of
+    the two field passes and the matrix-core rate (3 bfloat16 products of 2 N^4 flops each)."""
+    rows = []
+    for N in sizes:
+        op = K.Operator(KI.WORKLOADS["sphere32"].with_N(N), K.MIXED_FP32)
+        for kind, name in ((0, "radix k_pass DCT2 x"), (10, "matrix-core k_gemm_x DCT2 x")):
+            ms, by = op.time_pass(kind, 0, reps)
+            row = {"N": N, "kernel": name, "avg_us": round(ms * 1e3, 2), "gb_s": round(by / (ms * 1e-3) / 1e9, 1),
+                   "hbm_frac": round(by / (ms * 1e-3) / 1e9 / HBM_PEAK, 3)}
+            if kind == 10:
+                tf = 6.0 * N ** 4 / (ms * 1e-3) / 1e12
+                row.update({"bf16_tflop_s": round(tf, 1), "mfma_frac": round(tf / 2500.0, 3)})
+            say(json.dumps(row))
+            rows.append(row)
+        del op
+    return rows
+
+
 def copy_bandwidth(nbytes=1 << 30, reps=10):
     """Read+write bandwidth (GB/s) of a plain device-to-device copy of nbytes (larger than the
     256 MB last-level cache), timed with events on torch's current stream, where the copy runs."""
@@ -258,6 +278,8 @@ def main():
     ap.add_argument("--refine-rtol", type=float, default=3e-6, help="mixed: float64 residual tolerance")
     ap.add_argument("--inner-rtol", type=float, default=3e-6, help="mixed: float32 inner CG tolerance")
     ap.add_argument("--all-configs", action="store_true", help="time every configuration instead (one line each)")
+    ap.add_argument("--transforms", action="store_true",
+                    help="time the radix and the matrix-core DCT-II along x at 128^3, 256^3, 512^3 instead")
     ap.add_argument("--mixed-only", action="store_true",
                     help="time the headline mixed form only (for profiler runs; prints its result dict)")
     args = ap.parse_args()
@@ -270,6 +292,9 @@ def main():
 
     if args.all_configs:
         all_configs(K, KI, lambda m: print(m, flush=True))
+        return
+    if args.transforms:
+        transforms_compare(K, KI, lambda m: print(m, flush=True))
         return
     cfg = KI.WORKLOADS[args.workload]
     # the oracle's K phi at this size (tests/golden/make_oracle_reference.py), both trace forms,

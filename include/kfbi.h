@@ -213,7 +213,10 @@ enum {
   KFBI_K_ZFWD = 6, /* x += alpha d, r -= alpha (q - mean q), d = r + beta d, DST-II_z d and DCT-II_z d */
   KFBI_K_ZINV = 7, /* q = DST-III_z A + DCT-III_z B + c d, partial dot products */
   KFBI_K_YFWD = 8, /* DST-II_y A and DCT-II_y A */
-  KFBI_K_YINV = 9  /* DST-III_y A1 + DCT-III_y B2 */
+  KFBI_K_YINV = 9,  /* DST-III_y A1 + DCT-III_y B2 */
+  KFBI_K_GEMM_X = 10 /* DCT-II along x as a split-bfloat16 matrix product on the matrix cores
+                        (MIXED_FP32 contexts, N = 128, 256, 512; a measured alternative to the
+                        radix pass, not used by the evaluation) */
 };
 
 /* Measurement helper: launches one kernel of the context's MAC solver (kind: a transform
@@ -224,6 +227,14 @@ enum {
  * touched: 2 fields for a transform pass, 6 XMID, 9 ZFWD, 4 ZINV, 3 YFWD, 3 YINV). */
 kfbi_status kfbi_time_pass(kfbi_ctx* ctx, int32_t kind, int32_t axis, int32_t reps, double* avg_ms,
                            double* bytes_per_launch);
+
+/* Transform helper (for checking the transform engine): out = the one-dimensional pass `kind`
+ * (0 DCT-II, 1 DST-II, 2 DCT-III, 3 DST-III, all orthonormal, length N; 4 DST-I on indices
+ * 1..N-1 of the axis, index 0 being the box face: out 0 there; or KFBI_K_GEMM_X, the DCT-II
+ * along x on the matrix cores) of in along axis (0 x, 1 y, 2 z) for an N^3 field, layout
+ * [x][y][z], computed in the context's inner precision (float32 for MIXED_FP32): in_dev and
+ * out_dev are float64 device arrays of N^3 values (may alias). */
+kfbi_status kfbi_apply_pass(kfbi_ctx* ctx, int32_t kind, int32_t axis, const double* in_dev, double* out_dev);
 
 /* Measurement helper: live timing of one kernel (kind as above; for transform passes axis
  * 0..2 or -1 for every axis) inside the evaluations.  Calling it returns the launches and summed duration recorded since the

@@ -32,6 +32,7 @@ _lib = C.CDLL(LIB_PATH)
 
 STOKES, NAVIER = 0, 1
 FP64, MIXED_FP32 = 0, 1
+DCT2, DST2, DCT3, DST3, DST1, K_GEMM_X = 0, 1, 2, 3, 4, 10
 TRACE_AVERAGE, TRACE_INTERIOR = 0, 1
 _TRACE = {"interior": TRACE_INTERIOR, "average": TRACE_AVERAGE}
 OK, EINVAL, ENOMEM, EGEOM, ENOCONV, EDEVICE = 0, -1, -2, -3, -4, -5
@@ -90,6 +91,7 @@ _sig = {
     "kfbi_probe_adjoint": (C.c_int, [_P, _P, _P, C.POINTER(Info)]),
     "kfbi_solve_adjoint": (C.c_int, [_P, _P, _P, C.POINTER(Info)]),
     "kfbi_solve_bvp_adjoint": (C.c_int, [_P, _P, _P, _P, C.POINTER(Info)]),
+    "kfbi_apply_pass": (C.c_int, [_P, C.c_int32, C.c_int32, _P, _P]),
     "kfbi_time_pass": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_double),
                                  C.POINTER(C.c_double)]),
     "kfbi_profile_pass": (C.c_int, [_P, C.c_int32, C.c_int32, C.c_int32, C.POINTER(C.c_int64),
@@ -333,6 +335,16 @@ class Operator:
         self.last_info = info.as_dict()
         self._check(st)
         return gb, pb
+
+    def apply_pass(self, kind, axis, field):
+        """One transform pass (kfbi_apply_pass) of an N^3 field ([x][y][z], float64) along axis,
+        in the context's inner precision; returns a new float64 CUDA tensor."""
+        torch = _torch()
+        N = self.cfg.N
+        f = torch.as_tensor(field, dtype=torch.float64, device=self.device).reshape(N, N, N).contiguous()
+        out = torch.empty_like(f)
+        self._check(_lib.kfbi_apply_pass(self._h, int(kind), int(axis), _ptr(f), _ptr(out)))
+        return out
 
     def time_pass(self, kind=1, axis=1, reps=20):
         """Mean duration (ms) and algorithmic bytes of one transform-pass launch."""

@@ -15,7 +15,7 @@ SRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libkfbi.so")
 
-HIP_SOURCES = ["kernels.hip", "api.hip"]
+HIP_SOURCES = ["kernels.hip", "gemm.hip", "api.hip"]
 CPP_SOURCES = ["geometry.cpp", "surface.cpp", "assemble.cpp"]
 
 ARCH = os.environ.get("KFBI_ARCH", "gfx950")

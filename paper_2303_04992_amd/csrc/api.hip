@@ -187,6 +187,15 @@ struct MacSolver {
   int* act_live = nullptr;
   int* act_cg = nullptr;
   int rr_cap = 1;  // right-hand sides host_rr has room for
+  // hi/lo bfloat16 fragments of the DCT-II matrix for the matrix-core pass (built on first use)
+  void* gemm_cf = nullptr;
+  void ensure_gemm(std::vector<void*>& owned) {
+    if (gemm_cf) return;
+    if (sizeof(T) != 4 || !gemm_pass_supported(N))
+      throw std::invalid_argument("the matrix-core DCT-II pass needs a MIXED_FP32 context with N = 128, 256 or 512");
+    gemm_cf = dupload(gemm_dct2_fragments(N), owned, s);
+    HIPCHK(hipStreamSynchronize(s));
+  }
   template <class Q>
   Q* at(Q* p, int r) const {
     return p ? reinterpret_cast<Q*>(reinterpret_cast<uintptr_t>(p) + (uint64_t)r * (uint64_t)bt.A) : p;
@@ -313,6 +322,7 @@ struct MacSolver {
       case KFBI_K_ZINV: return 4 * f;  // A, B, d read; q written
       case KFBI_K_YFWD: return 3 * f;  // A read; A1, B2 written
       case KFBI_K_YINV: return 3 * f;  // A1, B2 read; A written
+      case KFBI_K_GEMM_X: return 2 * f;  // one field read and written
       default: return 2 * f;           // single transform pass
     }
   }
@@ -1572,13 +1582,14 @@ kfbi_status kfbi_profile_pass(kfbi_ctx* C, int32_t kind, int32_t axis, int32_t e
 }
 
 kfbi_status kfbi_time_pass(kfbi_ctx* C, int32_t kind, int32_t axis, int32_t reps, double* avg_ms, double* bytes) {
-  if (!C || !avg_ms || kind < 0 || kind > KFBI_K_YINV || axis < 0 || axis > 2 || reps <= 0) return KFBI_EINVAL;
+  if (!C || !avg_ms || kind < 0 || kind > KFBI_K_GEMM_X || axis < 0 || axis > 2 || reps <= 0) return KFBI_EINVAL;
   return guarded(C, [&] {
     hipEvent_t e0, e1;
     HIPCHK(hipEventCreate(&e0));
     HIPCHK(hipEventCreate(&e1));
     auto run = [&](auto& sv) {
       using T = std::remove_reference_t<decltype(*sv.A)>;
+      if (kind == KFBI_K_GEMM_X) sv.ensure_gemm(C->owned);
       for (T* f : {sv.A, sv.B, sv.A1, sv.B2, sv.B3, sv.r, sv.d, sv.q, sv.x})
         HIPCHK(launch_fill<T>(sv.M, f, T(1), C->s));
       HIPCHK(hipMemsetAsync(sv.scal, 0, 16 * sizeof(double), C->s));
@@ -1589,6 +1600,9 @@ kfbi_status kfbi_time_pass(kfbi_ctx* C, int32_t kind, int32_t axis, int32_t reps
           case KFBI_K_ZINV: sv.zinv(); break;
           case KFBI_K_YFWD: sv.yfwd(); break;
           case KFBI_K_YINV: sv.yinv(); break;
+          case KFBI_K_GEMM_X:
+            if constexpr (sizeof(T) == 4) HIPCHK(launch_gemm_dct2_x(sv.N, sv.A, sv.B, sv.gemm_cf, C->s));
+            break;
           default: sv.pass(kind, axis, sv.A, sv.B);
         }
       };
@@ -1608,6 +1622,30 @@ kfbi_status kfbi_time_pass(kfbi_ctx* C, int32_t kind, int32_t axis, int32_t reps
       run(C->s64);
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+  });
+}
+
+kfbi_status kfbi_apply_pass(kfbi_ctx* C, int32_t kind, int32_t axis, const double* in, double* out) {
+  if (!C || !in || !out || kind < 0 || (kind > 4 && kind != KFBI_K_GEMM_X) || axis < 0 || axis > 2)
+    return KFBI_EINVAL;
+  if (kind == KFBI_K_GEMM_X && axis != 0) return KFBI_EINVAL;
+  return guarded(C, [&] {
+    auto run = [&](auto& sv) {
+      using T = std::remove_reference_t<decltype(*sv.A)>;
+      if (kind == KFBI_K_GEMM_X) sv.ensure_gemm(C->owned);
+      HIPCHK((launch_convert<double, T>(sv.M, in, sv.A, C->s)));
+      if (kind == KFBI_K_GEMM_X) {
+        if constexpr (sizeof(T) == 4) HIPCHK(launch_gemm_dct2_x(sv.N, sv.A, sv.B, sv.gemm_cf, C->s));
+      } else {
+        HIPCHK(launch_pass<T>(sv.N, kind, axis, sv.A, sv.B, false, sv.tb, C->s));
+      }
+      HIPCHK((launch_convert<T, double>(sv.M, sv.B, out, C->s)));
+      HIPCHK(hipStreamSynchronize(C->s));
+    };
+    if (C->mixed)
+      run(C->s32);
+    else
+      run(C->s64);
   });
 }
 

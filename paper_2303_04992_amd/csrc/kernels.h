@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <vector>
 
 namespace kfbi {
 
@@ -158,5 +159,15 @@ hipError_t launch_export_u(int N, const double* u_int, double* u_ext, hipStream_
 hipError_t launch_import_u(int N, const double* u_ext, double* u_int, hipStream_t s);
 hipError_t launch_scatter_add(int64_t n, const int64_t* idx, const double* v, double* F, hipStream_t s);
 hipError_t launch_check_finite(int64_t n, const double* a, int* flag, hipStream_t s);
+// out[i] = (To) in[i]
+template <typename Ti, typename To>
+hipError_t launch_convert(int64_t n, const Ti* in, To* out, hipStream_t s);
+
+// ---- the DCT-II along x as a split-bfloat16 matrix product on the matrix cores (a measured
+// alternative to the radix pass; float32 fields, N = 128, 256, 512)
+bool gemm_pass_supported(int N);
+// the hi and lo bfloat16 A-operand fragments of the orthonormal DCT-II matrix (2 N^2 values)
+std::vector<uint16_t> gemm_dct2_fragments(int N);
+hipError_t launch_gemm_dct2_x(int N, const float* in, float* out, const void* Cf, hipStream_t s);
 
 }  // namespace kfbi

@@ -1511,6 +1511,12 @@ __global__ void k_scatter_add(int64_t n, const int64_t* __restrict__ idx, const 
   if (r < n) F[idx[r]] += v[r];
 }
 
+template <typename Ti, typename To>
+__global__ void k_convert(int64_t n, const Ti* __restrict__ in, To* __restrict__ out) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = (To)in[i];
+}
+
 __global__ void k_check_finite(int64_t n, const double* __restrict__ a, int* __restrict__ flag) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
     if (!isfinite(a[i])) *flag = 1;  // benign race: every writer stores 1
@@ -1849,6 +1855,15 @@ hipError_t launch_scatter_add(int64_t n, const int64_t* idx, const double* v, do
   hipLaunchKernelGGL(k_scatter_add, dim3(gb(n)), dim3(256), 0, s, n, idx, v, F);
   return hipGetLastError();
 }
+template <typename Ti, typename To>
+hipError_t launch_convert(int64_t n, const Ti* in, To* out, hipStream_t s) {
+  hipLaunchKernelGGL((k_convert<Ti, To>), dim3(ew_blocks(n)), dim3(256), 0, s, n, in, out);
+  return hipGetLastError();
+}
+template hipError_t launch_convert<double, float>(int64_t, const double*, float*, hipStream_t);
+template hipError_t launch_convert<float, double>(int64_t, const float*, double*, hipStream_t);
+template hipError_t launch_convert<double, double>(int64_t, const double*, double*, hipStream_t);
+
 hipError_t launch_check_finite(int64_t n, const double* a, int* flag, hipStream_t s) {
   hipLaunchKernelGGL(k_check_finite, dim3(ew_blocks(n)), dim3(256), 0, s, n, a, flag);
   return hipGetLastError();

@@ -56,8 +56,9 @@ def main():
     meta = {"workload": a.name, "N": cfg.N, "n_points": int(O.n), "n_crossings": int(O.T),
             "setup_s": t1 - t0, "cg_rtol": O.cg_rtol, "forms": list(FORMS), "workers": os.cpu_count(),
             "rows": ("sorted default_rng(7).choice(n, %d, replace=False)" % len(idx)) if a.sample else "all",
-            "inputs": {"uexact": "phi = exact velocity at the control points",
-                       "random": "phi = random_density(n), seed 2"}}
+            "inputs": {k: v for k, v in (("uexact", "phi = exact velocity at the control points"),
+                                         ("random", "phi = random_density(n), seed 2"))
+                       if k in a.inputs.split(",")}}
     out = {"idx": idx}
     for inp in a.inputs.split(","):
         phi = (KI.exact_u(cfg.solution, X[:, 0], X[:, 1], X[:, 2]) if inp == "uexact"
