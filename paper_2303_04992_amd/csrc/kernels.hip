@@ -865,24 +865,13 @@ __global__ __launch_bounds__(256) void k_zinv_cg(const T* __restrict__ A, const 
     for (int c = 0; c < 4; ++c) partials[4 * blockIdx.x + c] = t[c];
 }
 
-// y passes of the Schur matvec with two transforms per block.
-// forward: A1 = DST-II_y(A), B2 = DCT-II_y(A) (the tile of A is read twice, the second time
-// from L2); inverse: A = DST-III_y(A1) + DCT-III_y(B2)
-// The DST-II input is the DCT-II input (Makhoul order) with the samples from the second half of
-// the reordered pencil negated: one gather serves both transforms, A is read once.
 template <typename T, int N>
-__global__ __launch_bounds__(256) void k_ypair_fwd(const T* __restrict__ A, T* __restrict__ A1, T* __restrict__ B2,
-                                                  Tab<T> tb, Bat bt) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  if (rhs_skipped(bt)) return;
-  A = wb(A, bt);
-  A1 = wb(A1, bt);
-  B2 = wb(B2, bt);
-  T* lds = reinterpret_cast<T*>(smem);
+__device__ __forceinline__ void ypair_fwd_body(T* lds, const T* __restrict__ A, T* __restrict__ A1, T* __restrict__ B2,
+                                               const Tab<T>& tb, int blk) {
   using S = TileCfg<T, N, DCT2>;
   static_assert(S::R1 == TileCfg<T, N, DST2>::R1 && S::R2 == TileCfg<T, N, DST2>::R2, "one gather for both kinds");
   constexpr int W = S::W, R1 = S::R1, R2 = S::R2;
-  const TileAddr a = tile_addr<W, N>(1, blockIdx.x);
+  const TileAddr a = tile_addr<W, N>(1, blk);
   const GlobSrc<T> src{A, a.base, a.nstride};
   C2<T> zc[S::PT1][R1], zs[S::PT1][R1];
   fft_gather<T, N, DCT2>([&](int j, int n) { return pre_sample<T, N, DCT2>(src, tb, j, n); }, zc);
@@ -902,17 +891,11 @@ __global__ __launch_bounds__(256) void k_ypair_fwd(const T* __restrict__ A, T* _
 }
 
 template <typename T, int N>
-__global__ __launch_bounds__(256) void k_ypair_inv(const T* __restrict__ A1, const T* __restrict__ B2,
-                                                  T* __restrict__ A, Tab<T> tb, Bat bt) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  if (rhs_skipped(bt)) return;
-  A1 = wb(A1, bt);
-  B2 = wb(B2, bt);
-  A = wb(A, bt);
-  T* lds = reinterpret_cast<T*>(smem);
+__device__ __forceinline__ void ypair_inv_body(T* lds, const T* __restrict__ A1, const T* __restrict__ B2,
+                                               T* __restrict__ A, const Tab<T>& tb, int blk) {
   using O = OutItems<T, N, DST3>;
   constexpr int W = TileCfg<T, N, DST3>::W;
-  const TileAddr a = tile_addr<W, N>(1, blockIdx.x);
+  const TileAddr a = tile_addr<W, N>(1, blk);
   fft_tile<T, N, DST3>(lds, GlobSrc<T>{A1, a.base, a.nstride}, tb);
   C2<T> acc[O::PER_XY];
 #pragma unroll
@@ -935,6 +918,27 @@ __global__ __launch_bounds__(256) void k_ypair_inv(const T* __restrict__ A1, con
     }
   }
 }
+
+// y passes of the Schur matvec with two transforms per block.
+// forward: A1 = DST-II_y(A), B2 = DCT-II_y(A); inverse: A = DST-III_y(A1) + DCT-III_y(B2)
+// The DST-II input is the DCT-II input (Makhoul order) with the samples from the second half of
+// the reordered pencil negated: one gather serves both transforms, A is read once.
+template <typename T, int N>
+__global__ __launch_bounds__(256) void k_ypair_fwd(const T* __restrict__ A, T* __restrict__ A1, T* __restrict__ B2,
+                                                  Tab<T> tb, Bat bt) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  if (rhs_skipped(bt)) return;
+  ypair_fwd_body<T, N>(reinterpret_cast<T*>(smem), wb(A, bt), wb(A1, bt), wb(B2, bt), tb, blockIdx.x);
+}
+
+template <typename T, int N>
+__global__ __launch_bounds__(256) void k_ypair_inv(const T* __restrict__ A1, const T* __restrict__ B2,
+                                                  T* __restrict__ A, Tab<T> tb, Bat bt) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  if (rhs_skipped(bt)) return;
+  ypair_inv_body<T, N>(reinterpret_cast<T*>(smem), wb(A1, bt), wb(B2, bt), wb(A, bt), tb, blockIdx.x);
+}
+
 
 // CG coefficients after the matvec of iteration k, one block.  rpart: partial sums of r_k.r_k
 // (nr blocks); zpart: partial sums (d.q, q, d, q.q) of q = S d_k (nz blocks).  With q' = q - mean q
