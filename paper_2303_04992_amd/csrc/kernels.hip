@@ -89,6 +89,13 @@ __device__ __forceinline__ void block_sum4(double (&v)[4], double* sh) {
 
 constexpr int EW_NT = 256;  // threads per block of the elementwise and reduction kernels
 
+// Upper bound of the threads of a transform block at grid size N (TileCfg::NT): 512 from
+// N = 512 on, where a 256-thread block would hold 32 complex values per thread.
+template <int N>
+constexpr int tile_nt_max() {
+  return N >= 512 ? 512 : 256;
+}
+
 // Contiguous z tile (W pencils of N, 16-byte aligned) -> LDS rows of stride N + 1.  Every
 // load of the thread is issued before the first LDS write (vector loads, unrolled).
 template <typename T, int N, int NT>
@@ -184,7 +191,7 @@ __device__ __forceinline__ void stage_xy(T* lds, const C2<T> (&raw)[PipeCfg<T, N
 }
 
 template <typename T, int N, int KIND>
-__global__ __launch_bounds__(256) void k_pass_pipe(const T* in, T* out, int axis, int ntiles, Tab<T> tg, Bat bt) {
+__global__ __launch_bounds__(tile_nt_max<N>()) void k_pass_pipe(const T* in, T* out, int axis, int ntiles, Tab<T> tg, Bat bt) {
   extern __shared__ __align__(16) unsigned char smem[];
   if (rhs_skipped(bt)) return;
   in = wb(in, bt);
@@ -236,7 +243,7 @@ static int persistent_blocks(K kernel, int threads, size_t lds_bytes, int ntiles
 // ---------------------------------------------------------------------------------------
 // (in may equal out: a block reads its whole tile before it writes any output)
 template <typename T, int N, int KIND, bool ACC>
-__global__ __launch_bounds__(256) void k_pass(const T* in, T* out, int axis, Tab<T> tb, Bat bt) {
+__global__ __launch_bounds__(tile_nt_max<N>()) void k_pass(const T* in, T* out, int axis, Tab<T> tb, Bat bt) {
   extern __shared__ __align__(16) unsigned char smem[];
   if (rhs_skipped(bt)) return;
   in = wb(in, bt);
@@ -417,7 +424,7 @@ template <typename T, int N, int KF>
 struct XmidRegs {
   using S = TileCfg<T, N, KF>;
   static constexpr int SW = 64 / S::NJ;  // pass-2 slots per wavefront
-  static constexpr bool ok = S::R1 == S::R2 && S::NJ * S::R1 == S::NT && S::NJ * S::R2 == S::NT &&
+  static constexpr bool ok = S::R3 == 1 && S::R1 == S::R2 && S::NJ * S::R1 == S::NT && S::NJ * S::R2 == S::NT &&
                              S::NT % 64 == 0 && 64 % S::NJ == 0 && SW % 2 == 0 && S::R1 % SW == 0;
 };
 
@@ -554,7 +561,7 @@ __device__ __forceinline__ void store_xy_outputs(const T* lds, const Tab<T>& tb,
 // is restaged in LDS for the inverse.
 // ---------------------------------------------------------------------------------------
 template <typename T, int N, int KF, int KI, bool BACKSUB>
-__global__ __launch_bounds__(256) void k_xfuse(const T* __restrict__ in, T* __restrict__ fh, T* __restrict__ out,
+__global__ __launch_bounds__(tile_nt_max<N>()) void k_xfuse(const T* __restrict__ in, T* __restrict__ fh, T* __restrict__ out,
                                               int m, double mu, Tab<T> tb, Bat bt) {
   extern __shared__ __align__(16) unsigned char smem[];
   if (rhs_skipped(bt)) return;
@@ -647,7 +654,7 @@ __device__ void xmid_body(T* lds, T* field, int mc, double mu, const Tab<T>& tb)
 }
 
 template <typename T, int N>
-__global__ __launch_bounds__(256) void k_xmid(T* A0, T* A1, T* A2, double mu, Tab<T> tb, Bat bt) {
+__global__ __launch_bounds__(tile_nt_max<N>()) void k_xmid(T* A0, T* A1, T* A2, double mu, Tab<T> tb, Bat bt) {
   extern __shared__ __align__(16) unsigned char smem[];
   if (rhs_skipped(bt)) return;
   A0 = wb(A0, bt);
@@ -696,12 +703,12 @@ __device__ __forceinline__ void store_z_outputs(const T* lds, const Tab<T>& tb, 
 //             previous iteration in scal[1..3]), then the transforms of d; partial sums of r.r
 // Every thread streams its vectors once; d stays in registers for the second transform.
 template <typename T, int N, int MODE>
-__global__ __launch_bounds__(256) void k_zfwd_cg(T* __restrict__ x, T* __restrict__ r, T* __restrict__ d,
+__global__ __launch_bounds__(tile_nt_max<N>()) void k_zfwd_cg(T* __restrict__ x, T* __restrict__ r, T* __restrict__ d,
                                                 const T* __restrict__ q, T* __restrict__ A, T* __restrict__ B,
                                                 const double* __restrict__ scal, double* __restrict__ rpart,
                                                 Tab<T> tb, Bat bt) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ double red[4];
+  __shared__ double red[tile_nt_max<N>() / 64];
   if (rhs_skipped(bt)) return;
   x = wb(x, bt);
   r = wb(r, bt);
@@ -778,11 +785,11 @@ __global__ __launch_bounds__(256) void k_zfwd_cg(T* __restrict__ x, T* __restric
 
 // q = DST-III_z(A) + DCT-III_z(B) + c d; per-block partial sums of d.q, q, d, q.q
 template <typename T, int N>
-__global__ __launch_bounds__(256) void k_zinv_cg(const T* __restrict__ A, const T* __restrict__ B,
+__global__ __launch_bounds__(tile_nt_max<N>()) void k_zinv_cg(const T* __restrict__ A, const T* __restrict__ B,
                                                 T* __restrict__ q, const T* __restrict__ d, double c,
                                                 double* __restrict__ partials, Tab<T> tb, Bat bt) {
   extern __shared__ __align__(16) unsigned char smem[];
-  __shared__ double red[16];  // 4 sums x up to 4 wavefronts
+  __shared__ double red[4 * (tile_nt_max<N>() / 64)];  // 4 sums per wavefront
   if (rhs_skipped(bt)) return;
   A = wb(A, bt);
   B = wb(B, bt);
@@ -869,8 +876,8 @@ template <typename T, int N>
 __device__ __forceinline__ void ypair_fwd_body(T* lds, const T* __restrict__ A, T* __restrict__ A1, T* __restrict__ B2,
                                                const Tab<T>& tb, int blk) {
   using S = TileCfg<T, N, DCT2>;
-  static_assert(S::R1 == TileCfg<T, N, DST2>::R1 && S::R2 == TileCfg<T, N, DST2>::R2, "one gather for both kinds");
-  constexpr int W = S::W, R1 = S::R1, R2 = S::R2;
+  static_assert(S::R1 == TileCfg<T, N, DST2>::R1 && S::M == TileCfg<T, N, DST2>::M, "one gather for both kinds");
+  constexpr int W = S::W, R1 = S::R1;
   const TileAddr a = tile_addr<W, N>(1, blk);
   const GlobSrc<T> src{A, a.base, a.nstride};
   C2<T> zc[S::PT1][R1], zs[S::PT1][R1];
@@ -879,9 +886,9 @@ __device__ __forceinline__ void ypair_fwd_body(T* lds, const T* __restrict__ A, 
   for (int u = 0; u < S::PT1; ++u)
 #pragma unroll
     for (int n1 = 0; n1 < R1; ++n1) {
-      // sample R2 n1 + n2 (n2 < R2) comes from an odd source index iff R2 n1 + n2 >= N/2
-      static_assert((N / 2) % R2 == 0, "the sign of a sample depends on n1 only");
-      const bool odd = R2 * n1 >= N / 2;
+      // sample M n1 + m (m < M) comes from an odd source index iff M n1 + m >= N/2
+      static_assert((N / 2) % S::M == 0, "the sign of a sample depends on n1 only");
+      const bool odd = S::M * n1 >= N / 2;
       zs[u][n1] = odd ? C2<T>{-zc[u][n1].x, -zc[u][n1].y} : zc[u][n1];
     }
   fft_core_from<T, N, DST2>(lds, zs, tb);
@@ -924,7 +931,7 @@ __device__ __forceinline__ void ypair_inv_body(T* lds, const T* __restrict__ A1,
 // The DST-II input is the DCT-II input (Makhoul order) with the samples from the second half of
 // the reordered pencil negated: one gather serves both transforms, A is read once.
 template <typename T, int N>
-__global__ __launch_bounds__(256) void k_ypair_fwd(const T* __restrict__ A, T* __restrict__ A1, T* __restrict__ B2,
+__global__ __launch_bounds__(tile_nt_max<N>()) void k_ypair_fwd(const T* __restrict__ A, T* __restrict__ A1, T* __restrict__ B2,
                                                   Tab<T> tb, Bat bt) {
   extern __shared__ __align__(16) unsigned char smem[];
   if (rhs_skipped(bt)) return;
@@ -932,7 +939,7 @@ __global__ __launch_bounds__(256) void k_ypair_fwd(const T* __restrict__ A, T* _
 }
 
 template <typename T, int N>
-__global__ __launch_bounds__(256) void k_ypair_inv(const T* __restrict__ A1, const T* __restrict__ B2,
+__global__ __launch_bounds__(tile_nt_max<N>()) void k_ypair_inv(const T* __restrict__ A1, const T* __restrict__ B2,
                                                   T* __restrict__ A, Tab<T> tb, Bat bt) {
   extern __shared__ __align__(16) unsigned char smem[];
   if (rhs_skipped(bt)) return;
@@ -1659,8 +1666,8 @@ hipError_t launch_zinv_cg(int N, const T* A, const T* B, T* q, const T* d, doubl
     const int blocks = NN * NN / S::W;                                                                     \
     const size_t lds = S::BYTES;                                                                           \
     ensure_lds(k_zinv_cg<T, NN>, lds);                                                                     \
-    hipLaunchKernelGGL((k_zinv_cg<T, NN>), dim3(blocks, 1, bt.nb), dim3(S::NT), lds, s, A, B, q, d, c, partials, \
-                       t, bt);                                                                             \
+    hipLaunchKernelGGL((k_zinv_cg<T, NN>), dim3(blocks, 1, bt.nb), dim3(S::NT), lds, s, A, B, q, d, c,     \
+                       partials, t, bt);                                                                   \
   }
   KFBI_DISPATCH_N(N, KFBI_M)
 #undef KFBI_M

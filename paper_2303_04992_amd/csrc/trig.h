@@ -9,11 +9,13 @@
 // DCT-II of the sign-alternated pencil read backwards; DST-I is the FFT of the odd extension
 // of length 2N.
 //
-// The complex FFT of length L = R1 * R2 is done in two register passes: each thread loads
-// R1 strided samples, does an R1-point DFT in registers and applies the L-point twiddles,
-// the results are transposed through LDS (rows padded by one element so the transposed
-// reads hit distinct banks), and each thread does an R2-point DFT in registers.  Small
-// DFTs are unrolled radix-4/2 butterflies with literal twiddles.
+// The complex FFT of length L = R1 * M is done in register passes: each thread loads R1
+// strided samples, does an R1-point DFT in registers and applies the L-point twiddles, the
+// results are transposed through LDS (rows padded so the transposed reads hit distinct
+// banks), and the M-point DFTs follow: one register pass (M = R2), or, for L = 512 at N = 512,
+// two (M = R2 * R3 = 8 * 8, with the M-point twiddles between them and a second transpose),
+// which keeps eight samples per task so that 512 threads hold a tile with 16 complex values
+// each.  Small DFTs are unrolled radix-4/2 butterflies with literal twiddles.
 //
 // A workgroup owns a tile of W real pencils (W*sizeof(T) = 128 bytes, so every row of the
 // tile along the contiguous z axis is one 128-byte segment), stored in LDS as rows of length
@@ -55,22 +57,33 @@ struct TileCfg {
   static constexpr int RS = N + 1;                                                  // row stride
   static constexpr int L = (KIND == DST1) ? 2 * N : N;                              // FFT length
   static constexpr int NJ = W / 2;                                                  // complex jobs
-  static constexpr int R1 = 1 << ((ilog2(L) + 1) / 2);                              // first radix
-  static constexpr int R2 = L / R1;                                                 // second radix
+  static constexpr bool THREE = N >= 512 && L == 512;                                // three passes
+  static constexpr int R1 = THREE ? 8 : 1 << ((ilog2(L) + 1) / 2);                  // first radix
+  static constexpr int M = L / R1;                                  // length of the second stage
+  static constexpr int R2 = THREE ? 8 : M;                                          // second radix
+  static constexpr int R3 = M / R2;                                        // third radix (or 1)
 #ifndef KFBI_LDS_PAD
-#define KFBI_LDS_PAD 1, 2, 2
+#define KFBI_LDS_PAD 1, 1, 1
 #endif
-  static constexpr int PAD[3] = {KFBI_LDS_PAD};  // row, transpose-job and spectrum-job padding
-  static constexpr int P2 = R2 + PAD[0];                                             // padded row
+  // Row, transpose-job and spectrum-job padding.  LDS serves 8-byte accesses 16 lanes at a time
+  // over 32 four-byte banks, and the 16 lanes of a group are the NJ = 16 jobs of a tile at the
+  // same position (8 jobs of 16 bytes in float64): odd job strides put them in distinct banks.
+  static constexpr int PAD[3] = {KFBI_LDS_PAD};
+  static constexpr int P2 = M + PAD[0];                                              // padded row
   static constexpr int YS = R1 * P2 + PAD[1];                // job stride of the transpose buffer
+  static constexpr int P3 = R3 + 1;                          // padded row of the second transpose
+  static constexpr int YS3 = R1 * R2 * P3 + PAD[1];          // its job stride
   static constexpr int ZS = L + PAD[2];                      // job stride of the spectra
-  static constexpr int NT = (NJ * R2 > 256) ? 256 : (NJ * R2 > 64) ? NJ * R2 : 64;  // threads
-  static constexpr int PT1 = (NJ * R2 + NT - 1) / NT;  // pass-1 tasks per thread
+  static constexpr int NT_CAP = N >= 512 ? 512 : 256;
+  static constexpr int NT = (NJ * M > NT_CAP) ? NT_CAP : (NJ * M > 64) ? NJ * M : 64;  // threads
+  static constexpr int PT1 = (NJ * M + NT - 1) / NT;  // pass-1 tasks per thread
   static constexpr int REALS_TILE = W * RS;
   static constexpr int REALS_Y = NJ * YS * 2;
+  static constexpr int REALS_Y3 = THREE ? NJ * YS3 * 2 : 0;
   static constexpr int REALS_Z = NJ * ZS * 2;
   static constexpr int M1 = REALS_TILE > REALS_Y ? REALS_TILE : REALS_Y;
-  static constexpr int REALS = M1 > REALS_Z ? M1 : REALS_Z;
+  static constexpr int M2 = M1 > REALS_Y3 ? M1 : REALS_Y3;
+  static constexpr int REALS = M2 > REALS_Z ? M2 : REALS_Z;
   static constexpr size_t BYTES = (size_t)REALS * sizeof(T);
 };
 
@@ -213,20 +226,20 @@ __device__ __forceinline__ void fft_tile(T* lds, const Src& src, const Tab<T>& t
   fft_core<T, N, KIND>(lds, [&](int j, int n) { return pre_sample<T, N, KIND>(src, tb, j, n); }, tb);
 }
 
-// Pass-1 samples of the thread: z[u][n1] = sample(j, R2 n1 + n2) for its task u = (j, n2).
+// Pass-1 samples of the thread: z[u][n1] = sample(j, M n1 + m) for its task u = (j, m).
 template <typename T, int N, int KIND, class Sampler>
 __device__ __forceinline__ void fft_gather(Sampler&& sample,
                                            C2<T> (&z)[TileCfg<T, N, KIND>::PT1][TileCfg<T, N, KIND>::R1]) {
   using S = TileCfg<T, N, KIND>;
-  constexpr int NJ = S::NJ, R1 = S::R1, R2 = S::R2, NT = S::NT, TASKS = NJ * R2;
+  constexpr int NJ = S::NJ, R1 = S::R1, M = S::M, NT = S::NT, TASKS = NJ * M;
   const int tid = threadIdx.x;
 #pragma unroll
   for (int u = 0; u < S::PT1; ++u) {
     const int task = tid + u * NT;
     if ((TASKS % NT == 0 || task < TASKS) && tid < NT) {
-      const int j = task % NJ, n2 = task / NJ;
+      const int j = task % NJ, m = task / NJ;
 #pragma unroll
-      for (int n1 = 0; n1 < R1; ++n1) z[u][n1] = sample(j, R2 * n1 + n2);
+      for (int n1 = 0; n1 < R1; ++n1) z[u][n1] = sample(j, M * n1 + m);
     }
   }
 }
@@ -244,7 +257,7 @@ __device__ void fft_core(T* lds, Sampler&& sample, const Tab<T>& tb) {
   fft_core_from<T, N, KIND>(lds, z, tb);
 }
 
-// Pass 1 of one task (j, n2): R1-point DFT of its samples and the L-point twiddles
+// Pass 1 of one task (j, n2 = m): R1-point DFT of its samples and the L-point twiddles
 template <typename T, int N, int KIND>
 __device__ __forceinline__ void fft_pass1_dft(int n2, C2<T> (&z)[TileCfg<T, N, KIND>::R1], const Tab<T>& tb) {
   using S = TileCfg<T, N, KIND>;
@@ -266,7 +279,7 @@ __device__ __forceinline__ void fft_pass1_store(C2<T>* cb, const C2<T> (&z)[Tile
 #pragma unroll
   for (int k1 = 0; k1 < S::R1; ++k1) cb[j * S::YS + k1 * S::P2 + n2] = z[k1];
 }
-// Pass 2 of one task (j, k1): z[k2] = spectrum value k1 + R1 k2 of job j
+// Pass 2 of one task (j, k1) of a two-pass FFT: z[k2] = spectrum value k1 + R1 k2 of job j
 template <typename T, int N, int KIND>
 __device__ __forceinline__ void fft_pass2_dft(const C2<T>* cb, C2<T> (&z)[TileCfg<T, N, KIND>::R2], int j, int k1) {
   using S = TileCfg<T, N, KIND>;
@@ -288,12 +301,12 @@ template <typename T, int N, int KIND>
 __device__ void fft_core_from(T* lds, C2<T> (&z)[TileCfg<T, N, KIND>::PT1][TileCfg<T, N, KIND>::R1],
                               const Tab<T>& tb) {
   using S = TileCfg<T, N, KIND>;
-  constexpr int NJ = S::NJ, R1 = S::R1, R2 = S::R2, NT = S::NT;
+  constexpr int NJ = S::NJ, R1 = S::R1, R2 = S::R2, R3 = S::R3, M = S::M, NT = S::NT;
   C2<T>* cb = reinterpret_cast<C2<T>*>(lds);
   const int tid = threadIdx.x;
-  // ---------------- pass 1: R1-point DFTs over stride-R2 samples, twiddle, transpose
+  // ---------------- pass 1: R1-point DFTs over stride-M samples, twiddle, transpose
   {
-    constexpr int TASKS = NJ * R2;
+    constexpr int TASKS = NJ * M;
     constexpr int PT = S::PT1;
 #pragma unroll
     for (int u = 0; u < PT; ++u) {
@@ -307,6 +320,72 @@ __device__ void fft_core_from(T* lds, C2<T> (&z)[TileCfg<T, N, KIND>::PT1][TileC
       if ((TASKS % NT == 0 || task < TASKS) && tid < NT) fft_pass1_store<T, N, KIND>(cb, z[u], task % NJ, task / NJ);
     }
     __syncthreads();
+  }
+  if constexpr (R3 > 1) {
+    // ---------------- three passes: the M-point DFTs of Y[k1][m] (m = R3 m2 + m3) as R2-point
+    // DFTs over m2 with the M-point twiddles W_M^(m3 k2), a transpose, and R3-point DFTs over
+    // m3; spectrum value k1 + R1 (k2 + R2 k3) in natural order
+    constexpr bool INV = (KIND == DCT3 || KIND == DST3);
+    const C2<T>* tw = (S::L == N) ? tb.tw : tb.tw2;
+    {
+      constexpr int TASKS = NJ * R1 * R3;
+      constexpr int PT = (TASKS + NT - 1) / NT;
+      C2<T> zb[PT][R2];
+#pragma unroll
+      for (int u = 0; u < PT; ++u) {
+        const int task = tid + u * NT;
+        if ((TASKS % NT == 0 || task < TASKS) && tid < NT) {
+          const int j = task % NJ, rest = task / NJ, m3 = rest % R3, k1 = rest / R3;
+#pragma unroll
+          for (int m2 = 0; m2 < R2; ++m2) zb[u][m2] = cb[j * S::YS + k1 * S::P2 + R3 * m2 + m3];
+          dftR<T, R2, INV>(zb[u]);
+#pragma unroll
+          for (int k2 = 1; k2 < R2; ++k2) {
+            C2<T> w = tw[(S::L / M) * m3 * k2];
+            if (INV) w.y = -w.y;
+            zb[u][k2] = cmul(zb[u][k2], w);
+          }
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < PT; ++u) {
+        const int task = tid + u * NT;
+        if ((TASKS % NT == 0 || task < TASKS) && tid < NT) {
+          const int j = task % NJ, rest = task / NJ, m3 = rest % R3, k1 = rest / R3;
+#pragma unroll
+          for (int k2 = 0; k2 < R2; ++k2) cb[j * S::YS3 + (k1 * R2 + k2) * S::P3 + m3] = zb[u][k2];
+        }
+      }
+      __syncthreads();
+    }
+    {
+      constexpr int TASKS = NJ * R1 * R2;
+      constexpr int PT = (TASKS + NT - 1) / NT;
+      C2<T> zc[PT][R3];
+#pragma unroll
+      for (int u = 0; u < PT; ++u) {
+        const int task = tid + u * NT;
+        if ((TASKS % NT == 0 || task < TASKS) && tid < NT) {
+          const int j = task % NJ, rest = task / NJ, k2 = rest % R2, k1 = rest / R2;
+#pragma unroll
+          for (int m3 = 0; m3 < R3; ++m3) zc[u][m3] = cb[j * S::YS3 + (k1 * R2 + k2) * S::P3 + m3];
+          dftR<T, R3, INV>(zc[u]);
+        }
+      }
+      __syncthreads();
+#pragma unroll
+      for (int u = 0; u < PT; ++u) {
+        const int task = tid + u * NT;
+        if ((TASKS % NT == 0 || task < TASKS) && tid < NT) {
+          const int j = task % NJ, rest = task / NJ, k2 = rest % R2, k1 = rest / R2;
+#pragma unroll
+          for (int k3 = 0; k3 < R3; ++k3) cb[j * S::ZS + k1 + R1 * (k2 + R2 * k3)] = zc[u][k3];
+        }
+      }
+      __syncthreads();
+    }
+    return;
   }
   // ---------------- pass 2: R2-point DFTs, natural-order output
   {

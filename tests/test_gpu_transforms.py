@@ -93,3 +93,24 @@ def test_matrix_core_pass_needs_a_float32_context(K):
     with pytest.raises(K.KfbiError) as e:
         op.apply_pass(K.K_GEMM_X, 0, np.zeros((128,) * 3))
     assert e.value.status == K.EINVAL
+
+
+def test_passes_at_512(K):
+    """At N = 512 the length-512 transforms take three radix-8 passes in 512-thread blocks and the
+    length-1024 DST-I two radix-32 passes; both precisions against the definitions, along the
+    contiguous axis (tile staged in LDS), the strided axis read directly and the persistent
+    pipelined path (inverse kinds along x and y)."""
+    N = 512
+    f = np.random.default_rng(23).standard_normal((N, N, N))
+    cases = [(0, 2), (1, 0), (2, 1), (3, 2), (3, 0), (4, 1)]
+    refs = {c: _reference(c[0], f, c[1]) for c in cases}
+    for prec, tol in ((K.FP64, 1e-13), (K.MIXED_FP32, 1e-6)):
+        op = K.Operator(KI.WORKLOADS["sphere32"].with_N(N), prec)
+        for kind, axis in cases:
+            _say(f"[transforms N=512 prec={prec}] kind {kind} axis {axis}")
+            g = op.apply_pass(kind, axis, f).cpu().numpy()
+            l2, mx = _errs(g, refs[(kind, axis)])
+            _say(f"    rel l2 {l2:.2e} rel max {mx:.2e}")
+            assert l2 < tol and mx < tol, (prec, kind, axis, l2, mx)
+            del g
+        del op
