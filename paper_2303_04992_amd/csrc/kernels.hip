@@ -161,6 +161,79 @@ __device__ __forceinline__ Tab<T> tables_to_lds(unsigned char* smem, const Tab<T
   return t;
 }
 
+// The same tables (layout of PipeCfg) for one-tile kernels, in two steps: request() reads
+// the entries into registers before the kernel requests its samples, publish() writes them to
+// LDS once they (and not the samples, requested later) have arrived.  Used only where the
+// extra LDS keeps the resident blocks per compute unit (of the sizes here, float32 at N = 256).
+template <typename T, int N, int KIND>
+struct TabStage {
+  using S = TileCfg<T, N, KIND>;
+  using P = PipeCfg<T, N, KIND>;
+  static constexpr bool ON = sizeof(T) == 4 && P::BYTES <= 163840 && 163840 / P::BYTES >= 163840 / S::BYTES;
+  static constexpr size_t BYTES = ON ? P::BYTES : S::BYTES;
+  static constexpr int NT = S::NT, PL = (S::L + NT - 1) / NT, PN = (N + NT - 1) / NT;
+  C2<T> rtw[ON ? PL : 1], rmk[ON ? PN : 1];
+  T rsc[ON ? PN : 1];
+  __device__ __forceinline__ void request(const Tab<T>& g) {
+    if constexpr (ON) {
+      const C2<T>* gtw = (S::L == N) ? g.tw : g.tw2;
+      const T* gsc = (KIND == DCT3 || KIND == DST3) ? g.isc : g.sc;
+#pragma unroll
+      for (int u = 0; u < PL; ++u) {
+        const int i = threadIdx.x + u * NT;
+        if (i < S::L) rtw[u] = gtw[i];
+      }
+#pragma unroll
+      for (int u = 0; u < PN; ++u) {
+        const int i = threadIdx.x + u * NT;
+        if (i < N) {
+          rmk[u] = g.mk[i];
+          rsc[u] = gsc[i];
+        }
+      }
+    }
+  }
+  // writes the entries to LDS (the caller synchronises the block before they are read) and
+  // returns the tables to read: the LDS copies, or g itself when the stage is off
+  __device__ __forceinline__ Tab<T> publish(unsigned char* smem, const Tab<T>& g) const {
+    if constexpr (ON) {
+      C2<T>* ltw = reinterpret_cast<C2<T>*>(smem + P::TAB_OFF);
+      C2<T>* lmk = ltw + S::L;
+      T* lsc = reinterpret_cast<T*>(lmk + N);
+#pragma unroll
+      for (int u = 0; u < PL; ++u) {
+        const int i = threadIdx.x + u * NT;
+        if (i < S::L) ltw[i] = rtw[u];
+      }
+#pragma unroll
+      for (int u = 0; u < PN; ++u) {
+        const int i = threadIdx.x + u * NT;
+        if (i < N) {
+          lmk[i] = rmk[u];
+          lsc[i] = rsc[u];
+        }
+      }
+    }
+    return view(smem, g);
+  }
+  __device__ __forceinline__ static Tab<T> view(unsigned char* smem, const Tab<T>& g) {
+    if constexpr (ON) {
+      C2<T>* ltw = reinterpret_cast<C2<T>*>(smem + P::TAB_OFF);
+      C2<T>* lmk = ltw + S::L;
+      T* lsc = reinterpret_cast<T*>(lmk + N);
+      Tab<T> t = g;
+      t.tw = ltw;
+      t.tw2 = ltw;
+      t.mk = lmk;
+      t.sc = lsc;
+      t.isc = lsc;
+      return t;
+    } else {
+      return g;
+    }
+  }
+};
+
 // raw element pairs (pencils 2j, 2j+1 at sample n) of an x or y tile: pair e -> (n, j) = (e / NJ, e % NJ)
 template <typename T, int N, int KIND>
 __device__ __forceinline__ void fetch_xy(const T* g, const TileAddr& a, C2<T> (&raw)[PipeCfg<T, N, KIND>::PER]) {
@@ -428,14 +501,28 @@ struct XmidRegs {
                              S::NT % 64 == 0 && 64 % S::NJ == 0 && SW % 2 == 0 && S::R1 % SW == 0;
 };
 
+// LDS of the register-path x pass: the transform work area, then (float32) the tables the pass
+// reads between its transforms: pass-1 twiddles tw[n2 k1] (n2, k1 < R1), mk and the x
+// eigenvalues of the block's component, copied once per block so that no table read waits
+// behind the tile's outstanding sample loads.  Float64 blocks keep the tables in global memory
+// (their larger entries would cost a resident block per compute unit).
+template <typename T, int N>
+struct XmidLds {
+  using S = TileCfg<T, N, DCT2>;
+  static constexpr bool TABLES = XmidRegs<T, N, DCT2>::ok && XmidRegs<T, N, DST2>::ok && sizeof(T) == 4;
+  static constexpr int NTW = (S::R1 - 1) * (S::R1 - 1) + 1;
+  static constexpr size_t TAB_OFF = (S::BYTES + 15) / 16 * 16;
+  static constexpr size_t BYTES = TABLES ? TAB_OFF + (size_t)(NTW + N) * sizeof(C2<T>) + (size_t)N * sizeof(T) : S::BYTES;
+};
+
 template <typename T, int N, int KF, int KI>
 __device__ void xmid_tile_regs(T* lds, T* field, int tile, int mc, double mu, const Tab<T>& tb,
-                               C2<T> (&zs)[TileCfg<T, N, KF>::PT1][TileCfg<T, N, KF>::R1]) {
+                               C2<T> (&zs)[TileCfg<T, N, KF>::PT1][TileCfg<T, N, KF>::R1], const T* lxt, T ly,
+                               const T (&lz)[2]) {
   using S = TileCfg<T, N, KF>;
   constexpr int W = S::W, NJ = S::NJ, R1 = S::R1, R2 = S::R2, SW = XmidRegs<T, N, KF>::SW;
   static_assert(XmidRegs<T, N, KF>::ok, "register path needs R1 == R2 and one task per thread");
   const TileAddr a = tile_addr<W, N>(0, tile);
-  const int yi = tile / (N / W), z0 = (tile % (N / W)) * W;
   C2<T>* cb = reinterpret_cast<C2<T>*>(lds);
   const int tid = threadIdx.x, j = tid % NJ;
   // forward: pass 1 of task (j, tid / NJ), then pass 2 of task (j, k1) in the paired slot order
@@ -463,18 +550,13 @@ __device__ void xmid_tile_regs(T* lds, T* field, int tile, int mc, double mu, co
     for (int k2 = 0; k2 < R2; ++k2)
       if (zero_k1) zr[k2] = z[(R2 - k2) & (R2 - 1)];
   }
-  // y and z eigenvalues of the thread's two pencils
-  const T ly = (mc == 1) ? tb.sg2[yi] : tb.sg2s[yi];
-  T lz[2];
-#pragma unroll
-  for (int w = 0; w < 2; ++w) lz[w] = (mc == 2) ? tb.sg2[z0 + 2 * j + w] : tb.sg2s[z0 + 2 * j + w];
   const T mu2 = T(2 * mu);  // the factor 1/2 of V is folded into the weight denominators
   T ya[R2], yb[R2];
 #pragma unroll
   for (int k2 = 0; k2 < R2; ++k2) {
     const int k = k1 + R1 * k2;
     const int mode = (KF == DST2) ? N - 1 - k : k;
-    const T lx = (mc == 0) ? tb.sg2[mode] : tb.sg2s[mode];
+    const T lx = lxt[mode];
     T om[2];
 #pragma unroll
     for (int w = 0; w < 2; ++w) {
@@ -646,11 +728,64 @@ __device__ void xmid_body(T* lds, T* field, int mc, double mu, const Tab<T>& tb)
   const TileAddr a = tile_addr<S::W, N>(0, tile);
   const GlobSrc<T> src{field, a.base, a.nstride};
   C2<T> zs[S::PT1][S::R1];
-  fft_gather<T, N, KF>([&](int j, int n) { return pre_sample<T, N, KF>(src, tb, j, n); }, zs);
-  if constexpr (XmidRegs<T, N, KF>::ok)
-    xmid_tile_regs<T, N, KF, KI>(lds, field, tile, mc, mu, tb, zs);
-  else
+  if constexpr (XmidRegs<T, N, KF>::ok) {
+    using X = XmidLds<T, N>;
+    // y and z eigenvalues of the thread's two pencils, the x eigenvalues of the component
+    const int yi = tile / (N / S::W), z0 = (tile % (N / S::W)) * S::W, j = threadIdx.x % S::NJ;
+    const T ly = (mc == 1) ? tb.sg2[yi] : tb.sg2s[yi];
+    T lz[2];
+#pragma unroll
+    for (int w = 0; w < 2; ++w) lz[w] = (mc == 2) ? tb.sg2[z0 + 2 * j + w] : tb.sg2s[z0 + 2 * j + w];
+    const T* gx = (mc == 0) ? tb.sg2 : tb.sg2s;
+    if constexpr (X::TABLES) {
+      // table entries requested before the samples, written to LDS once they (not the samples) are in
+      constexpr int NT = S::NT, PT = (X::NTW + NT - 1) / NT, PN = (N + NT - 1) / NT;
+      unsigned char* base = reinterpret_cast<unsigned char*>(lds) + X::TAB_OFF;
+      C2<T>* ltw = reinterpret_cast<C2<T>*>(base);
+      C2<T>* lmk = ltw + X::NTW;
+      T* lsg = reinterpret_cast<T*>(lmk + N);
+      C2<T> rtw[PT], rmk[PN];
+      T rsg[PN];
+#pragma unroll
+      for (int u = 0; u < PT; ++u) {
+        const int i = threadIdx.x + u * NT;
+        if (i < X::NTW) rtw[u] = tb.tw[i];
+      }
+#pragma unroll
+      for (int u = 0; u < PN; ++u) {
+        const int i = threadIdx.x + u * NT;
+        if (i < N) {
+          rmk[u] = tb.mk[i];
+          rsg[u] = gx[i];
+        }
+      }
+      fft_gather<T, N, KF>([&](int jj, int n) { return pre_sample<T, N, KF>(src, tb, jj, n); }, zs);
+#pragma unroll
+      for (int u = 0; u < PT; ++u) {
+        const int i = threadIdx.x + u * NT;
+        if (i < X::NTW) ltw[i] = rtw[u];
+      }
+#pragma unroll
+      for (int u = 0; u < PN; ++u) {
+        const int i = threadIdx.x + u * NT;
+        if (i < N) {
+          lmk[i] = rmk[u];
+          lsg[i] = rsg[u];
+        }
+      }
+      __syncthreads();
+      Tab<T> tl = tb;
+      tl.tw = ltw;
+      tl.mk = lmk;
+      xmid_tile_regs<T, N, KF, KI>(lds, field, tile, mc, mu, tl, zs, lsg, ly, lz);
+    } else {
+      fft_gather<T, N, KF>([&](int jj, int n) { return pre_sample<T, N, KF>(src, tb, jj, n); }, zs);
+      xmid_tile_regs<T, N, KF, KI>(lds, field, tile, mc, mu, tb, zs, gx, ly, lz);
+    }
+  } else {
+    fft_gather<T, N, KF>([&](int j, int n) { return pre_sample<T, N, KF>(src, tb, j, n); }, zs);
     xmid_tile<T, N, KF, KI>(lds, field, tile, mc, mu, tb, zs);
+  }
 }
 
 template <typename T, int N>
@@ -706,7 +841,7 @@ template <typename T, int N, int MODE>
 __global__ __launch_bounds__(tile_nt_max<N>()) void k_zfwd_cg(T* __restrict__ x, T* __restrict__ r, T* __restrict__ d,
                                                 const T* __restrict__ q, T* __restrict__ A, T* __restrict__ B,
                                                 const double* __restrict__ scal, double* __restrict__ rpart,
-                                                Tab<T> tb, Bat bt) {
+                                                Tab<T> tg, Bat bt) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red[tile_nt_max<N>() / 64];
   if (rhs_skipped(bt)) return;
@@ -723,6 +858,8 @@ __global__ __launch_bounds__(tile_nt_max<N>()) void k_zfwd_cg(T* __restrict__ x,
   constexpr int W = S::W, RS = N + 1, NT = S::NT, VEC = V16<T>::n;
   constexpr int NV = W * N / VEC, PER = (NV + NT - 1) / NT;
   const TileAddr a = tile_addr<W, N>(2, blockIdx.x);
+  TabStage<T, N, DST2> ts;  // DST-II and DCT-II read the same tables
+  ts.request(tg);
   const V16<T>* rv = reinterpret_cast<const V16<T>*>(r + a.base);
   V16<T> v[PER];
   double rr = 0;
@@ -758,6 +895,7 @@ __global__ __launch_bounds__(tile_nt_max<N>()) void k_zfwd_cg(T* __restrict__ x,
       }
     }
   }
+  const Tab<T> tb = ts.publish(smem, tg);  // read after the first stage's barrier
   if constexpr (MODE != ZF_PLAIN) {
     const double t = block_sum(rr, red);
     if (threadIdx.x == 0) rpart[blockIdx.x] = t;
@@ -787,7 +925,7 @@ __global__ __launch_bounds__(tile_nt_max<N>()) void k_zfwd_cg(T* __restrict__ x,
 template <typename T, int N>
 __global__ __launch_bounds__(tile_nt_max<N>()) void k_zinv_cg(const T* __restrict__ A, const T* __restrict__ B,
                                                 T* __restrict__ q, const T* __restrict__ d, double c,
-                                                double* __restrict__ partials, Tab<T> tb, Bat bt) {
+                                                double* __restrict__ partials, Tab<T> tg, Bat bt) {
   extern __shared__ __align__(16) unsigned char smem[];
   __shared__ double red[4 * (tile_nt_max<N>() / 64)];  // 4 sums per wavefront
   if (rhs_skipped(bt)) return;
@@ -801,15 +939,45 @@ __global__ __launch_bounds__(tile_nt_max<N>()) void k_zinv_cg(const T* __restric
   using O = OutItems<T, N, DCT3>;
   constexpr int W = S::W, NT = S::NT, VEC = V16<T>::n, RV = N / VEC;
   const TileAddr a = tile_addr<W, N>(2, blockIdx.x);
-  load_tile_z<T, N, NT>(lds, A + a.base);
-  // the B tile is requested before the first transform and staged in LDS after it
+  // tables, then the A tile, then the B tile (staged in LDS after the first transform) are
+  // requested; the tables and the A tile go to LDS as they arrive
+  using TS = TabStage<T, N, DST3>;
+  TS ts;
+  ts.request(tg);
   constexpr int NV = W * N / VEC, PV = (NV + NT - 1) / NT;
   V16<T> vb[PV];
+  if constexpr (TS::ON) {
+    V16<T> va[PV];
 #pragma unroll
-  for (int u = 0; u < PV; ++u) {
-    const int e = threadIdx.x + u * NT;
-    if (NV % NT == 0 || e < NV) vb[u] = reinterpret_cast<const V16<T>*>(B + a.base)[e];
+    for (int u = 0; u < PV; ++u) {
+      const int e = threadIdx.x + u * NT;
+      if (NV % NT == 0 || e < NV) va[u] = reinterpret_cast<const V16<T>*>(A + a.base)[e];
+    }
+#pragma unroll
+    for (int u = 0; u < PV; ++u) {
+      const int e = threadIdx.x + u * NT;
+      if (NV % NT == 0 || e < NV) vb[u] = reinterpret_cast<const V16<T>*>(B + a.base)[e];
+    }
+    (void)ts.publish(smem, tg);
+#pragma unroll
+    for (int u = 0; u < PV; ++u) {
+      const int e = threadIdx.x + u * NT;
+      if (NV % NT == 0 || e < NV) {
+        const int p = (e * VEC) / N, n = (e * VEC) - p * N;
+#pragma unroll
+        for (int qq = 0; qq < VEC; ++qq) lds[p * (N + 1) + n + qq] = va[u].a[qq];
+      }
+    }
+    __syncthreads();
+  } else {  // float64: the A tile is staged before the B tile is requested (register budget)
+    load_tile_z<T, N, NT>(lds, A + a.base);
+#pragma unroll
+    for (int u = 0; u < PV; ++u) {
+      const int e = threadIdx.x + u * NT;
+      if (NV % NT == 0 || e < NV) vb[u] = reinterpret_cast<const V16<T>*>(B + a.base)[e];
+    }
   }
+  const Tab<T> tb = TS::view(smem, tg);
   fft_tile<T, N, DST3>(lds, LdsSrc<T, N>{lds}, tb);
   V16<T> acc[2 * O::PER_Z];
 #pragma unroll
@@ -874,14 +1042,18 @@ __global__ __launch_bounds__(tile_nt_max<N>()) void k_zinv_cg(const T* __restric
 
 template <typename T, int N>
 __device__ __forceinline__ void ypair_fwd_body(T* lds, const T* __restrict__ A, T* __restrict__ A1, T* __restrict__ B2,
-                                               const Tab<T>& tb, int blk) {
+                                               const Tab<T>& tg, int blk) {
   using S = TileCfg<T, N, DCT2>;
   static_assert(S::R1 == TileCfg<T, N, DST2>::R1 && S::M == TileCfg<T, N, DST2>::M, "one gather for both kinds");
   constexpr int W = S::W, R1 = S::R1;
   const TileAddr a = tile_addr<W, N>(1, blk);
   const GlobSrc<T> src{A, a.base, a.nstride};
+  TabStage<T, N, DCT2> ts;  // DCT-II and DST-II read the same tables
+  ts.request(tg);
   C2<T> zc[S::PT1][R1], zs[S::PT1][R1];
-  fft_gather<T, N, DCT2>([&](int j, int n) { return pre_sample<T, N, DCT2>(src, tb, j, n); }, zc);
+  fft_gather<T, N, DCT2>([&](int j, int n) { return pre_sample<T, N, DCT2>(src, tg, j, n); }, zc);
+  const Tab<T> tb = ts.publish(reinterpret_cast<unsigned char*>(lds), tg);
+  if constexpr (TabStage<T, N, DCT2>::ON) __syncthreads();
 #pragma unroll
   for (int u = 0; u < S::PT1; ++u)
 #pragma unroll
@@ -946,6 +1118,60 @@ __global__ __launch_bounds__(tile_nt_max<N>()) void k_ypair_inv(const T* __restr
   ypair_inv_body<T, N>(reinterpret_cast<T*>(smem), wb(A1, bt), wb(B2, bt), wb(A, bt), tb, blockIdx.x);
 }
 
+
+// Persistent, pipelined form of the inverse y pair (as k_pass_pipe): per tile, the staged A1
+// rows are transformed while the B2 rows of the same tile arrive in registers, and the staged
+// B2 rows while the A1 rows of the block's next tile arrive.  The two inverse kinds share their
+// tables (twiddles, mk, 1/s_k), which live in LDS.
+template <typename T, int N>
+__global__ __launch_bounds__(tile_nt_max<N>()) void k_ypair_inv_pipe(const T* __restrict__ A1, const T* __restrict__ B2,
+                                                       T* __restrict__ A, int ntiles, Tab<T> tg, Bat bt) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  if (rhs_skipped(bt)) return;
+  A1 = wb(A1, bt);
+  B2 = wb(B2, bt);
+  A = wb(A, bt);
+  T* lds = reinterpret_cast<T*>(smem);
+  using O = OutItems<T, N, DST3>;
+  constexpr int W = TileCfg<T, N, DST3>::W;
+  static_assert(PipeCfg<T, N, DST3>::PER == PipeCfg<T, N, DCT3>::PER, "one prefetch buffer for both kinds");
+  const Tab<T> tb = tables_to_lds<T, N, DST3>(smem, tg);
+  C2<T> raw[PipeCfg<T, N, DST3>::PER];
+  int tile = blockIdx.x;
+  if (tile < ntiles) fetch_xy<T, N, DST3>(A1, tile_addr<W, N>(1, tile), raw);
+  for (; tile < ntiles; tile += gridDim.x) {
+    const TileAddr a = tile_addr<W, N>(1, tile);
+    __syncthreads();  // the previous tile's outputs have been read from LDS
+    stage_xy<T, N, DST3>(lds, raw);
+    __syncthreads();
+    fetch_xy<T, N, DCT3>(B2, a, raw);
+    fft_tile<T, N, DST3>(lds, LdsSrc<T, N>{lds}, tb);
+    C2<T> acc[O::PER_XY];
+#pragma unroll
+    for (int u = 0; u < O::PER_XY; ++u) {
+      int j, k;
+      if (O::xy(u, j, k)) post_pair<T, N, DST3>(lds, tb, j, k, acc[u].x, acc[u].y);
+    }
+    __syncthreads();
+    stage_xy<T, N, DCT3>(lds, raw);
+    __syncthreads();
+    if (tile + (int)gridDim.x < ntiles) fetch_xy<T, N, DST3>(A1, tile_addr<W, N>(1, tile + gridDim.x), raw);
+    fft_tile<T, N, DCT3>(lds, LdsSrc<T, N>{lds}, tb);
+    C2<T>* o = reinterpret_cast<C2<T>*>(A + a.base);
+    const long ns = a.nstride / 2;
+#pragma unroll
+    for (int u = 0; u < O::PER_XY; ++u) {
+      int j, k;
+      if (O::xy(u, j, k)) {
+        C2<T> v;
+        post_pair<T, N, DCT3>(lds, tb, j, k, v.x, v.y);
+        v.x += acc[u].x;
+        v.y += acc[u].y;
+        o[k * ns + j] = v;
+      }
+    }
+  }
+}
 
 // CG coefficients after the matvec of iteration k, one block.  rpart: partial sums of r_k.r_k
 // (nr blocks); zpart: partial sums (d.q, q, d, q.q) of q = S d_k (nz blocks).  With q' = q - mean q
@@ -1616,7 +1842,7 @@ hipError_t launch_xmid(int N, T* A0, T* A1, T* A2, double mu, const DevTables<T>
   {                                                                                                             \
     using S = TileCfg<T, NN, DCT2>;                                                                             \
     const int blocks = NN * NN / S::W;                                                                          \
-    const size_t lds = S::BYTES;                                                                                \
+    const size_t lds = XmidLds<T, NN>::BYTES;                                                                   \
     ensure_lds(k_xmid<T, NN>, lds);                                                                             \
     hipLaunchKernelGGL((k_xmid<T, NN>), dim3(blocks, 3, bt.nb), dim3(S::NT), lds, s, A0, A1, A2, mu, t, bt);    \
   }
@@ -1633,7 +1859,7 @@ hipError_t launch_zfwd_cg(int N, int mode, T* x, T* r, T* d, const T* q, T* A, T
   {                                                                                                        \
     using S = TileCfg<T, NN, DST2>;                                                                        \
     const int blocks = NN * NN / S::W;                                                                     \
-    const size_t lds = S::BYTES;                                                                           \
+    const size_t lds = TabStage<T, NN, DST2>::BYTES;                                                       \
     ensure_lds(k_zfwd_cg<T, NN, MODE>, lds);                                                               \
     hipLaunchKernelGGL((k_zfwd_cg<T, NN, MODE>), dim3(blocks, 1, bt.nb), dim3(S::NT), lds, s, x, r, d, q, A, B, \
                        scal, rpart, t, bt);                                                                \
@@ -1664,7 +1890,7 @@ hipError_t launch_zinv_cg(int N, const T* A, const T* B, T* q, const T* d, doubl
   {                                                                                                        \
     using S = TileCfg<T, NN, DCT3>;                                                                        \
     const int blocks = NN * NN / S::W;                                                                     \
-    const size_t lds = S::BYTES;                                                                           \
+    const size_t lds = TabStage<T, NN, DST3>::BYTES;                                                       \
     ensure_lds(k_zinv_cg<T, NN>, lds);                                                                     \
     hipLaunchKernelGGL((k_zinv_cg<T, NN>), dim3(blocks, 1, bt.nb), dim3(S::NT), lds, s, A, B, q, d, c,     \
                        partials, t, bt);                                                                   \
@@ -1712,12 +1938,20 @@ hipError_t launch_ypair(int N, bool inverse, const T* in0, const T* in1, T* out0
     using S = TileCfg<T, NN, DCT2>;                                                                       \
     const int blocks = NN * NN / S::W;                                                                    \
     const size_t lds = S::BYTES;                                                                          \
-    if (inverse) {                                                                                        \
+    using P = PipeCfg<T, NN, DST3>;                                                                       \
+    if (inverse && NN <= 256 && P::BYTES <= 163840) {                                                     \
+      ensure_lds(k_ypair_inv_pipe<T, NN>, P::BYTES);                                                      \
+      static std::atomic<int> per_cu{0};                                                                  \
+      const int pb = persistent_blocks(k_ypair_inv_pipe<T, NN>, S::NT, P::BYTES, blocks, per_cu);         \
+      hipLaunchKernelGGL((k_ypair_inv_pipe<T, NN>), dim3(pb, 1, bt.nb), dim3(S::NT), P::BYTES, s, in0, in1, out0, \
+                         blocks, t, bt);                                                                  \
+    } else if (inverse) {                                                                                 \
       ensure_lds(k_ypair_inv<T, NN>, lds);                                                                \
       hipLaunchKernelGGL((k_ypair_inv<T, NN>), dim3(blocks, 1, bt.nb), dim3(S::NT), lds, s, in0, in1, out0, t, bt); \
     } else {                                                                                              \
-      ensure_lds(k_ypair_fwd<T, NN>, lds);                                                                \
-      hipLaunchKernelGGL((k_ypair_fwd<T, NN>), dim3(blocks, 1, bt.nb), dim3(S::NT), lds, s, in0, out0, out1, t, bt); \
+      const size_t ldsf = TabStage<T, NN, DCT2>::BYTES;                                                   \
+      ensure_lds(k_ypair_fwd<T, NN>, ldsf);                                                               \
+      hipLaunchKernelGGL((k_ypair_fwd<T, NN>), dim3(blocks, 1, bt.nb), dim3(S::NT), ldsf, s, in0, out0, out1, t, bt); \
     }                                                                                                     \
   }
   KFBI_DISPATCH_N(N, KFBI_M)
