@@ -1119,6 +1119,49 @@ __global__ __launch_bounds__(tile_nt_max<N>()) void k_ypair_inv(const T* __restr
 }
 
 
+// Persistent, pipelined form of the forward y pair: the raw rows of the block's tile are staged
+// in LDS, the rows of its next tile are requested into registers, and the pass-1 samples of both
+// transforms come from one gather of the staged rows (the DST-II input being the DCT-II input
+// with sign flips); tables (twiddles, mk, s_k, shared by the two kinds) in LDS.
+template <typename T, int N>
+__global__ __launch_bounds__(tile_nt_max<N>()) void k_ypair_fwd_pipe(const T* __restrict__ A, T* __restrict__ A1,
+                                                       T* __restrict__ B2, int ntiles, Tab<T> tg, Bat bt) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  if (rhs_skipped(bt)) return;
+  A = wb(A, bt);
+  A1 = wb(A1, bt);
+  B2 = wb(B2, bt);
+  T* lds = reinterpret_cast<T*>(smem);
+  using S = TileCfg<T, N, DCT2>;
+  static_assert(S::R1 == TileCfg<T, N, DST2>::R1 && S::M == TileCfg<T, N, DST2>::M, "one gather for both kinds");
+  constexpr int W = S::W, R1 = S::R1;
+  const Tab<T> tb = tables_to_lds<T, N, DCT2>(smem, tg);
+  C2<T> raw[PipeCfg<T, N, DCT2>::PER];
+  int tile = blockIdx.x;
+  if (tile < ntiles) fetch_xy<T, N, DCT2>(A, tile_addr<W, N>(1, tile), raw);
+  for (; tile < ntiles; tile += gridDim.x) {
+    const TileAddr a = tile_addr<W, N>(1, tile);
+    __syncthreads();  // the previous tile's outputs have been read from LDS
+    stage_xy<T, N, DCT2>(lds, raw);
+    __syncthreads();
+    if (tile + (int)gridDim.x < ntiles) fetch_xy<T, N, DCT2>(A, tile_addr<W, N>(1, tile + gridDim.x), raw);
+    const LdsSrc<T, N> src{lds};
+    C2<T> zc[S::PT1][R1], zs[S::PT1][R1];
+    fft_gather<T, N, DCT2>([&](int j, int n) { return pre_sample<T, N, DCT2>(src, tb, j, n); }, zc);
+#pragma unroll
+    for (int u = 0; u < S::PT1; ++u)
+#pragma unroll
+      for (int n1 = 0; n1 < R1; ++n1) {
+        const bool odd = S::M * n1 >= N / 2;  // as in ypair_fwd_body
+        zs[u][n1] = odd ? C2<T>{-zc[u][n1].x, -zc[u][n1].y} : zc[u][n1];
+      }
+    fft_core_from<T, N, DST2>(lds, zs, tb);
+    store_xy_outputs<T, N, DST2>(lds, tb, A1 + a.base, a.nstride);
+    fft_core_from<T, N, DCT2>(lds, zc, tb);
+    store_xy_outputs<T, N, DCT2>(lds, tb, B2 + a.base, a.nstride);
+  }
+}
+
 // Persistent, pipelined form of the inverse y pair (as k_pass_pipe): per tile, the staged A1
 // rows are transformed while the B2 rows of the same tile arrive in registers, and the staged
 // B2 rows while the A1 rows of the block's next tile arrive.  The two inverse kinds share their
@@ -1948,6 +1991,13 @@ hipError_t launch_ypair(int N, bool inverse, const T* in0, const T* in1, T* out0
     } else if (inverse) {                                                                                 \
       ensure_lds(k_ypair_inv<T, NN>, lds);                                                                \
       hipLaunchKernelGGL((k_ypair_inv<T, NN>), dim3(blocks, 1, bt.nb), dim3(S::NT), lds, s, in0, in1, out0, t, bt); \
+    } else if (sizeof(T) == 4 && NN <= 256 && PipeCfg<T, NN, DCT2>::BYTES <= 163840) {                    \
+      using PF = PipeCfg<T, NN, DCT2>;                                                                    \
+      ensure_lds(k_ypair_fwd_pipe<T, NN>, PF::BYTES);                                                     \
+      static std::atomic<int> per_cu_f{0};                                                                \
+      const int pb = persistent_blocks(k_ypair_fwd_pipe<T, NN>, S::NT, PF::BYTES, blocks, per_cu_f);      \
+      hipLaunchKernelGGL((k_ypair_fwd_pipe<T, NN>), dim3(pb, 1, bt.nb), dim3(S::NT), PF::BYTES, s, in0, out0, out1, \
+                         blocks, t, bt);                                                                  \
     } else {                                                                                              \
       const size_t ldsf = TabStage<T, NN, DCT2>::BYTES;                                                   \
       ensure_lds(k_ypair_fwd<T, NN>, ldsf);                                                               \
