@@ -96,6 +96,21 @@ constexpr int tile_nt_max() {
   return N >= 512 ? 512 : 256;
 }
 
+// Minimum waves per SIMD a transform kernel is compiled for (amdgpu_waves_per_eu; 1 = the
+// compiler's choice).  Float32 tiles from N = 128 on are held to four (at most 128 registers): at
+// 512 a block has 512 threads, so one register above 128 leaves a single block per compute unit
+// where the LDS holds two (z inverse 129, DST-I pass 134 registers as compiled otherwise).  The
+// fused x passes of the right-hand side and back-substitution (136-154 registers) then spill a
+// few registers, which pays only at 512.
+template <typename T, int N>
+constexpr int tile_waves() {
+  return (sizeof(T) == 4 && N >= 128) ? 4 : 1;
+}
+template <typename T, int N>
+constexpr int xfuse_waves() {
+  return (sizeof(T) == 4 && N >= 512) ? 4 : 1;
+}
+
 // Contiguous z tile (W pencils of N, 16-byte aligned) -> LDS rows of stride N + 1.  Every
 // load of the thread is issued before the first LDS write (vector loads, unrolled).
 template <typename T, int N, int NT>
@@ -316,7 +331,7 @@ static int persistent_blocks(K kernel, int threads, size_t lds_bytes, int ntiles
 // ---------------------------------------------------------------------------------------
 // (in may equal out: a block reads its whole tile before it writes any output)
 template <typename T, int N, int KIND, bool ACC>
-__global__ __launch_bounds__(tile_nt_max<N>()) void k_pass(const T* in, T* out, int axis, Tab<T> tb, Bat bt) {
+__global__ __launch_bounds__(tile_nt_max<N>()) __attribute__((amdgpu_waves_per_eu(tile_waves<T, N>()))) void k_pass(const T* in, T* out, int axis, Tab<T> tb, Bat bt) {
   extern __shared__ __align__(16) unsigned char smem[];
   if (rhs_skipped(bt)) return;
   in = wb(in, bt);
@@ -618,6 +633,148 @@ __device__ void xmid_tile_regs(T* lds, T* field, int tile, int mc, double mu, co
   }
 }
 
+// Register path of the x pass for three-pass transforms (R1 = R2 = R3 = 8, 32 threads per job).
+// After the third forward pass a task (j, k1, k2) holds spectrum values k = k1 + 8 k2 + 64 k3
+// (k3 < 8), exactly the input set of inverse pass-1 task m = k1 + 8 k2 (samples m + 64 n1).
+// The partner values at N - k belong to task (8 - k1, 7 - k2) for k1 != 0 and (0, 8 - k2) for
+// k1 = 0 (at k3' = 7 - k3), while (0, 0) (k3' = 8 - k3 mod 8) and (0, 4) (k3' = 7 - k3) are
+// their own partners; every thread takes a task and its partner (slot 0 of a job takes (0, 0)
+// and (0, 4)), so the weight is applied in registers without any lane exchange, and the
+// spectrum transpose before it and the one after it disappear.
+template <typename T, int N, int KF>
+struct XmidRegs3 {
+  using S = TileCfg<T, N, KF>;
+  static constexpr bool ok = S::R1 == 8 && S::R2 == 8 && S::R3 == 8 && S::NT == S::NJ * 32;
+};
+// own ? a : b as a bitwise blend of the two values: a select between two register-array entries
+// may otherwise be rewritten as a load through a selected address, which moves the arrays to
+// scratch memory
+template <typename T>
+__device__ __forceinline__ T blend(uint32_t mask, T a, T b) {
+  if constexpr (sizeof(T) == 4) {
+    return __uint_as_float((__float_as_uint(a) & mask) | (__float_as_uint(b) & ~mask));
+  } else {
+    const uint64_t m = ((uint64_t)mask << 32) | mask;
+    return __longlong_as_double((long long)(((uint64_t)__double_as_longlong(a) & m) |
+                                            ((uint64_t)__double_as_longlong(b) & ~m)));
+  }
+}
+template <typename T>
+__device__ __forceinline__ C2<T> blend(uint32_t mask, C2<T> a, C2<T> b) {
+  return {blend(mask, a.x, b.x), blend(mask, a.y, b.y)};
+}
+
+// the two pass-3 tasks (k1, k2) of pair slot p < 32 of a job
+__device__ __forceinline__ void xmid3_tasks(int p, int& a1, int& a2, int& b1, int& b2) {
+  if (p == 0) {
+    a1 = 0, a2 = 0, b1 = 0, b2 = 4;
+  } else if (p < 4) {
+    a1 = 0, a2 = p, b1 = 0, b2 = 8 - p;
+  } else {
+    const int q = p - 4;  // 24 tasks with k1 = 1..3, then (4, 0..3)
+    a1 = (q < 24) ? 1 + q / 8 : 4;
+    a2 = (q < 24) ? q % 8 : q - 24;
+    b1 = 8 - a1, b2 = 7 - a2;
+  }
+}
+
+template <typename T, int N, int KF, int KI>
+__device__ __forceinline__ void xmid_tile_regs3(T* lds, T* field, int tile, int mc, double mu, const Tab<T>& tb,
+                                C2<T> (&zs)[TileCfg<T, N, KF>::PT1][TileCfg<T, N, KF>::R1], const T* lxt, T ly,
+                                const T (&lz)[2]) {
+  using S = TileCfg<T, N, KF>;
+  constexpr int W = S::W, NJ = S::NJ;
+  static_assert(XmidRegs3<T, N, KF>::ok && XmidRegs3<T, N, KI>::ok, "three radix-8 passes, two tasks per thread");
+  const TileAddr a = tile_addr<W, N>(0, tile);
+  C2<T>* cb = reinterpret_cast<C2<T>*>(lds);
+  fft_pass1_all<T, N, KF>(cb, zs, tb);
+  fft3_pass2<T, N, KF>(cb, tb);
+  const int j = threadIdx.x % NJ, p = threadIdx.x / NJ;
+  int a1, a2, b1, b2;
+  xmid3_tasks(p, a1, a2, b1, b2);
+  const uint32_t own = (p == 0) ? ~0u : 0u;  // tasks (0, 0) and (0, 4): partners inside each task
+  C2<T> za[8], zb[8];
+  fft3_pass3_task<T, N, KF>(cb, za, j, a1, a2);
+  fft3_pass3_task<T, N, KF>(cb, zb, j, b1, b2);
+  // Z_{N-k} for the values of task a and of task b
+  C2<T> ra[8], rb[8];
+#pragma unroll
+  for (int k3 = 0; k3 < 8; ++k3) {
+    ra[k3] = blend(own, za[(8 - k3) & 7], zb[7 - k3]);
+    rb[k3] = blend(own, zb[7 - k3], za[7 - k3]);
+  }
+  const T mu2 = T(2 * mu);  // the factor 1/2 of V is folded into the weight denominators
+  // Y_k of pencils a and b for the eight values of one task (k = k0 + 64 k3)
+  auto weigh = [&](const C2<T>(&z)[8], const C2<T>(&r)[8], int k0, T(&ya)[8], T(&yb)[8]) {
+#pragma unroll
+    for (int k3 = 0; k3 < 8; ++k3) {
+      const int k = k0 + 64 * k3;
+      const int mode = (KF == DST2) ? N - 1 - k : k;
+      const T lx = lxt[mode];
+      T om[2];
+#pragma unroll
+      for (int w = 0; w < 2; ++w) {
+        const T num = (mc == 0) ? lx : (mc == 1) ? ly : lz[w];
+        const T den = mu2 * (lx + ly + lz[w]);
+        if constexpr (sizeof(T) == 4)
+          om[w] = num * __builtin_amdgcn_rcpf(den);  // 1 ulp: the float32 inner solve
+        else
+          om[w] = num / den;
+      }
+      const C2<T> Zk = z[k3], Zr = r[k3], mkk = tb.mk[k];
+      const C2<T> Va = {Zk.x + Zr.x, Zk.y - Zr.y};  // 2 V^a_k
+      const C2<T> Vb = {Zk.y + Zr.y, Zr.x - Zk.x};  // 2 V^b_k
+      ya[k3] = om[0] * (mkk.x * Va.x - mkk.y * Va.y);
+      yb[k3] = om[1] * (mkk.x * Vb.x - mkk.y * Vb.y);
+    }
+  };
+  const int ka = a1 + 8 * a2, kb = b1 + 8 * b2;
+  T yaa[8], yba[8], yab[8], ybb[8];  // y<pencil><task>
+  weigh(za, ra, ka, yaa, yba);
+  weigh(zb, rb, kb, yab, ybb);
+  // inverse input Z'_k = V'^a_k + i V'^b_k, V'_k = conj(mk_k)(Y_k - i Y_{N-k}), Y_N = 0; the
+  // Y_{N-k} sit where Z_{N-k} did
+  auto prep = [&](const T(&ya)[8], const T(&yb)[8], const T(&yar)[8], const T(&ybr)[8], int k0, C2<T>(&z)[8]) {
+#pragma unroll
+    for (int k3 = 0; k3 < 8; ++k3) {
+      const C2<T> mk = tb.mk[k0 + 64 * k3], ck = {mk.x, -mk.y};
+      const C2<T> Wa = cmul(ck, C2<T>{ya[k3], -yar[k3]}), Wb = cmul(ck, C2<T>{yb[k3], -ybr[k3]});
+      z[k3] = {Wa.x - Wb.y, Wa.y + Wb.x};
+    }
+  };
+  T raa[8], rba[8], rab[8], rbb[8];
+#pragma unroll
+  for (int k3 = 0; k3 < 8; ++k3) {
+    raa[k3] = blend(own, (k3 == 0) ? T(0) : yaa[(8 - k3) & 7], yab[7 - k3]);
+    rba[k3] = blend(own, (k3 == 0) ? T(0) : yba[(8 - k3) & 7], ybb[7 - k3]);
+    rab[k3] = blend(own, yab[7 - k3], yaa[7 - k3]);
+    rbb[k3] = blend(own, ybb[7 - k3], yba[7 - k3]);
+  }
+  prep(yaa, yba, raa, rba, ka, za);
+  prep(yab, ybb, rab, rbb, kb, zb);
+  // inverse pass 1 of tasks m = k1 + 8 k2 from registers, then passes 2 and 3 from LDS
+  fft_pass1_dft<T, N, KI>(ka, za, tb);
+  fft_pass1_dft<T, N, KI>(kb, zb, tb);
+  __syncthreads();  // every forward pass-3 read of the transpose buffer is done
+  fft_pass1_store<T, N, KI>(cb, za, j, ka);
+  fft_pass1_store<T, N, KI>(cb, zb, j, kb);
+  __syncthreads();
+  fft3_pass2<T, N, KI>(cb, tb);
+  fft3_pass3<T, N, KI>(cb);
+  using O = OutItems<T, N, KI>;
+  C2<T>* o = reinterpret_cast<C2<T>*>(field + a.base);
+  const long ns = a.nstride / 2;
+#pragma unroll 4
+  for (int u = 0; u < O::PER_XY; ++u) {
+    int jj, k;
+    if (O::xy(u, jj, k)) {
+      C2<T> v;
+      post_pair<T, N, KI>(lds, tb, jj, k, v.x, v.y);
+      o[k * ns + jj] = v;
+    }
+  }
+}
+
 template <typename T, int N, int KIND>
 __device__ __forceinline__ void store_xy_outputs(const T* lds, const Tab<T>& tb, T* out, long nstride) {
   using O = OutItems<T, N, KIND>;
@@ -643,7 +800,7 @@ __device__ __forceinline__ void store_xy_outputs(const T* lds, const Tab<T>& tb,
 // is restaged in LDS for the inverse.
 // ---------------------------------------------------------------------------------------
 template <typename T, int N, int KF, int KI, bool BACKSUB>
-__global__ __launch_bounds__(tile_nt_max<N>()) void k_xfuse(const T* __restrict__ in, T* __restrict__ fh, T* __restrict__ out,
+__global__ __launch_bounds__(tile_nt_max<N>()) __attribute__((amdgpu_waves_per_eu(xfuse_waves<T, N>()))) void k_xfuse(const T* __restrict__ in, T* __restrict__ fh, T* __restrict__ out,
                                               int m, double mu, Tab<T> tb, Bat bt) {
   extern __shared__ __align__(16) unsigned char smem[];
   if (rhs_skipped(bt)) return;
@@ -782,6 +939,14 @@ __device__ void xmid_body(T* lds, T* field, int mc, double mu, const Tab<T>& tb)
       fft_gather<T, N, KF>([&](int jj, int n) { return pre_sample<T, N, KF>(src, tb, jj, n); }, zs);
       xmid_tile_regs<T, N, KF, KI>(lds, field, tile, mc, mu, tb, zs, gx, ly, lz);
     }
+  } else if constexpr (XmidRegs3<T, N, KF>::ok && XmidRegs3<T, N, KI>::ok) {
+    const int yi = tile / (N / S::W), z0 = (tile % (N / S::W)) * S::W, j = threadIdx.x % S::NJ;
+    const T ly = (mc == 1) ? tb.sg2[yi] : tb.sg2s[yi];
+    T lz[2];
+#pragma unroll
+    for (int w = 0; w < 2; ++w) lz[w] = (mc == 2) ? tb.sg2[z0 + 2 * j + w] : tb.sg2s[z0 + 2 * j + w];
+    fft_gather<T, N, KF>([&](int jj, int n) { return pre_sample<T, N, KF>(src, tb, jj, n); }, zs);
+    xmid_tile_regs3<T, N, KF, KI>(lds, field, tile, mc, mu, tb, zs, (mc == 0) ? tb.sg2 : tb.sg2s, ly, lz);
   } else {
     fft_gather<T, N, KF>([&](int j, int n) { return pre_sample<T, N, KF>(src, tb, j, n); }, zs);
     xmid_tile<T, N, KF, KI>(lds, field, tile, mc, mu, tb, zs);
@@ -923,7 +1088,7 @@ __global__ __launch_bounds__(tile_nt_max<N>()) void k_zfwd_cg(T* __restrict__ x,
 
 // q = DST-III_z(A) + DCT-III_z(B) + c d; per-block partial sums of d.q, q, d, q.q
 template <typename T, int N>
-__global__ __launch_bounds__(tile_nt_max<N>()) void k_zinv_cg(const T* __restrict__ A, const T* __restrict__ B,
+__global__ __launch_bounds__(tile_nt_max<N>()) __attribute__((amdgpu_waves_per_eu(tile_waves<T, N>()))) void k_zinv_cg(const T* __restrict__ A, const T* __restrict__ B,
                                                 T* __restrict__ q, const T* __restrict__ d, double c,
                                                 double* __restrict__ partials, Tab<T> tg, Bat bt) {
   extern __shared__ __align__(16) unsigned char smem[];

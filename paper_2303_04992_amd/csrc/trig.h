@@ -296,95 +296,121 @@ __device__ __forceinline__ void fft_pass2_store(C2<T>* cb, const C2<T> (&z)[Tile
   for (int k2 = 0; k2 < S::R2; ++k2) cb[j * S::ZS + k1 + S::R1 * k2] = z[k2];
 }
 
+// pass 1 of every task: R1-point DFTs over stride-M samples, twiddle, transpose (block barrier
+// before the transposed stores, which may overwrite the samples' source, and after them)
+template <typename T, int N, int KIND>
+__device__ __forceinline__ void fft_pass1_all(C2<T>* cb, C2<T> (&z)[TileCfg<T, N, KIND>::PT1][TileCfg<T, N, KIND>::R1],
+                                              const Tab<T>& tb) {
+  using S = TileCfg<T, N, KIND>;
+  constexpr int NJ = S::NJ, M = S::M, NT = S::NT, TASKS = NJ * M, PT = S::PT1;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int u = 0; u < PT; ++u) {
+    const int task = tid + u * NT;
+    if ((TASKS % NT == 0 || task < TASKS) && tid < NT) fft_pass1_dft<T, N, KIND>(task / NJ, z[u], tb);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < PT; ++u) {
+    const int task = tid + u * NT;
+    if ((TASKS % NT == 0 || task < TASKS) && tid < NT) fft_pass1_store<T, N, KIND>(cb, z[u], task % NJ, task / NJ);
+  }
+  __syncthreads();
+}
+
+// Three-pass FFTs (R3 > 1): after pass 1, the M-point DFTs of Y[k1][m] (m = R3 m2 + m3) as
+// R2-point DFTs over m2 with the M-point twiddles W_M^(m3 k2), a transpose (pass 2), and
+// R3-point DFTs over m3 (pass 3); spectrum value k1 + R1 (k2 + R2 k3) in natural order.  Each
+// pass ends with a block barrier.
+template <typename T, int N, int KIND>
+__device__ __forceinline__ void fft3_pass2(C2<T>* cb, const Tab<T>& tb) {
+  using S = TileCfg<T, N, KIND>;
+  constexpr int NJ = S::NJ, R1 = S::R1, R2 = S::R2, R3 = S::R3, M = S::M, NT = S::NT;
+  constexpr bool INV = (KIND == DCT3 || KIND == DST3);
+  const C2<T>* tw = (S::L == N) ? tb.tw : tb.tw2;
+  const int tid = threadIdx.x;
+  constexpr int TASKS = NJ * R1 * R3;
+  constexpr int PT = (TASKS + NT - 1) / NT;
+  C2<T> zb[PT][R2];
+#pragma unroll
+  for (int u = 0; u < PT; ++u) {
+    const int task = tid + u * NT;
+    if ((TASKS % NT == 0 || task < TASKS) && tid < NT) {
+      const int j = task % NJ, rest = task / NJ, m3 = rest % R3, k1 = rest / R3;
+#pragma unroll
+      for (int m2 = 0; m2 < R2; ++m2) zb[u][m2] = cb[j * S::YS + k1 * S::P2 + R3 * m2 + m3];
+      dftR<T, R2, INV>(zb[u]);
+#pragma unroll
+      for (int k2 = 1; k2 < R2; ++k2) {
+        C2<T> w = tw[(S::L / M) * m3 * k2];
+        if (INV) w.y = -w.y;
+        zb[u][k2] = cmul(zb[u][k2], w);
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < PT; ++u) {
+    const int task = tid + u * NT;
+    if ((TASKS % NT == 0 || task < TASKS) && tid < NT) {
+      const int j = task % NJ, rest = task / NJ, m3 = rest % R3, k1 = rest / R3;
+#pragma unroll
+      for (int k2 = 0; k2 < R2; ++k2) cb[j * S::YS3 + (k1 * R2 + k2) * S::P3 + m3] = zb[u][k2];
+    }
+  }
+  __syncthreads();
+}
+// pass 3 of one task (j, k1, k2): z[k3] = spectrum value k1 + R1 (k2 + R2 k3) of job j
+template <typename T, int N, int KIND>
+__device__ __forceinline__ void fft3_pass3_task(const C2<T>* cb, C2<T> (&z)[TileCfg<T, N, KIND>::R3], int j, int k1,
+                                                int k2) {
+  using S = TileCfg<T, N, KIND>;
+  constexpr bool INV = (KIND == DCT3 || KIND == DST3);
+#pragma unroll
+  for (int m3 = 0; m3 < S::R3; ++m3) z[m3] = cb[j * S::YS3 + (k1 * S::R2 + k2) * S::P3 + m3];
+  dftR<T, S::R3, INV>(z);
+}
+template <typename T, int N, int KIND>
+__device__ __forceinline__ void fft3_pass3(C2<T>* cb) {
+  using S = TileCfg<T, N, KIND>;
+  constexpr int NJ = S::NJ, R1 = S::R1, R2 = S::R2, R3 = S::R3, NT = S::NT;
+  const int tid = threadIdx.x;
+  constexpr int TASKS = NJ * R1 * R2;
+  constexpr int PT = (TASKS + NT - 1) / NT;
+  C2<T> zc[PT][R3];
+#pragma unroll
+  for (int u = 0; u < PT; ++u) {
+    const int task = tid + u * NT;
+    if ((TASKS % NT == 0 || task < TASKS) && tid < NT) {
+      const int j = task % NJ, rest = task / NJ, k2 = rest % R2, k1 = rest / R2;
+      fft3_pass3_task<T, N, KIND>(cb, zc[u], j, k1, k2);
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int u = 0; u < PT; ++u) {
+    const int task = tid + u * NT;
+    if ((TASKS % NT == 0 || task < TASKS) && tid < NT) {
+      const int j = task % NJ, rest = task / NJ, k2 = rest % R2, k1 = rest / R2;
+#pragma unroll
+      for (int k3 = 0; k3 < R3; ++k3) cb[j * S::ZS + k1 + R1 * (k2 + R2 * k3)] = zc[u][k3];
+    }
+  }
+  __syncthreads();
+}
+
 // The FFTs from the pass-1 samples already in registers (z is overwritten).
 template <typename T, int N, int KIND>
 __device__ void fft_core_from(T* lds, C2<T> (&z)[TileCfg<T, N, KIND>::PT1][TileCfg<T, N, KIND>::R1],
                               const Tab<T>& tb) {
   using S = TileCfg<T, N, KIND>;
-  constexpr int NJ = S::NJ, R1 = S::R1, R2 = S::R2, R3 = S::R3, M = S::M, NT = S::NT;
+  constexpr int NJ = S::NJ, R1 = S::R1, R2 = S::R2, R3 = S::R3, NT = S::NT;
   C2<T>* cb = reinterpret_cast<C2<T>*>(lds);
   const int tid = threadIdx.x;
-  // ---------------- pass 1: R1-point DFTs over stride-M samples, twiddle, transpose
-  {
-    constexpr int TASKS = NJ * M;
-    constexpr int PT = S::PT1;
-#pragma unroll
-    for (int u = 0; u < PT; ++u) {
-      const int task = tid + u * NT;
-      if ((TASKS % NT == 0 || task < TASKS) && tid < NT) fft_pass1_dft<T, N, KIND>(task / NJ, z[u], tb);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int u = 0; u < PT; ++u) {
-      const int task = tid + u * NT;
-      if ((TASKS % NT == 0 || task < TASKS) && tid < NT) fft_pass1_store<T, N, KIND>(cb, z[u], task % NJ, task / NJ);
-    }
-    __syncthreads();
-  }
+  fft_pass1_all<T, N, KIND>(cb, z, tb);
   if constexpr (R3 > 1) {
-    // ---------------- three passes: the M-point DFTs of Y[k1][m] (m = R3 m2 + m3) as R2-point
-    // DFTs over m2 with the M-point twiddles W_M^(m3 k2), a transpose, and R3-point DFTs over
-    // m3; spectrum value k1 + R1 (k2 + R2 k3) in natural order
-    constexpr bool INV = (KIND == DCT3 || KIND == DST3);
-    const C2<T>* tw = (S::L == N) ? tb.tw : tb.tw2;
-    {
-      constexpr int TASKS = NJ * R1 * R3;
-      constexpr int PT = (TASKS + NT - 1) / NT;
-      C2<T> zb[PT][R2];
-#pragma unroll
-      for (int u = 0; u < PT; ++u) {
-        const int task = tid + u * NT;
-        if ((TASKS % NT == 0 || task < TASKS) && tid < NT) {
-          const int j = task % NJ, rest = task / NJ, m3 = rest % R3, k1 = rest / R3;
-#pragma unroll
-          for (int m2 = 0; m2 < R2; ++m2) zb[u][m2] = cb[j * S::YS + k1 * S::P2 + R3 * m2 + m3];
-          dftR<T, R2, INV>(zb[u]);
-#pragma unroll
-          for (int k2 = 1; k2 < R2; ++k2) {
-            C2<T> w = tw[(S::L / M) * m3 * k2];
-            if (INV) w.y = -w.y;
-            zb[u][k2] = cmul(zb[u][k2], w);
-          }
-        }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int u = 0; u < PT; ++u) {
-        const int task = tid + u * NT;
-        if ((TASKS % NT == 0 || task < TASKS) && tid < NT) {
-          const int j = task % NJ, rest = task / NJ, m3 = rest % R3, k1 = rest / R3;
-#pragma unroll
-          for (int k2 = 0; k2 < R2; ++k2) cb[j * S::YS3 + (k1 * R2 + k2) * S::P3 + m3] = zb[u][k2];
-        }
-      }
-      __syncthreads();
-    }
-    {
-      constexpr int TASKS = NJ * R1 * R2;
-      constexpr int PT = (TASKS + NT - 1) / NT;
-      C2<T> zc[PT][R3];
-#pragma unroll
-      for (int u = 0; u < PT; ++u) {
-        const int task = tid + u * NT;
-        if ((TASKS % NT == 0 || task < TASKS) && tid < NT) {
-          const int j = task % NJ, rest = task / NJ, k2 = rest % R2, k1 = rest / R2;
-#pragma unroll
-          for (int m3 = 0; m3 < R3; ++m3) zc[u][m3] = cb[j * S::YS3 + (k1 * R2 + k2) * S::P3 + m3];
-          dftR<T, R3, INV>(zc[u]);
-        }
-      }
-      __syncthreads();
-#pragma unroll
-      for (int u = 0; u < PT; ++u) {
-        const int task = tid + u * NT;
-        if ((TASKS % NT == 0 || task < TASKS) && tid < NT) {
-          const int j = task % NJ, rest = task / NJ, k2 = rest % R2, k1 = rest / R2;
-#pragma unroll
-          for (int k3 = 0; k3 < R3; ++k3) cb[j * S::ZS + k1 + R1 * (k2 + R2 * k3)] = zc[u][k3];
-        }
-      }
-      __syncthreads();
-    }
+    fft3_pass2<T, N, KIND>(cb, tb);
+    fft3_pass3<T, N, KIND>(cb);
     return;
   }
   // ---------------- pass 2: R2-point DFTs, natural-order output

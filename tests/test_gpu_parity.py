@@ -9,7 +9,7 @@ Tolerances: the float64 path matches the oracle to 1e-10 -- both sides solve the
 system by CG to 1e-12 / 1e-13 relative residual, so their results differ only at that level;
 the mixed path (float32 transforms and inner CG inside float64 refinement) to 1e-6, the
 accuracy the mixed form is specified for, both at a tight refinement tolerance (1e-9) and at
-the benchmark's settings (refinement 3e-6, inner CG 3e-6) on rough (random) densities.
+the benchmark's settings (refinement 8e-6, inner CG 8e-6) on rough (random) densities.
 """
 import json
 import os
@@ -25,7 +25,7 @@ pytestmark = pytest.mark.gpu
 HERE = os.path.dirname(os.path.abspath(__file__))
 FORMS = ("average", "interior")
 # the benchmark's mixed settings (bench.py defaults)
-BENCH_REFINE, BENCH_INNER = 3e-6, 3e-6
+BENCH_REFINE, BENCH_INNER = 8e-6, 8e-6
 
 
 def _say(msg):
