@@ -163,6 +163,8 @@ struct MacSolver {
   double* rpart = nullptr;  // partial r.r of the forward z pass
   double* scal = nullptr;
   double* host_rr = nullptr;  // pinned: two look-ahead slots of the 8 CG scalars (scal[0..7])
+  double* host_rr_dev = nullptr;  // its device address (the coefficient kernel writes it)
+  double* coef_slot = nullptr;    // slot of the iteration being queued (device address)
   StageClock* clock = nullptr;  // stage marks of the calling context
   void mark(int st) {
     if (clock) clock->mark(st, s);
@@ -260,12 +262,14 @@ struct MacSolver {
     rpart = dalloc<double>(nparts_z, owned);
     scal = dalloc<double>(16, owned);
     HIPCHK(hipHostMalloc((void**)&host_rr, 16 * sizeof(double), hipHostMallocDefault));
+    HIPCHK(hipHostGetDevicePointer((void**)&host_rr_dev, host_rr, 0));
     HIPCHK(hipEventCreateWithFlags(&ev[0], hipEventDisableTiming));
     HIPCHK(hipEventCreateWithFlags(&ev[1], hipEventDisableTiming));
   }
   void release() {
     if (host_rr) (void)hipHostFree(host_rr);
     host_rr = nullptr;
+    host_rr_dev = nullptr;
     for (auto& e : prof_ev) {
       (void)hipEventDestroy(e.first);
       (void)hipEventDestroy(e.second);
@@ -379,7 +383,7 @@ struct MacSolver {
     yinv();                               // A = DST_y^T A1 + DCT_y^T B2 (components 0 and 1 share DST_z)
     pass(DST3, 1, B3, B);
     zinv();                // q = DST_z^T A + DCT_z^T B + c d, partial dots
-    HIPCHK(launch_cg_coef(rpart, nparts_z, partials, nparts_x, scal, 1, M, s, cur));  // mean-zero iterates
+    HIPCHK(launch_cg_coef(rpart, nparts_z, partials, nparts_x, scal, 1, M, s, cur, coef_slot));  // mean-zero iterates
   }
 
   // Solve A_u u + G p = F_u, D u + c p = F_p (Stokes: D u = F_p - mean F_p, mean p = 0).
@@ -485,13 +489,13 @@ struct MacSolver {
       bytes += 3.0 * M * sizeof(T);
       if (NB > 1) HIPCHK(launch_fill<int>(1, act_cg + rr, 0, s));
     };
-    auto copy_slots = [&](int i) {
-      HIPCHK(hipMemcpy2DAsync(slot(i, 0), 8 * sizeof(double), scal, NB > 1 ? (size_t)bt.A : 8 * sizeof(double),
-                              8 * sizeof(double), NB, hipMemcpyDeviceToHost, s));
-    };
     while (ndone < NB && it < maxit) {
+      // the coefficient kernel writes scal[0] and scal[7] of each right-hand side straight into
+      // the iteration's host slot (a copy operation there would put a gap of about 20 us
+      // between the iterations' kernels)
+      coef_slot = host_rr_dev + 8 * ((it & 1) * NB);
       cg_iteration(it == 0);
-      copy_slots(it);
+      coef_slot = nullptr;
       HIPCHK(hipEventRecord(ev[it & 1], s));
       ++it;
       if (it >= 2) {
@@ -1222,7 +1226,9 @@ void ensure_batch(kfbi_ctx* C, int nrhs) {
   auto grow_rr = [&](auto& sv) {
     if (sv.host_rr) (void)hipHostFree(sv.host_rr);
     sv.host_rr = nullptr;
+    sv.host_rr_dev = nullptr;
     HIPCHK(hipHostMalloc((void**)&sv.host_rr, 16 * nrhs * sizeof(double), hipHostMallocDefault));
+    HIPCHK(hipHostGetDevicePointer((void**)&sv.host_rr_dev, sv.host_rr, 0));
     sv.rr_cap = nrhs;
   };
   if (C->mixed)

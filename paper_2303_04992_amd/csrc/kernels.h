@@ -82,7 +82,7 @@ hipError_t launch_axpy_scal(int64_t M, T* x, const T* d, const double* scal, int
 // inverse z pass (nz blocks of 4): scal[0] = |r_next|^2 (recurrence), [1] alpha, [2] beta,
 // [3] mean q (Stokes), [7] r.r
 hipError_t launch_cg_coef(const double* rpart, int nr, const double* zpart, int nz, double* scal, int stokes,
-                          int64_t M, hipStream_t s, const Bat& bt = Bat());
+                          int64_t M, hipStream_t s, const Bat& bt = Bat(), double* hslot = nullptr);
 
 // ---- reductions (float64, deterministic)
 // scal layout: [0] |r_next|^2, [1] alpha, [2] beta, [3] mean q, [5] scratch sum, [6] aux, [7] r.r,

@@ -1388,9 +1388,12 @@ __global__ __launch_bounds__(tile_nt_max<N>()) void k_ypair_inv_pipe(const T* __
 // is formed (the next forward z pass forms it together with x and d).
 // scal: [0] |r_{k+1}|^2 (recurrence), [1] alpha, [2] beta, [3] mean q, [7] r_k.r_k
 constexpr int CG_NT = 1024;  // threads of the coefficient kernel (its loads are latency-bound)
+// hslot (may be null): pinned host memory, 8 doubles per right-hand side, that receives
+// scal[0] and scal[7] of this iteration (the stop test reads them there, with no copy between
+// the iteration's kernels and the next one)
 __global__ __launch_bounds__(CG_NT) void k_cg_coef(const double* __restrict__ rpart, int nr,
                                                 const double* __restrict__ zpart, int nz, double* __restrict__ scal,
-                                                int stokes, int64_t M, Bat bt) {
+                                                int stokes, int64_t M, Bat bt, double* __restrict__ hslot) {
   __shared__ double red[CG_NT / 64];
   if (rhs_skipped(bt)) return;
   rpart = wb(rpart, bt);
@@ -1425,6 +1428,12 @@ __global__ __launch_bounds__(CG_NT) void k_cg_coef(const double* __restrict__ rp
     scal[2] = (rr > 0.0) ? rn / rr : 0.0;
     scal[3] = mq;
     scal[7] = rr;
+    if (hslot) {
+      double* h = hslot + 8 * (int)blockIdx.z;
+      h[0] = rn;
+      h[7] = rr;
+      __threadfence_system();  // visible to the host once the kernel has completed
+    }
   }
 }
 
@@ -2181,8 +2190,9 @@ hipError_t launch_axpy_scal(int64_t M, T* x, const T* d, const double* scal, int
 }
 
 hipError_t launch_cg_coef(const double* rpart, int nr, const double* zpart, int nz, double* scal, int stokes,
-                          int64_t M, hipStream_t s, const Bat& bt) {
-  hipLaunchKernelGGL(k_cg_coef, dim3(1, 1, bt.nb), dim3(CG_NT), 0, s, rpart, nr, zpart, nz, scal, stokes, M, bt);
+                          int64_t M, hipStream_t s, const Bat& bt, double* hslot) {
+  hipLaunchKernelGGL(k_cg_coef, dim3(1, 1, bt.nb), dim3(CG_NT), 0, s, rpart, nr, zpart, nz, scal, stokes, M, bt,
+                     hslot);
   return hipGetLastError();
 }
 
