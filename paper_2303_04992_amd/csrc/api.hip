@@ -236,6 +236,10 @@ struct MacSolver {
     tb.mk = dupload(mk, owned, s);
     tb.sc = dupload(sc, owned, s);
     tb.isc = dupload(isc, owned, s);
+    tb.s0 = sc[0];
+    tb.s1 = sc[N > 1 ? 1 : 0];
+    tb.is0 = isc[0];
+    tb.is1 = isc[N > 1 ? 1 : 0];
     tb.sig = dupload(sig, owned, s);
     tb.sig2s = dupload(sig2s, owned, s);
     std::vector<T> sg2t(N), sg2st(N);

@@ -32,6 +32,7 @@ struct DevTables {
   void* mk = nullptr;   // C2<T>[N]
   T* sc = nullptr;      // [N]
   T* isc = nullptr;     // [N]
+  T s0 = 0, s1 = 0, is0 = 0, is1 = 0;  // sc[0], sc[k > 0], isc[0], isc[k > 0]
   double* sig = nullptr;   // sigma_k = (2/h) sin(pi k / 2N), k < N
   double* sig2s = nullptr; // sigma_{k+1}^2, k < N
   T* sg2 = nullptr;        // sigma_k^2 in T

@@ -30,6 +30,10 @@ static Tab<T> tab_of(const DevTables<T>& d) {
   t.mk = reinterpret_cast<const C2<T>*>(d.mk);
   t.sc = d.sc;
   t.isc = d.isc;
+  t.s0 = d.s0;
+  t.s1 = d.s1;
+  t.is0 = d.is0;
+  t.is1 = d.is1;
   t.sg2 = d.sg2;
   t.sg2s = d.sg2s;
   return t;
@@ -148,31 +152,24 @@ template <typename T, int N, int KIND>
 struct PipeCfg {
   using S = TileCfg<T, N, KIND>;
   static constexpr size_t TAB_OFF = (S::BYTES + 15) / 16 * 16;
-  static constexpr size_t BYTES = TAB_OFF + (size_t)(S::L + N) * sizeof(C2<T>) + (size_t)N * sizeof(T);
+  static constexpr size_t BYTES = TAB_OFF + (size_t)(S::L + N) * sizeof(C2<T>);
   static constexpr int NPAIR = S::NJ * N;                  // element pairs of a tile
   static constexpr int PER = (NPAIR + S::NT - 1) / S::NT;  // per thread
 };
 
-// twiddles (tw or tw2), mk and the scale table of the kind (sc, or isc for the inverses) in LDS
+// twiddles (tw or tw2) and mk in LDS (the orthonormal scales travel as the scalars of Tab)
 template <typename T, int N, int KIND>
 __device__ __forceinline__ Tab<T> tables_to_lds(unsigned char* smem, const Tab<T>& g) {
   using S = TileCfg<T, N, KIND>;
   C2<T>* ltw = reinterpret_cast<C2<T>*>(smem + PipeCfg<T, N, KIND>::TAB_OFF);
   C2<T>* lmk = ltw + S::L;
-  T* lsc = reinterpret_cast<T*>(lmk + N);
   const C2<T>* gtw = (S::L == N) ? g.tw : g.tw2;
-  const T* gsc = (KIND == DCT3 || KIND == DST3) ? g.isc : g.sc;
   for (int i = threadIdx.x; i < S::L; i += blockDim.x) ltw[i] = gtw[i];
-  for (int i = threadIdx.x; i < N; i += blockDim.x) {
-    lmk[i] = g.mk[i];
-    lsc[i] = gsc[i];
-  }
+  for (int i = threadIdx.x; i < N; i += blockDim.x) lmk[i] = g.mk[i];
   Tab<T> t = g;
   t.tw = ltw;
   t.tw2 = ltw;
   t.mk = lmk;
-  t.sc = lsc;
-  t.isc = lsc;
   return t;
 }
 
@@ -188,11 +185,9 @@ struct TabStage {
   static constexpr size_t BYTES = ON ? P::BYTES : S::BYTES;
   static constexpr int NT = S::NT, PL = (S::L + NT - 1) / NT, PN = (N + NT - 1) / NT;
   C2<T> rtw[ON ? PL : 1], rmk[ON ? PN : 1];
-  T rsc[ON ? PN : 1];
   __device__ __forceinline__ void request(const Tab<T>& g) {
     if constexpr (ON) {
       const C2<T>* gtw = (S::L == N) ? g.tw : g.tw2;
-      const T* gsc = (KIND == DCT3 || KIND == DST3) ? g.isc : g.sc;
 #pragma unroll
       for (int u = 0; u < PL; ++u) {
         const int i = threadIdx.x + u * NT;
@@ -201,10 +196,7 @@ struct TabStage {
 #pragma unroll
       for (int u = 0; u < PN; ++u) {
         const int i = threadIdx.x + u * NT;
-        if (i < N) {
-          rmk[u] = g.mk[i];
-          rsc[u] = gsc[i];
-        }
+        if (i < N) rmk[u] = g.mk[i];
       }
     }
   }
@@ -214,7 +206,6 @@ struct TabStage {
     if constexpr (ON) {
       C2<T>* ltw = reinterpret_cast<C2<T>*>(smem + P::TAB_OFF);
       C2<T>* lmk = ltw + S::L;
-      T* lsc = reinterpret_cast<T*>(lmk + N);
 #pragma unroll
       for (int u = 0; u < PL; ++u) {
         const int i = threadIdx.x + u * NT;
@@ -223,10 +214,7 @@ struct TabStage {
 #pragma unroll
       for (int u = 0; u < PN; ++u) {
         const int i = threadIdx.x + u * NT;
-        if (i < N) {
-          lmk[i] = rmk[u];
-          lsc[i] = rsc[u];
-        }
+        if (i < N) lmk[i] = rmk[u];
       }
     }
     return view(smem, g);
@@ -234,14 +222,10 @@ struct TabStage {
   __device__ __forceinline__ static Tab<T> view(unsigned char* smem, const Tab<T>& g) {
     if constexpr (ON) {
       C2<T>* ltw = reinterpret_cast<C2<T>*>(smem + P::TAB_OFF);
-      C2<T>* lmk = ltw + S::L;
-      T* lsc = reinterpret_cast<T*>(lmk + N);
       Tab<T> t = g;
       t.tw = ltw;
       t.tw2 = ltw;
-      t.mk = lmk;
-      t.sc = lsc;
-      t.isc = lsc;
+      t.mk = ltw + S::L;
       return t;
     } else {
       return g;
@@ -2156,7 +2140,7 @@ hipError_t launch_ypair(int N, bool inverse, const T* in0, const T* in1, T* out0
     const int blocks = NN * NN / S::W;                                                                    \
     const size_t lds = S::BYTES;                                                                          \
     using P = PipeCfg<T, NN, DST3>;                                                                       \
-    if (inverse && NN <= 256 && P::BYTES <= 163840) {                                                     \
+    if (inverse && NN <= 512 && P::BYTES <= 163840) {                                                     \
       ensure_lds(k_ypair_inv_pipe<T, NN>, P::BYTES);                                                      \
       static std::atomic<int> per_cu{0};                                                                  \
       const int pb = persistent_blocks(k_ypair_inv_pipe<T, NN>, S::NT, P::BYTES, blocks, per_cu);         \
@@ -2165,7 +2149,7 @@ hipError_t launch_ypair(int N, bool inverse, const T* in0, const T* in1, T* out0
     } else if (inverse) {                                                                                 \
       ensure_lds(k_ypair_inv<T, NN>, lds);                                                                \
       hipLaunchKernelGGL((k_ypair_inv<T, NN>), dim3(blocks, 1, bt.nb), dim3(S::NT), lds, s, in0, in1, out0, t, bt); \
-    } else if (sizeof(T) == 4 && NN <= 256 && PipeCfg<T, NN, DCT2>::BYTES <= 163840) {                    \
+    } else if (sizeof(T) == 4 && NN <= 512 && PipeCfg<T, NN, DCT2>::BYTES <= 163840) {                    \
       using PF = PipeCfg<T, NN, DCT2>;                                                                    \
       ensure_lds(k_ypair_fwd_pipe<T, NN>, PF::BYTES);                                                     \
       static std::atomic<int> per_cu_f{0};                                                                \

@@ -39,6 +39,8 @@ struct Tab {
   const C2<T>* mk;   // e^{-i pi k / 2N}, k < N
   const T* sc;       // orthonormal DCT-II scale s_k: sqrt(1/N) (k=0), sqrt(2/N)
   const T* isc;      // 1 / s_k
+  T s0, s1;          // s_0 and s_k (k > 0), the two values of sc, read without a table access
+  T is0, is1;        // 1 / s_0 and 1 / s_k (k > 0)
   const T* sg2;      // sigma_k^2 = (4/h^2) sin^2(pi k / 2N), k < N   (DCT-II / DST-I modes)
   const T* sg2s;     // sigma_{k+1}^2, k < N                           (DST-II modes)
 };
@@ -193,11 +195,11 @@ __device__ __forceinline__ C2<T> pre_sample(const Src& src, const Tab<T>& tb, in
     // Y_k = X'_k / s_k and Y_{N-k} (Y_N = 0); X' = X (DCT-III) or X reversed (DST-III)
     const int ik = (KIND == DST3) ? N - 1 - k : k;
     const int ir = (KIND == DST3) ? k - 1 : N - k;  // index of X'_{N-k}
-    const T s1 = tb.isc[k];
+    const T s1 = (k == 0) ? tb.is0 : tb.is1;
     const C2<T> y = src.pair(j, ik);
     C2<T> yr = {T(0), T(0)};
     if (k > 0) {
-      const T s2 = tb.isc[N - k];
+      const T s2 = tb.is1;  // 1 / s_{N-k}, N - k > 0
       const C2<T> t = src.pair(j, ir);
       yr = {t.x * s2, t.y * s2};
     }
@@ -442,7 +444,7 @@ __device__ __forceinline__ void post_pair(const T* lds, const Tab<T>& tb, int j,
     const int kk = (KIND == DST2) ? N - 1 - k : k;
     const C2<T> a = Z[kk], b = Z[(N - kk) & (N - 1)];
     const C2<T> m = tb.mk[kk];
-    const T f = tb.sc[kk] * T(0.5);
+    const T f = ((kk == 0) ? tb.s0 : tb.s1) * T(0.5);
     // V_a = (a + conj b)/2, V_b = (a - conj b)/(2i); output = sc Re(m V)
     v0 = f * (m.x * (a.x + b.x) - m.y * (a.y - b.y));
     v1 = f * (m.x * (a.y + b.y) - m.y * (b.x - a.x));
