@@ -605,7 +605,6 @@ struct kfbi_ctx {
   double *fitw, *jmap, *jfmap, *emap, *efmap, *arm_a, *itp_w, *uT_w, *cT_a;
   // work
   double *jumps, *fitvals, *ejump, *F, *u, *p, *jbar, *fitbar;
-  int* flag;
   // body force of the last kfbi_solve_bvp with f != NULL: the force jumps at the crossings (Fj)
   // and the volume values at the interior nodes; has_force covers both (set together)
   bool has_force = false;
@@ -642,10 +641,14 @@ struct kfbi_ctx {
   // F is zero outside the irregular nodes (the correction pass then assigns those and no clear
   // of the 4 N^3 values is needed); false after any other writer of F
   bool f_clean = false;
-  // pinned host scalars read after a later synchronisation (hflag: non-finite input seen by the
-  // check of the current call), and the stage clock of a call
+  // pinned host scalars written by kernels and read after a later synchronisation (hflag: the
+  // tag of the current call's input check if it saw a non-finite value), their device
+  // addresses, and the stage clock of a call
   double* hpin = nullptr;
   int* hflag = nullptr;
+  double* hpin_dev = nullptr;
+  int* hflag_dev = nullptr;
+  int check_tag = 0;
   StageClock clock;
   // batched evaluations (kfbi_eval_batch): the current batch of the context-level launches, the
   // per-right-hand-side work arenas (bat_A bytes each) and their flags
@@ -655,6 +658,7 @@ struct kfbi_ctx {
   int bat_cap = 0, bat_clean = 0;
   int* bat_act = nullptr;  // 3 x bat_cap flags: the solver's live and CG flags, the refinement's
   double* hpin_bat = nullptr;  // pinned: |F| and |r| of each right-hand side (2 x bat_cap)
+  double* hpin_bat_dev = nullptr;
   ~kfbi_ctx() {
     if (hpin) (void)hipHostFree(hpin);
     if (hflag) (void)hipHostFree(hflag);
@@ -732,6 +736,8 @@ kfbi_status kfbi_create(const kfbi_config* cfg_in, kfbi_ctx** out) {
     HIPCHK(hipHostMalloc((void**)&C->hpin, 16 * sizeof(double), hipHostMallocDefault));
     HIPCHK(hipHostMalloc((void**)&C->hflag, sizeof(int), hipHostMallocDefault));
     *C->hflag = 0;
+    HIPCHK(hipHostGetDevicePointer((void**)&C->hpin_dev, C->hpin, 0));
+    HIPCHK(hipHostGetDevicePointer((void**)&C->hflag_dev, C->hflag, 0));
     C->clock.init();
     C->M = S.M;
     C->nb_ptr = dupload(S.nb_ptr, o, s);
@@ -783,7 +789,6 @@ kfbi_status kfbi_create(const kfbi_config* cfg_in, kfbi_ctx** out) {
     C->F = dalloc<double>(4 * S.M, o);
     C->u = dalloc<double>(3 * S.M, o);
     C->p = dalloc<double>(S.M, o);
-    C->flag = dalloc<int>(1, o);
     const double c = (S.pde == KFBI_STOKES) ? 0.0 : 1.0 / (S.lam + S.mu);
     C->mixed = (C->cfg.precision == KFBI_MIXED_FP32);
     if (C->mixed) {
@@ -854,21 +859,25 @@ kfbi_status kfbi_sizes(const kfbi_ctx* ctx, int64_t* n_crossings, int64_t* n_irr
 // ---------------------------------------------------------------------------------------
 namespace {
 
-// Non-finite check of an input vector: the flag is cleared by a fill kernel, set by the check
-// kernel and copied to pinned host memory, all on the stream; it is read at the call's next
+// Non-finite check of an input vector: the check kernel stores a fresh tag of this check into
+// pinned host memory when it meets a non-finite value; the host reads it at the call's next
 // synchronisation (finish_input_check, or guarded() when the call fails), so the check costs
-// no synchronisation of its own.
+// no synchronisation and no copy of its own. A tag, not a cleared flag: a store of an earlier
+// check that is still in flight cannot be taken for this one.
 void check_finite(kfbi_ctx* C, const double* v, int64_t n) {
-  HIPCHK(launch_fill<int>(1, C->flag, 0, C->s));
-  HIPCHK(launch_check_finite(n, v, C->flag, C->s));
-  HIPCHK(hipMemcpyAsync(C->hflag, C->flag, sizeof(int), hipMemcpyDeviceToHost, C->s));
+  C->check_tag = C->check_tag == INT32_MAX ? 1 : C->check_tag + 1;
+  HIPCHK(launch_check_finite(n, v, C->hflag_dev, C->check_tag, C->s));
+}
+// after a synchronisation (no check kernel in flight): did the latest check see a non-finite
+// value? A seen flag is consumed (tags only grow, so a later check never reuses it).
+bool input_flagged(kfbi_ctx* C) {
+  const bool b = C->check_tag != 0 && *C->hflag == C->check_tag;
+  if (b) *C->hflag = 0;
+  return b;
 }
 void finish_input_check(kfbi_ctx* C) {
   HIPCHK(hipStreamSynchronize(C->s));
-  if (*C->hflag) {
-    *C->hflag = 0;
-    throw std::invalid_argument("non-finite input");
-  }
+  if (input_flagged(C)) throw std::invalid_argument("non-finite input");
 }
 
 // blocks of the refinement passes and of the correction pass that stands in for the first of them
@@ -959,12 +968,11 @@ int mac_solve(kfbi_ctx* C, const double* F, double* u, double* p, kfbi_info* inf
     HIPCHK(hipStreamSynchronize(s));
   }
   // |F| and |r| of every right-hand side in pinned host memory (f0 read with the first residual)
+  // (written by the reduction kernels through the device addresses hf0_dev, hrn_dev)
   double* hf0 = NB > 1 ? C->hpin_bat : C->hpin + 1;
   double* hrn = NB > 1 ? C->hpin_bat + NB : C->hpin;
-  auto scal_to_host = [&](double* dst) {  // rscal[5] of every right-hand side
-    HIPCHK(hipMemcpy2DAsync(dst, sizeof(double), C->rscal + 5, NB > 1 ? (size_t)bt.A : sizeof(double), sizeof(double),
-                            NB, hipMemcpyDeviceToHost, s));
-  };
+  double* hf0_dev = NB > 1 ? C->hpin_bat_dev : C->hpin_dev + 1;
+  double* hrn_dev = NB > 1 ? C->hpin_bat_dev + NB : C->hpin_dev;
   // the first inner solve is queued without a synchronisation (F = 0 gives x32 = 0 and a zero
   // residual)
   if (!(C->r32_ready && C->f_clean && F == C->F)) {
@@ -973,8 +981,7 @@ int mac_solve(kfbi_ctx* C, const double* F, double* u, double* p, kfbi_info* inf
     C->r32_clean = false;
   }
   C->r32_ready = false;
-  HIPCHK(launch_reduce(C->rpart, NP, 3, C->rscal, R_RESNORM0, stokes, M, s, nullptr, bt));
-  scal_to_host(hf0);
+  HIPCHK(launch_reduce(C->rpart, NP, 3, C->rscal, R_RESNORM0, stokes, M, s, nullptr, bt, hf0_dev));
   const double* shift = stokes ? C->rscal + 6 : nullptr;  // mean of F_p (Stokes)
   // the iterate alternates between (u, p) and the spare float64 fields (neighbour values of
   // the old iterate are read while the new one is written); in_ru[r]: where right-hand side r
@@ -998,8 +1005,7 @@ int mac_solve(kfbi_ctx* C, const double* F, double* u, double* p, kfbi_info* inf
     C->bytes_extra += (rounds == 0 ? 96.0 : 128.0) * Md * nlive;
     cu = nu;
     cp = np;
-    HIPCHK(launch_reduce(C->rpart, NP, 3, C->rscal, R_RESNORM, stokes, M, s, nullptr, bref));
-    scal_to_host(hrn);
+    HIPCHK(launch_reduce(C->rpart, NP, 3, C->rscal, R_RESNORM, stokes, M, s, nullptr, bref, hrn_dev));
     HIPCHK(hipStreamSynchronize(s));
     ++rounds;
     for (int r = 0; r < NB; ++r) {
@@ -1107,9 +1113,7 @@ kfbi_status guarded(kfbi_ctx* C, F&& f) {
   if (!C) return KFBI_EINVAL;
   auto bad_input = [&]() -> bool {  // a failure caused by a non-finite input reports EINVAL
     (void)hipStreamSynchronize(C->s);
-    const bool b = *C->hflag != 0;
-    *C->hflag = 0;
-    return b;
+    return input_flagged(C);
   };
   C->clock.used = 0;
   C->bytes_extra = C->s32.bytes = C->s64.bytes = 0;
@@ -1144,7 +1148,6 @@ kfbi_status guarded(kfbi_ctx* C, F&& f) {
 struct WorkSet {
   double *jumps, *fitvals, *ejump, *F, *u, *p, *ru, *rscal, *rpart;
   float *r32, *r32b, *x32;
-  int* flag;
   SolverPtrs<float> s32;
   SolverPtrs<double> s64;
   bool f_clean, r32_clean, r32_ready;
@@ -1153,14 +1156,13 @@ struct WorkSet {
 
 WorkSet get_work(const kfbi_ctx* C) {
   return {C->jumps, C->fitvals, C->ejump, C->F, C->u, C->p, C->ru, C->rscal, C->rpart, C->r32, C->r32b, C->x32,
-          C->flag, C->s32.ptrs(), C->s64.ptrs(), C->f_clean, C->r32_clean, C->r32_ready,
+          C->s32.ptrs(), C->s64.ptrs(), C->f_clean, C->r32_clean, C->r32_ready,
           C->s32.prof_kind, C->s64.prof_kind};
 }
 
 void set_work(kfbi_ctx* C, const WorkSet& w) {
   C->jumps = w.jumps, C->fitvals = w.fitvals, C->ejump = w.ejump, C->F = w.F, C->u = w.u, C->p = w.p;
   C->ru = w.ru, C->rscal = w.rscal, C->rpart = w.rpart, C->r32 = w.r32, C->r32b = w.r32b, C->x32 = w.x32;
-  C->flag = w.flag;
   if (C->mixed)
     C->s32.set(w.s32);
   else
@@ -1181,7 +1183,6 @@ WorkSet carve_work(const kfbi_ctx* C, Arena& a) {
   w.F = a.take<double>(4 * S.M);
   w.u = a.take<double>(3 * S.M);
   w.p = a.take<double>(S.M);
-  w.flag = a.take<int>(1);
   if (C->mixed) {
     w.ru = a.take<double>(4 * S.M);
     w.r32 = a.take<float>(4 * S.M);
@@ -1225,8 +1226,9 @@ void ensure_batch(kfbi_ctx* C, int nrhs) {
   C->bat_A = A;
   C->bat_act = dalloc<int>(3 * nrhs, C->owned);
   if (C->hpin_bat) (void)hipHostFree(C->hpin_bat);
-  C->hpin_bat = nullptr;
+  C->hpin_bat = C->hpin_bat_dev = nullptr;
   HIPCHK(hipHostMalloc((void**)&C->hpin_bat, 2 * nrhs * sizeof(double), hipHostMallocDefault));
+  HIPCHK(hipHostGetDevicePointer((void**)&C->hpin_bat_dev, C->hpin_bat, 0));
   auto grow_rr = [&](auto& sv) {
     if (sv.host_rr) (void)hipHostFree(sv.host_rr);
     sv.host_rr = nullptr;

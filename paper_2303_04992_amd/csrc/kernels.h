@@ -90,9 +90,11 @@ hipError_t launch_cg_coef(const double* rpart, int nr, const double* zpart, int 
 // [9] sum of the right-hand side
 enum ReduceOp { R_SUM = 2, R_RESNORM = 4, R_RESNORM0 = 5 };
 // (out, when given, is a work buffer like scal: it moves with the right-hand side in a batch)
+// hdst (optional): the residual norm of R_RESNORM / R_RESNORM0 also goes to hdst[rhs]
+// (a device address of pinned host memory)
 hipError_t launch_reduce(const double* partials, int nparts, int nper, double* scal, int op, int stokes,
                          int64_t M, hipStream_t s, double* out = nullptr,
-                         const Bat& bt = Bat());  // R_SUM: *out (or scal[5])
+                         const Bat& bt = Bat(), double* hdst = nullptr);  // R_SUM: *out (or scal[5])
 template <typename T>
 hipError_t launch_dot_partials(int64_t M, const T* a, const T* b, double* partials, int nblocks, hipStream_t s);
 template <typename T>
@@ -159,7 +161,8 @@ hipError_t launch_fit_T(int64_t n, const int64_t* ptr, const int64_t* entry, con
 hipError_t launch_export_u(int N, const double* u_int, double* u_ext, hipStream_t s);
 hipError_t launch_import_u(int N, const double* u_ext, double* u_int, hipStream_t s);
 hipError_t launch_scatter_add(int64_t n, const int64_t* idx, const double* v, double* F, hipStream_t s);
-hipError_t launch_check_finite(int64_t n, const double* a, int* flag, hipStream_t s);
+// *flag = tag if any a[i] is not finite (flag: a device address, pinned host memory in practice)
+hipError_t launch_check_finite(int64_t n, const double* a, int* flag, int tag, hipStream_t s);
 // out[i] = (To) in[i]
 template <typename Ti, typename To>
 hipError_t launch_convert(int64_t n, const Ti* in, To* out, hipStream_t s);

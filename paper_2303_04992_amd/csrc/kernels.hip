@@ -1458,9 +1458,12 @@ __global__ __launch_bounds__(EW_NT) void k_sum_partials(int64_t M, const T* __re
   if (threadIdx.x == 0) partials[blockIdx.x] = t;
 }
 
+// hdst (may be null): pinned host memory that also receives the residual norm scal[5] of the
+// R_RESNORM / R_RESNORM0 ops, one double per right-hand side (read by the host after a
+// synchronisation, with no copy operation on the stream)
 __global__ __launch_bounds__(EW_NT) void k_reduce(const double* __restrict__ partials, int nparts, int nper,
                                                double* __restrict__ scal, int op, int stokes, int64_t M,
-                                               double* __restrict__ out, Bat bt) {
+                                               double* __restrict__ out, Bat bt, double* __restrict__ hdst) {
   __shared__ double red[EW_NT / 64];
   if (rhs_skipped(bt)) return;
   partials = wb(partials, bt);
@@ -1477,6 +1480,10 @@ __global__ __launch_bounds__(EW_NT) void k_reduce(const double* __restrict__ par
       // R_RESNORM0 also keeps the mean of the pressure part in scal[6]
       scal[5] = tot[0] + tot[2] - (stokes ? tot[1] * tot[1] / (double)M : 0.0);
       if (op == R_RESNORM0) scal[6] = tot[1] / (double)M;
+      if (hdst) {
+        hdst[blockIdx.z] = scal[5];
+        __threadfence_system();
+      }
     } else {
       if (out)
         *out = tot[0];
@@ -1955,9 +1962,15 @@ __global__ void k_convert(int64_t n, const Ti* __restrict__ in, To* __restrict__
     out[i] = (To)in[i];
 }
 
-__global__ void k_check_finite(int64_t n, const double* __restrict__ a, int* __restrict__ flag) {
+// flag: pinned host memory (its device address), read by the host after a synchronisation;
+// a non-finite entry stores the call's tag there, so a store left over from an earlier check
+// can never be taken for this one
+__global__ void k_check_finite(int64_t n, const double* __restrict__ a, int* __restrict__ flag, int tag) {
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-    if (!isfinite(a[i])) *flag = 1;  // benign race: every writer stores 1
+    if (!isfinite(a[i])) {
+      *flag = tag;  // benign race: every writer stores the same value
+      __threadfence_system();
+    }
 }
 
 // ---------------------------------------------------------------------------------------
@@ -2181,9 +2194,9 @@ hipError_t launch_cg_coef(const double* rpart, int nr, const double* zpart, int 
 }
 
 hipError_t launch_reduce(const double* partials, int nparts, int nper, double* scal, int op, int stokes, int64_t M,
-                         hipStream_t s, double* out, const Bat& bt) {
+                         hipStream_t s, double* out, const Bat& bt, double* hdst) {
   hipLaunchKernelGGL(k_reduce, dim3(1, 1, bt.nb), dim3(EW_NT), 0, s, partials, nparts, nper, scal, op, stokes, M, out,
-                     bt);
+                     bt, hdst);
   return hipGetLastError();
 }
 
@@ -2318,8 +2331,8 @@ template hipError_t launch_convert<double, float>(int64_t, const double*, float*
 template hipError_t launch_convert<float, double>(int64_t, const float*, double*, hipStream_t);
 template hipError_t launch_convert<double, double>(int64_t, const double*, double*, hipStream_t);
 
-hipError_t launch_check_finite(int64_t n, const double* a, int* flag, hipStream_t s) {
-  hipLaunchKernelGGL(k_check_finite, dim3(ew_blocks(n)), dim3(256), 0, s, n, a, flag);
+hipError_t launch_check_finite(int64_t n, const double* a, int* flag, int tag, hipStream_t s) {
+  hipLaunchKernelGGL(k_check_finite, dim3(ew_blocks(n)), dim3(256), 0, s, n, a, flag, tag);
   return hipGetLastError();
 }
 
