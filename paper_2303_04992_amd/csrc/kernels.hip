@@ -501,17 +501,23 @@ struct XmidRegs {
 };
 
 // LDS of the register-path x pass: the transform work area, then (float32) the tables the pass
-// reads between its transforms: pass-1 twiddles tw[n2 k1] (n2, k1 < R1), mk and the x
-// eigenvalues of the block's component, copied once per block so that no table read waits
-// behind the tile's outstanding sample loads.  Float64 blocks keep the tables in global memory
-// (their larger entries would cost a resident block per compute unit).
+// reads between its transforms: the pass twiddles tw[i] (i <= (M - 1)(R1 - 1), which covers the
+// second-pass twiddles of three passes too), mk and the x eigenvalues of the block's component,
+// copied once per block so that no table read waits behind the tile's outstanding sample loads.
+// Only where the tables keep the resident blocks per compute unit; float64 blocks keep them in
+// global memory (their larger entries would cost a resident block per compute unit).
+template <typename T, int N, int KF>
+struct XmidRegs3;
 template <typename T, int N>
 struct XmidLds {
   using S = TileCfg<T, N, DCT2>;
-  static constexpr bool TABLES = XmidRegs<T, N, DCT2>::ok && XmidRegs<T, N, DST2>::ok && sizeof(T) == 4;
-  static constexpr int NTW = (S::R1 - 1) * (S::R1 - 1) + 1;
+  static constexpr bool REGS = (XmidRegs<T, N, DCT2>::ok && XmidRegs<T, N, DST2>::ok) ||
+                               (XmidRegs3<T, N, DCT2>::ok && XmidRegs3<T, N, DST2>::ok);
+  static constexpr int NTW = (S::M - 1) * (S::R1 - 1) + 1;
   static constexpr size_t TAB_OFF = (S::BYTES + 15) / 16 * 16;
-  static constexpr size_t BYTES = TABLES ? TAB_OFF + (size_t)(NTW + N) * sizeof(C2<T>) + (size_t)N * sizeof(T) : S::BYTES;
+  static constexpr size_t TAB_BYTES = TAB_OFF + (size_t)(NTW + N) * sizeof(C2<T>) + (size_t)N * sizeof(T);
+  static constexpr bool TABLES = REGS && sizeof(T) == 4 && 163840 / TAB_BYTES >= 163840 / S::BYTES;
+  static constexpr size_t BYTES = TABLES ? TAB_BYTES : S::BYTES;
 };
 
 template <typename T, int N, int KF, int KI>
@@ -869,8 +875,15 @@ __device__ void xmid_body(T* lds, T* field, int mc, double mu, const Tab<T>& tb)
   const TileAddr a = tile_addr<S::W, N>(0, tile);
   const GlobSrc<T> src{field, a.base, a.nstride};
   C2<T> zs[S::PT1][S::R1];
-  if constexpr (XmidRegs<T, N, KF>::ok) {
-    using X = XmidLds<T, N>;
+  using X = XmidLds<T, N>;
+  if constexpr (X::REGS) {
+    constexpr bool THREE = XmidRegs3<T, N, KF>::ok;
+    auto run = [&](const Tab<T>& t, const T* lxt, T ly, const T(&lz)[2]) {
+      if constexpr (THREE)
+        xmid_tile_regs3<T, N, KF, KI>(lds, field, tile, mc, mu, t, zs, lxt, ly, lz);
+      else
+        xmid_tile_regs<T, N, KF, KI>(lds, field, tile, mc, mu, t, zs, lxt, ly, lz);
+    };
     // y and z eigenvalues of the thread's two pencils, the x eigenvalues of the component
     const int yi = tile / (N / S::W), z0 = (tile % (N / S::W)) * S::W, j = threadIdx.x % S::NJ;
     const T ly = (mc == 1) ? tb.sg2[yi] : tb.sg2s[yi];
@@ -918,19 +931,11 @@ __device__ void xmid_body(T* lds, T* field, int mc, double mu, const Tab<T>& tb)
       Tab<T> tl = tb;
       tl.tw = ltw;
       tl.mk = lmk;
-      xmid_tile_regs<T, N, KF, KI>(lds, field, tile, mc, mu, tl, zs, lsg, ly, lz);
+      run(tl, lsg, ly, lz);
     } else {
       fft_gather<T, N, KF>([&](int jj, int n) { return pre_sample<T, N, KF>(src, tb, jj, n); }, zs);
-      xmid_tile_regs<T, N, KF, KI>(lds, field, tile, mc, mu, tb, zs, gx, ly, lz);
+      run(tb, gx, ly, lz);
     }
-  } else if constexpr (XmidRegs3<T, N, KF>::ok && XmidRegs3<T, N, KI>::ok) {
-    const int yi = tile / (N / S::W), z0 = (tile % (N / S::W)) * S::W, j = threadIdx.x % S::NJ;
-    const T ly = (mc == 1) ? tb.sg2[yi] : tb.sg2s[yi];
-    T lz[2];
-#pragma unroll
-    for (int w = 0; w < 2; ++w) lz[w] = (mc == 2) ? tb.sg2[z0 + 2 * j + w] : tb.sg2s[z0 + 2 * j + w];
-    fft_gather<T, N, KF>([&](int jj, int n) { return pre_sample<T, N, KF>(src, tb, jj, n); }, zs);
-    xmid_tile_regs3<T, N, KF, KI>(lds, field, tile, mc, mu, tb, zs, (mc == 0) ? tb.sg2 : tb.sg2s, ly, lz);
   } else {
     fft_gather<T, N, KF>([&](int j, int n) { return pre_sample<T, N, KF>(src, tb, j, n); }, zs);
     xmid_tile<T, N, KF, KI>(lds, field, tile, mc, mu, tb, zs);

@@ -73,8 +73,10 @@ struct TileCfg {
   static constexpr int PAD[3] = {KFBI_LDS_PAD};
   static constexpr int P2 = M + PAD[0];                                              // padded row
   static constexpr int YS = R1 * P2 + PAD[1];                // job stride of the transpose buffer
-  static constexpr int P3 = R3 + 1;                          // padded row of the second transpose
-  static constexpr int YS3 = R1 * R2 * P3 + PAD[1];          // its job stride
+  // second transpose (three passes): rows of R3 unpadded (the lanes of a 16-lane group differ
+  // in the job only, both when it is written and when it is read), odd job stride
+  static constexpr int P3 = R3;
+  static constexpr int YS3 = R1 * R2 * P3 + PAD[1];
   static constexpr int ZS = L + PAD[2];                      // job stride of the spectra
   static constexpr int NT_CAP = N >= 512 ? 512 : 256;
   static constexpr int NT = (NJ * M > NT_CAP) ? NT_CAP : (NJ * M > 64) ? NJ * M : 64;  // threads
