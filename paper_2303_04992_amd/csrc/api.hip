@@ -426,6 +426,13 @@ struct MacSolver {
   int solve(const T* Fu, const T* Fp, T* u, T* p, double rtol, int maxit, const std::vector<char>* live = nullptr,
             std::vector<int>* its = nullptr) {
     const int NB = bt.nb;
+    // the CG iterate x lives in the caller's p itself (no copy after the solve)
+    struct XGuard {
+      T*& x;
+      T* own;
+      ~XGuard() { x = own; }
+    } xguard{x, x};
+    if (p) x = p;
     int nlive = 1;
     set_live(live, nlive);
     auto is_live = [&](int r) { return !live || (*live)[r]; };
@@ -563,11 +570,6 @@ struct MacSolver {
       pass(m == 1 ? DST1 : DST3, 1, um, um);
       pass(m == 2 ? DST1 : DST3, 2, um, um);
     }
-    if (p) {
-      for (int rr = 0; rr < NB; ++rr)
-        if (is_live(rr)) HIPCHK(hipMemcpyAsync(at(p, rr), at(x, rr), M * sizeof(T), hipMemcpyDeviceToDevice, s));
-      count(2);
-    }
     cur = bt;
     nact = 1;
     if (prof_used) {
@@ -641,6 +643,8 @@ struct kfbi_ctx {
   // F is zero outside the irregular nodes (the correction pass then assigns those and no clear
   // of the 4 N^3 values is needed); false after any other writer of F
   bool f_clean = false;
+  // the last mac_solve left its velocity in x32 (lean mixed solve; C->u and C->p not written)
+  bool u_x32 = false;
   // pinned host scalars written by kernels and read after a later synchronisation (hflag: the
   // tag of the current call's input check if it saw a non-finite value), their device
   // addresses, and the stage clock of a call
@@ -929,8 +933,15 @@ void assemble_rhs(kfbi_ctx* C, const double* phi, bool vol) {
 }
 
 // float64 MAC solve of C->F into C->u, C->p (either directly or by mixed refinement)
-int mac_solve(kfbi_ctx* C, const double* F, double* u, double* p, kfbi_info* info) {
+// lean (evaluations of K phi): only the velocity is needed, and only where the interpolation
+// reads it.  The mixed form then checks its first refinement round with a norms-only residual
+// pass; when every right-hand side meets the tolerance there, the float64 iterate of that round
+// is never stored: C->u_x32 is set and the velocity is to be read from x32 (launch_interp_x32),
+// the pressure is left unset.  Otherwise the full first-round pass stores the iterate and the
+// rounds go on as usual.
+int mac_solve(kfbi_ctx* C, const double* F, double* u, double* p, kfbi_info* info, bool lean = false) {
   const Setup& S = C->S;
+  C->u_x32 = false;
   const int64_t M = S.M;
   hipStream_t s = C->s;
   const Bat& bt = C->bt;
@@ -1000,9 +1011,10 @@ int mac_solve(kfbi_ctx* C, const double* F, double* u, double* p, kfbi_info* inf
     double* nu = (rounds == 0 || cu != u) ? u : C->ru;
     double* np = (rounds == 0 || cu != u) ? p : C->ru + 3 * M;
     C->clock.mark(ST_CG, s);
+    const bool norms_only = lean && rounds == 0;
     HIPCHK(launch_refine_residual(rounds == 0, S.N, S.h, S.mu, c, cu, cp, C->x32, F, shift, nu, np, C->r32b, C->rpart,
-                                  NP, s, bref));
-    C->bytes_extra += (rounds == 0 ? 96.0 : 128.0) * Md * nlive;
+                                  NP, s, bref, norms_only));
+    C->bytes_extra += (norms_only ? 48.0 : rounds == 0 ? 96.0 : 128.0) * Md * nlive;
     cu = nu;
     cp = np;
     HIPCHK(launch_reduce(C->rpart, NP, 3, C->rscal, R_RESNORM, stokes, M, s, nullptr, bref, hrn_dev));
@@ -1018,6 +1030,21 @@ int mac_solve(kfbi_ctx* C, const double* F, double* u, double* p, kfbi_info* inf
         in_ru[r] = nu != u;
         if (NB > 1) HIPCHK(launch_fill<int>(1, const_cast<int*>(bref.act) + r, 0, s));
       }
+    }
+    if (norms_only) {
+      if (nlive == 0) {  // the velocity stays in x32
+        C->u_x32 = true;
+        if (info) {
+          info->cg_iters += total;
+          info->refine_rounds = rounds;
+        }
+        return total;
+      }
+      // a right-hand side refines further: the full first-round pass stores the iterate of
+      // every right-hand side of the call (and the residual of the next round)
+      HIPCHK(launch_refine_residual(true, S.N, S.h, S.mu, c, u, p, C->x32, F, shift, u, p, C->r32b, C->rpart, NP, s,
+                                    bt));
+      C->bytes_extra += 96.0 * Md * NB;
     }
   }
   for (int r = 0; r < NB; ++r)
@@ -1052,9 +1079,12 @@ void eval_impl(kfbi_ctx* C, const double* phi, double* out, bool vol, kfbi_info*
   hipStream_t s = C->s;
   // stage times from events on the stream (no synchronisation between the stages)
   assemble_rhs(C, phi, vol);
-  mac_solve(C, C->F, C->u, C->p, info);
+  mac_solve(C, C->F, C->u, C->p, info, true);
   C->clock.mark(ST_INTERP, s);
-  HIPCHK(launch_interp(S.n, C->itp_idx, C->itp_w, C->u, C->ejump, out, s, C->bt));
+  if (C->u_x32)
+    HIPCHK(launch_interp_x32(S.n, C->itp_idx, C->itp_w, C->x32, S.N, C->ejump, out, s, C->bt));
+  else
+    HIPCHK(launch_interp(S.n, C->itp_idx, C->itp_w, C->u, C->ejump, out, s, C->bt));
   if (C->cfg.trace == KFBI_TRACE_AVERAGE)
     HIPCHK(launch_stab(S.n, C->sv_ptr, C->sv_idx, C->sv_w, C->stab_a, phi, out, s, C->bt));
   C->bytes_extra += C->bytes_interp * C->bt.nb;

@@ -116,10 +116,12 @@ hipError_t launch_axpby(int64_t n, T* y, double a, const T* x, double b, hipStre
 hipError_t launch_refine_prep(int64_t M, const double* F, float* r32, double* partials, int nparts, hipStream_t s,
                               const Bat& bt = Bat());
 // un, pn = u, p (+ 0 if first) + x32; r32 = float32 of the float64 residual F - A(un, pn) (pressure
-// part minus *shift); partial sums
+// part minus *shift); partial sums.  norms_only (first round only): the partial sums alone,
+// un, pn and r32 are not written (may be null)
 hipError_t launch_refine_residual(bool first, int N, double h, double mu, double c, const double* u, const double* p,
                                   const float* x32, const double* F, const double* shift, double* un, double* pn,
-                                  float* r32, double* partials, int nparts, hipStream_t s, const Bat& bt = Bat());
+                                  float* r32, double* partials, int nparts, hipStream_t s, const Bat& bt = Bat(),
+                                  bool norms_only = false);
 
 // ---- surface stages (float64)
 // jumps of every crossing (jmap component-major: jmap[(r * 18 + c) * T + t]) and the fit
@@ -148,6 +150,10 @@ hipError_t launch_stab_T(int64_t n, const int64_t* ptr, const int32_t* row, cons
                          const double* w, double* out, hipStream_t s);
 hipError_t launch_interp(int64_t n, const int64_t* idx, const double* w, const double* u, const double* ejump,
                          double* out, hipStream_t s, const Bat& bt = Bat());
+// the same with the velocity given by the float32 first-round solution x32 of the mixed solve
+// (face 0 of each component at zero); N a power of two
+hipError_t launch_interp_x32(int64_t n, const int64_t* idx, const double* w, const float* x32, int N,
+                             const double* ejump, double* out, hipStream_t s, const Bat& bt = Bat());
 // adjoint
 hipError_t launch_interp_T(int64_t nnode, const int64_t* ptr, const int64_t* node, const int32_t* row,
                            const double* w, const double* wbar, double* ubar, hipStream_t s);

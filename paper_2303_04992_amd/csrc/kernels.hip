@@ -1577,7 +1577,9 @@ __global__ __launch_bounds__(EW_NT) void k_refine_prep(int64_t M, const double* 
 // (Stokes: the mean of F_p, which the residual keeps; left in, the float32 inner solve would
 // have to cancel an O(|F|) constant against an O(1e-5 |F|) residual and stagnates).  Neighbour values of u' are formed on the fly, so u', p' go to
 // buffers other than u, p.
-template <bool FIRST>
+// WRITE = false: the residual norms only (the partial sums); nothing else is written, for a
+// first round whose result is then read from x32 itself when it meets the tolerance
+template <bool FIRST, bool WRITE>
 __global__ __launch_bounds__(EW_NT) void k_refine_residual(int N, double h, double mu, double cc,
                                                         const double* __restrict__ u, const double* __restrict__ p,
                                                         const float* __restrict__ x32, const double* __restrict__ F,
@@ -1644,13 +1646,17 @@ __global__ __launch_bounds__(EW_NT) void k_refine_residual(int N, double h, doub
       div += (hi_m - c) * ih;
       const double gp = (pc - P(id[m] > 0 ? i - st[m] : i)) * ih;  // cells a-1, a
       const double r = (id[m] > 0) ? F[(int64_t)m * M + i] - (-mu * lap + gp) : 0.0;
-      un[(int64_t)m * M + i] = c;
-      r32[(int64_t)m * M + i] = (float)r;
+      if constexpr (WRITE) {
+        un[(int64_t)m * M + i] = c;
+        r32[(int64_t)m * M + i] = (float)r;
+      }
       su += r * r;
     }
     const double rp = F[(int64_t)3 * M + i] - (div + cc * pc) - sh;
-    pn[i] = pc;
-    r32[(int64_t)3 * M + i] = (float)rp;
+    if constexpr (WRITE) {
+      pn[i] = pc;
+      r32[(int64_t)3 * M + i] = (float)rp;
+    }
     sp += rp;
     spp += rp * rp;
   }
@@ -1822,6 +1828,32 @@ __global__ void k_interp(int64_t n, const int64_t* __restrict__ idx, const doubl
   double s = ejump[r];
 #pragma unroll
   for (int q = 0; q < 10; ++q) s += w[10 * r + q] * u[idx[10 * r + q]];
+  out[r] = s;
+}
+
+// The same from the float32 first-round solution x32 of the mixed solve (velocity components
+// in the layout of u): the float64 iterate of that round is x32 itself with face 0 of each
+// component (the box face) at zero, read here without being stored.
+__global__ void k_interp_x32(int64_t n, const int64_t* __restrict__ idx, const double* __restrict__ w,
+                             const float* __restrict__ x32, int lg, const double* __restrict__ ejump,
+                             double* __restrict__ out, Bat bt) {
+  if (rhs_skipped(bt)) return;
+  x32 = wb(x32, bt);
+  ejump = wb(ejump, bt);
+  out = ub(out, bt);
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= 3 * n) return;
+  const int64_t M = (int64_t)1 << (3 * lg), mask = ((int64_t)1 << lg) - 1;
+  double s = ejump[r];
+#pragma unroll
+  for (int q = 0; q < 10; ++q) {
+    const int64_t g = idx[10 * r + q];
+    const int m = (int)(g >> (3 * lg));
+    const int64_t i = g & (M - 1);
+    const int64_t face = (i >> (lg * (2 - m))) & mask;  // index along axis m
+    const double v = face == 0 ? 0.0 : (double)x32[g];
+    s += w[10 * r + q] * v;
+  }
   out[r] = s;
 }
 
@@ -2167,7 +2199,7 @@ hipError_t launch_ypair(int N, bool inverse, const T* in0, const T* in1, T* out0
     } else if (inverse) {                                                                                 \
       ensure_lds(k_ypair_inv<T, NN>, lds);                                                                \
       hipLaunchKernelGGL((k_ypair_inv<T, NN>), dim3(blocks, 1, bt.nb), dim3(S::NT), lds, s, in0, in1, out0, t, bt); \
-    } else if (sizeof(T) == 4 && NN <= 512 && PipeCfg<T, NN, DCT2>::BYTES <= 163840) {                    \
+    } else if (sizeof(T) == 4 && NN <= 512 && PipeCfg<T, NN, DCT2>::BYTES <= 163840) { \
       using PF = PipeCfg<T, NN, DCT2>;                                                                    \
       ensure_lds(k_ypair_fwd_pipe<T, NN>, PF::BYTES);                                                     \
       static std::atomic<int> per_cu_f{0};                                                                \
@@ -2240,14 +2272,19 @@ hipError_t launch_refine_prep(int64_t M, const double* F, float* r32, double* pa
 }
 hipError_t launch_refine_residual(bool first, int N, double h, double mu, double c, const double* u, const double* p,
                                   const float* x32, const double* F, const double* shift, double* un, double* pn,
-                                  float* r32, double* partials, int nparts, hipStream_t s, const Bat& bt) {
+                                  float* r32, double* partials, int nparts, hipStream_t s, const Bat& bt,
+                                  bool norms_only) {
   if (nparts % 8) return hipErrorInvalidValue;  // XCD-aware chunking needs a multiple of 8 blocks
-  if (first)
-    hipLaunchKernelGGL(k_refine_residual<true>, dim3(nparts, 1, bt.nb), dim3(EW_NT), 0, s, N, h, mu, c, u, p, x32, F,
-                       shift, un, pn, r32, partials, bt);
+  if (norms_only && !first) return hipErrorInvalidValue;
+  if (norms_only)
+    hipLaunchKernelGGL((k_refine_residual<true, false>), dim3(nparts, 1, bt.nb), dim3(EW_NT), 0, s, N, h, mu, c, u, p,
+                       x32, F, shift, un, pn, r32, partials, bt);
+  else if (first)
+    hipLaunchKernelGGL((k_refine_residual<true, true>), dim3(nparts, 1, bt.nb), dim3(EW_NT), 0, s, N, h, mu, c, u, p,
+                       x32, F, shift, un, pn, r32, partials, bt);
   else
-    hipLaunchKernelGGL(k_refine_residual<false>, dim3(nparts, 1, bt.nb), dim3(EW_NT), 0, s, N, h, mu, c, u, p, x32, F,
-                       shift, un, pn, r32, partials, bt);
+    hipLaunchKernelGGL((k_refine_residual<false, true>), dim3(nparts, 1, bt.nb), dim3(EW_NT), 0, s, N, h, mu, c, u,
+                       p, x32, F, shift, un, pn, r32, partials, bt);
   return hipGetLastError();
 }
 
@@ -2279,6 +2316,13 @@ hipError_t launch_correct(int64_t nirr, const int64_t* irr_node, const int64_t* 
 hipError_t launch_interp(int64_t n, const int64_t* idx, const double* w, const double* u, const double* ejump,
                          double* out, hipStream_t s, const Bat& bt) {
   hipLaunchKernelGGL(k_interp, dim3(gb(3 * n), 1, bt.nb), dim3(256), 0, s, n, idx, w, u, ejump, out, bt);
+  return hipGetLastError();
+}
+hipError_t launch_interp_x32(int64_t n, const int64_t* idx, const double* w, const float* x32, int N,
+                             const double* ejump, double* out, hipStream_t s, const Bat& bt) {
+  if (N < 2 || (N & (N - 1))) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_interp_x32, dim3(gb(3 * n), 1, bt.nb), dim3(256), 0, s, n, idx, w, x32, __builtin_ctz(N),
+                     ejump, out, bt);
   return hipGetLastError();
 }
 hipError_t launch_stab(int64_t n, const int64_t* ptr, const int32_t* idx, const double* sw, const double* a,

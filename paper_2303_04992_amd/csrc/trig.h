@@ -119,6 +119,18 @@ __host__ __device__ __forceinline__ C2<T> wR(int m) {
 }
 
 // R-point DFT in registers, R in {1, 2, 4, 8, 16, 32}; INV selects the exponent sign
+// u W_R^m for a literal m: the powers of i as sign changes and swaps (a product with the
+// literal 0 of such a twiddle is not folded away under IEEE rules)
+template <typename T, int R, bool INV>
+__host__ __device__ __forceinline__ C2<T> twR(C2<T> u, int m) {
+  const int q = (m * (32 / R)) & 31;
+  if (q == 0) return u;
+  if (q == 16) return {-u.x, -u.y};
+  if (q == 8) return INV ? C2<T>{-u.y, u.x} : C2<T>{u.y, -u.x};   // W = i or -i
+  if (q == 24) return INV ? C2<T>{u.y, -u.x} : C2<T>{-u.y, u.x};  // W = -i or i
+  return cmul(u, wR<T, R, INV>(m));
+}
+
 template <typename T, int R, bool INV>
 __host__ __device__ __forceinline__ void dftR(C2<T>* v) {
   if constexpr (R == 2) {
@@ -146,7 +158,7 @@ __host__ __device__ __forceinline__ void dftR(C2<T>* v) {
       for (int n1 = 0; n1 < 4; ++n1) u[n1] = v[B * n1 + n2];
       dftR<T, 4, INV>(u);
 #pragma unroll
-      for (int k1 = 0; k1 < 4; ++k1) t[k1 * B + n2] = (n2 * k1 == 0) ? u[k1] : cmul(u[k1], wR<T, R, INV>(n2 * k1));
+      for (int k1 = 0; k1 < 4; ++k1) t[k1 * B + n2] = twR<T, R, INV>(u[k1], n2 * k1);
     }
 #pragma unroll
     for (int k1 = 0; k1 < 4; ++k1) {
