@@ -423,8 +423,10 @@ struct MacSolver {
   // live right-hand side in lockstep; each stops by the same rule, at the same iteration, as
   // its own solve would (its flag in act_cg then skips it), and its iteration count goes to
   // its[r].
+  // mean_free = false (Stokes only): the mean of p is left as the iterations made it (a
+  // rounding drift; the velocity does not depend on it), for callers that project it later
   int solve(const T* Fu, const T* Fp, T* u, T* p, double rtol, int maxit, const std::vector<char>* live = nullptr,
-            std::vector<int>* its = nullptr) {
+            std::vector<int>* its = nullptr, bool mean_free = true) {
     const int NB = bt.nb;
     // the CG iterate x lives in the caller's p itself (no copy after the solve)
     struct XGuard {
@@ -549,7 +551,7 @@ struct MacSolver {
     }
     cur = with_act(act_live);
     nact = nlive;
-    project_mean(x);
+    if (mean_free || c > 0) project_mean(x);
     if (c > 0) {
       HIPCHK(launch_add_scalar<T>(M, x, scal, 9, 1.0 / ((double)M * c), s, cur));  // + mean(b) / c
       count(2);
@@ -645,6 +647,10 @@ struct kfbi_ctx {
   bool f_clean = false;
   // the last mac_solve left its velocity in x32 (lean mixed solve; C->u and C->p not written)
   bool u_x32 = false;
+  // per z-pencil flags of the components of F that can be nonzero while F is clean (the
+  // irregular nodes): the refinement passes read F only there
+  uint8_t* fmask = nullptr;
+  double fmask_frac = 1;  // share of the (pencil, component) pairs flagged
   // pinned host scalars written by kernels and read after a later synchronisation (hflag: the
   // tag of the current call's input check if it saw a non-finite value), their device
   // addresses, and the stage clock of a call
@@ -759,6 +765,17 @@ kfbi_status kfbi_create(const kfbi_config* cfg_in, kfbi_ctx** out) {
     C->emap = dupload(em, o, s);
     C->efmap = dupload(efm, o, s);
     C->irr_node = dupload(S.irr_node, o, s);
+    {  // per z-pencil (x, y): bit c set iff component c of F has an irregular node in the pencil
+      std::vector<uint8_t> fm((size_t)S.N * S.N, 0);
+      for (int64_t node : S.irr_node) {
+        const int64_t c = node / S.M, cell = node % S.M;
+        fm[(size_t)(cell / S.N)] |= (uint8_t)(1u << c);
+      }
+      int64_t bits = 0;
+      for (uint8_t v : fm) bits += __builtin_popcount(v);
+      C->fmask_frac = (double)bits / (4.0 * (double)fm.size());
+      C->fmask = dupload(fm, o, s);
+    }
     C->irr_ptr = dupload(S.irr_ptr, o, s);
     C->arm_t = dupload(S.arm_t, o, s);
     C->arm_o = dupload(S.arm_o, o, s);
@@ -994,6 +1011,9 @@ int mac_solve(kfbi_ctx* C, const double* F, double* u, double* p, kfbi_info* inf
   C->r32_ready = false;
   HIPCHK(launch_reduce(C->rpart, NP, 3, C->rscal, R_RESNORM0, stokes, M, s, nullptr, bt, hf0_dev));
   const double* shift = stokes ? C->rscal + 6 : nullptr;  // mean of F_p (Stokes)
+  // F zero outside the irregular nodes (the corrections alone): read only in their pencils
+  const uint8_t* fm = (F == C->F && C->f_clean) ? C->fmask : nullptr;
+  const double fbytes = 32.0 * (fm ? C->fmask_frac : 1.0);  // F bytes read per cell
   // the iterate alternates between (u, p) and the spare float64 fields (neighbour values of
   // the old iterate are read while the new one is written); in_ru[r]: where right-hand side r
   // left its final iterate
@@ -1005,7 +1025,10 @@ int mac_solve(kfbi_ctx* C, const double* F, double* u, double* p, kfbi_info* inf
     if (rounds >= 30) throw std::runtime_error("ENOCONV: mixed refinement did not converge");
     const float* rin = (rounds == 0) ? C->r32 : C->r32b;
     std::fill(its.begin(), its.end(), 0);
-    int it = C->s32.solve(rin, rin + 3 * M, C->x32, C->x32 + 3 * M, C->cfg.inner_rtol, C->cfg.cg_maxit, &live, &its);
+    // Stokes: the pressure correction enters the residual only through its gradient, and the
+    // final pressure is projected after the rounds
+    int it = C->s32.solve(rin, rin + 3 * M, C->x32, C->x32 + 3 * M, C->cfg.inner_rtol, C->cfg.cg_maxit, &live, &its,
+                          !stokes);
     if (it < 0) throw std::runtime_error("ENOCONV: inner float32 CG reached cg_maxit");
     total += NB == 1 ? it : sum_its();
     double* nu = (rounds == 0 || cu != u) ? u : C->ru;
@@ -1013,8 +1036,8 @@ int mac_solve(kfbi_ctx* C, const double* F, double* u, double* p, kfbi_info* inf
     C->clock.mark(ST_CG, s);
     const bool norms_only = lean && rounds == 0;
     HIPCHK(launch_refine_residual(rounds == 0, S.N, S.h, S.mu, c, cu, cp, C->x32, F, shift, nu, np, C->r32b, C->rpart,
-                                  NP, s, bref, norms_only));
-    C->bytes_extra += (norms_only ? 48.0 : rounds == 0 ? 96.0 : 128.0) * Md * nlive;
+                                  NP, s, bref, norms_only, fm));
+    C->bytes_extra += ((norms_only ? 16.0 : rounds == 0 ? 64.0 : 96.0) + fbytes) * Md * nlive;
     cu = nu;
     cp = np;
     HIPCHK(launch_reduce(C->rpart, NP, 3, C->rscal, R_RESNORM, stokes, M, s, nullptr, bref, hrn_dev));
@@ -1043,8 +1066,8 @@ int mac_solve(kfbi_ctx* C, const double* F, double* u, double* p, kfbi_info* inf
       // a right-hand side refines further: the full first-round pass stores the iterate of
       // every right-hand side of the call (and the residual of the next round)
       HIPCHK(launch_refine_residual(true, S.N, S.h, S.mu, c, u, p, C->x32, F, shift, u, p, C->r32b, C->rpart, NP, s,
-                                    bt));
-      C->bytes_extra += 96.0 * Md * NB;
+                                    bt, false, fm));
+      C->bytes_extra += (64.0 + fbytes) * Md * NB;
     }
   }
   for (int r = 0; r < NB; ++r)

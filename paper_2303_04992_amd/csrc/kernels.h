@@ -117,11 +117,12 @@ hipError_t launch_refine_prep(int64_t M, const double* F, float* r32, double* pa
                               const Bat& bt = Bat());
 // un, pn = u, p (+ 0 if first) + x32; r32 = float32 of the float64 residual F - A(un, pn) (pressure
 // part minus *shift); partial sums.  norms_only (first round only): the partial sums alone,
-// un, pn and r32 are not written (may be null)
+// un, pn and r32 are not written (may be null).  fmask (optional, N^2 bytes): per z-pencil (x, y)
+// bit c set where component c of F may be nonzero; F is read only there (zero elsewhere)
 hipError_t launch_refine_residual(bool first, int N, double h, double mu, double c, const double* u, const double* p,
                                   const float* x32, const double* F, const double* shift, double* un, double* pn,
                                   float* r32, double* partials, int nparts, hipStream_t s, const Bat& bt = Bat(),
-                                  bool norms_only = false);
+                                  bool norms_only = false, const uint8_t* fmask = nullptr);
 
 // ---- surface stages (float64)
 // jumps of every crossing (jmap component-major: jmap[(r * 18 + c) * T + t]) and the fit

@@ -1585,7 +1585,8 @@ __global__ __launch_bounds__(EW_NT) void k_refine_residual(int N, double h, doub
                                                         const float* __restrict__ x32, const double* __restrict__ F,
                                                         const double* __restrict__ shift, double* __restrict__ un,
                                                         double* __restrict__ pn, float* __restrict__ r32,
-                                                        double* __restrict__ partials, Bat bt) {
+                                                        double* __restrict__ partials, Bat bt,
+                                                        const uint8_t* __restrict__ fmask) {
   __shared__ double red[EW_NT / 64];
   if (rhs_skipped(bt)) return;
   u = wb(u, bt);
@@ -1619,9 +1620,15 @@ __global__ __launch_bounds__(EW_NT) void k_refine_residual(int N, double h, doub
   const int L = (blockIdx.x % 8) * (nb / 8) + blockIdx.x / 8;
   const int chunk = (M + nb - 1) / nb;
   const int i1 = (L + 1) * chunk < M ? (L + 1) * chunk : M;
+  // fmask (may be null): per z-pencil bits of the components of F that can be nonzero; a
+  // wavefront covers 64 cells of one pencil when N >= 64 and the chunks are 64-aligned, so its
+  // flags are read once per wavefront and the loads of zero F entries are skipped as a whole
+  const bool wave_pencil = N >= 64 && chunk % 64 == 0;
   double su = 0, sp = 0, spp = 0;
   for (int i = L * chunk + threadIdx.x; i < i1; i += EW_NT) {
     const int id[3] = {i >> (2 * lg), (i >> lg) & mask, i & mask};
+    unsigned fm = 0xFu;
+    if (fmask) fm = wave_pencil ? fmask[__builtin_amdgcn_readfirstlane(i >> lg)] : fmask[i >> lg];
     const double pc = P(i);
     double div = 0;
 #pragma unroll
@@ -1645,14 +1652,15 @@ __global__ __launch_bounds__(EW_NT) void k_refine_residual(int N, double h, doub
       }
       div += (hi_m - c) * ih;
       const double gp = (pc - P(id[m] > 0 ? i - st[m] : i)) * ih;  // cells a-1, a
-      const double r = (id[m] > 0) ? F[(int64_t)m * M + i] - (-mu * lap + gp) : 0.0;
+      const double fv = ((fm >> m) & 1u) ? F[(int64_t)m * M + i] : 0.0;
+      const double r = (id[m] > 0) ? fv - (-mu * lap + gp) : 0.0;
       if constexpr (WRITE) {
         un[(int64_t)m * M + i] = c;
         r32[(int64_t)m * M + i] = (float)r;
       }
       su += r * r;
     }
-    const double rp = F[(int64_t)3 * M + i] - (div + cc * pc) - sh;
+    const double rp = (((fm >> 3) & 1u) ? F[(int64_t)3 * M + i] : 0.0) - (div + cc * pc) - sh;
     if constexpr (WRITE) {
       pn[i] = pc;
       r32[(int64_t)3 * M + i] = (float)rp;
@@ -2273,18 +2281,18 @@ hipError_t launch_refine_prep(int64_t M, const double* F, float* r32, double* pa
 hipError_t launch_refine_residual(bool first, int N, double h, double mu, double c, const double* u, const double* p,
                                   const float* x32, const double* F, const double* shift, double* un, double* pn,
                                   float* r32, double* partials, int nparts, hipStream_t s, const Bat& bt,
-                                  bool norms_only) {
+                                  bool norms_only, const uint8_t* fmask) {
   if (nparts % 8) return hipErrorInvalidValue;  // XCD-aware chunking needs a multiple of 8 blocks
   if (norms_only && !first) return hipErrorInvalidValue;
   if (norms_only)
     hipLaunchKernelGGL((k_refine_residual<true, false>), dim3(nparts, 1, bt.nb), dim3(EW_NT), 0, s, N, h, mu, c, u, p,
-                       x32, F, shift, un, pn, r32, partials, bt);
+                       x32, F, shift, un, pn, r32, partials, bt, fmask);
   else if (first)
     hipLaunchKernelGGL((k_refine_residual<true, true>), dim3(nparts, 1, bt.nb), dim3(EW_NT), 0, s, N, h, mu, c, u, p,
-                       x32, F, shift, un, pn, r32, partials, bt);
+                       x32, F, shift, un, pn, r32, partials, bt, fmask);
   else
     hipLaunchKernelGGL((k_refine_residual<false, true>), dim3(nparts, 1, bt.nb), dim3(EW_NT), 0, s, N, h, mu, c, u,
-                       p, x32, F, shift, un, pn, r32, partials, bt);
+                       p, x32, F, shift, un, pn, r32, partials, bt, fmask);
   return hipGetLastError();
 }
 
