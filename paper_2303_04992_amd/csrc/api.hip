@@ -357,7 +357,7 @@ struct MacSolver {
   // C_0 = DCT_x DST_y DST_z, C_1 = DST_x DCT_y DST_z, C_2 = DST_x DST_y DCT_z (orthonormal);
   // order z, y, [x fused with the weights], y, z
   void zfwd(int mode = ZF_FUSED) {
-    count(mode == ZF_FUSED ? 9 : mode == ZF_FIRST ? 4 : 3);
+    count(mode == ZF_FUSED ? 9 : mode == ZF_FIRST ? 6 : 3);
     timed(prof_kind == KFBI_K_ZFWD && mode == ZF_FUSED,
           [&] { return launch_zfwd_cg<T>(N, mode, x, r, d, q, A, B, scal, rpart, tb, s, cur); });
   }
@@ -460,7 +460,9 @@ struct MacSolver {
     // (c > 0) the constant mode, whose eigenvalue c = 1/(lambda + mu) is the smallest of S and
     // grows the iteration count as nu -> 1/2, is solved exactly, mean(p) = mean(b) / c, and CG
     // runs on the mean-zero part.  Stokes (c = 0): P b, mean(p) = 0.
-    project_mean(b, 9);
+    // sum of b (kept in scal[9]) from the partial sums of the z inverse pass that formed it; the
+    // first forward z pass of the CG subtracts the mean
+    HIPCHK(launch_reduce(partials, nparts_x, 4, scal, R_SUM1, 1, M, s, scal + 9, cur));
     // 3. CG on S x = b.  Iteration k forms x_k, r_k (with alpha_{k-1}) and d_k in its first
     // pass, so x lags one step until the final x += alpha d.
     // The residual starts as b itself (b is not needed afterwards: the buffers swap roles), and
@@ -468,9 +470,7 @@ struct MacSolver {
     // first check (no synchronisation before the first iterations are queued; b = 0 converges
     // at that check with x = 0).
     mark(ST_CG);
-    HIPCHK(launch_fill<T>(M, x, T(0), s, cur));
-    count(1);
-    std::swap(r, b);
+    std::swap(r, b);  // x = 0 is set by the first forward z pass
     // Stop test.  Iteration k leaves in scal[7] the r_k.r_k that its forward z pass summed over
     // the updated residual r_k, and in scal[0] the recurrence estimate of |r_{k+1}|^2 (used
     // for beta only: it assumes the conjugacy of d_k and d_{k-1}).  With one iteration of

@@ -51,7 +51,8 @@ hipError_t launch_xmid(int N, T* A0, T* A1, T* A2, double mu, const DevTables<T>
                        const Bat& bt = Bat());
 // Forward z pass of the Schur matvec (A = DST-II_z v, B = DCT-II_z v) with the CG updates folded in:
 //   ZF_PLAIN  v = r (x, d, q, scal, rpart unused)
-//   ZF_FIRST  d = r, v = d; rpart[block] = partial r.r
+//   ZF_FIRST  r -= scal[9] / N^3 (the mean of r given its sum), d = r, x = 0, v = d;
+//             rpart[block] = partial r.r
 //   ZF_FUSED  x += alpha d; r -= alpha (q - mean q); d = r + beta d (scal[1], scal[2], scal[3]);
 //             v = d; rpart[block] = partial r.r of the updated r
 // rpart holds zfwd_blocks(N, sizeof(T)) doubles.
@@ -88,7 +89,8 @@ hipError_t launch_cg_coef(const double* rpart, int nr, const double* zpart, int 
 // ---- reductions (float64, deterministic)
 // scal layout: [0] |r_next|^2, [1] alpha, [2] beta, [3] mean q, [5] scratch sum, [6] aux, [7] r.r,
 // [9] sum of the right-hand side
-enum ReduceOp { R_SUM = 2, R_RESNORM = 4, R_RESNORM0 = 5 };
+// R_SUM: the sum of the first of nper values per block; R_SUM1: of the second (nper <= 4)
+enum ReduceOp { R_SUM = 2, R_RESNORM = 4, R_RESNORM0 = 5, R_SUM1 = 6 };
 // (out, when given, is a work buffer like scal: it moves with the right-hand side in a batch)
 // hdst (optional): the residual norm of R_RESNORM / R_RESNORM0 also goes to hdst[rhs]
 // (a device address of pinned host memory)

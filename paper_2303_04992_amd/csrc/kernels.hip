@@ -987,7 +987,8 @@ __device__ __forceinline__ void store_z_outputs(const T* lds, const Tab<T>& tb, 
 
 // Forward z pass of the Schur matvec with the CG vector updates folded in.
 //   ZF_PLAIN  A = DST-II_z r, B = DCT-II_z r (velocity back-substitution; r is only read)
-//   ZF_FIRST  d = r, then the transforms of d; partial sums of r.r
+//   ZF_FIRST  r -= mean r (the mean from the sum in scal[9]), d = r, x = 0, then the transforms of
+//             d; partial sums of r.r
 //   ZF_FUSED  x += alpha d, r -= alpha (q - mean q), d = r + beta d (alpha, beta, mean q of the
 //             previous iteration in scal[1..3]), then the transforms of d; partial sums of r.r
 // Every thread streams its vectors once; d stays in registers for the second transform.
@@ -1043,9 +1044,18 @@ __global__ __launch_bounds__(tile_nt_max<N>()) void k_zfwd_cg(T* __restrict__ x,
         }
         dv[e] = v[u];
       } else if constexpr (MODE == ZF_FIRST) {
+        const T shift = T(scal[9] * (-1.0 / ((double)N * N * N)));
 #pragma unroll
-        for (int c = 0; c < VEC; ++c) rr += (double)v[u].a[c] * (double)v[u].a[c];
+        for (int c = 0; c < VEC; ++c) {
+          v[u].a[c] += shift;
+          rr += (double)v[u].a[c] * (double)v[u].a[c];
+        }
+        V16<T> zero;
+#pragma unroll
+        for (int c = 0; c < VEC; ++c) zero.a[c] = T(0);
+        reinterpret_cast<V16<T>*>(r + a.base)[e] = v[u];
         reinterpret_cast<V16<T>*>(d + a.base)[e] = v[u];
+        reinterpret_cast<V16<T>*>(x + a.base)[e] = zero;
       }
     }
   }
@@ -1474,11 +1484,11 @@ __global__ __launch_bounds__(EW_NT) void k_reduce(const double* __restrict__ par
   partials = wb(partials, bt);
   scal = wb(scal, bt);
   out = wb(out, bt);
-  double acc[3] = {0, 0, 0};
+  double acc[4] = {0, 0, 0, 0};
   for (int i = threadIdx.x; i < nparts; i += EW_NT)
     for (int c = 0; c < nper; ++c) acc[c] += partials[(int64_t)i * nper + c];
-  double tot[3];
-  for (int c = 0; c < 3; ++c) tot[c] = block_sum(c < nper ? acc[c] : 0.0, red);
+  double tot[4];
+  for (int c = 0; c < 4; ++c) tot[c] = block_sum(c < nper ? acc[c] : 0.0, red);
   if (threadIdx.x == 0) {
     if (op == R_RESNORM || op == R_RESNORM0) {
       // |r_u|^2 + |r_p - mean r_p|^2 (Stokes: the pressure equation is taken modulo constants);
@@ -1490,10 +1500,11 @@ __global__ __launch_bounds__(EW_NT) void k_reduce(const double* __restrict__ par
         __threadfence_system();
       }
     } else {
+      const double v = (op == R_SUM1) ? tot[1] : tot[0];
       if (out)
-        *out = tot[0];
+        *out = v;
       else
-        scal[5] = tot[0];
+        scal[5] = v;
     }
   }
 }
