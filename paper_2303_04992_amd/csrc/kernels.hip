@@ -325,9 +325,36 @@ __global__ __launch_bounds__(tile_nt_max<N>()) __attribute__((amdgpu_waves_per_e
   using O = OutItems<T, N, KIND>;
   constexpr int W = S::W, NT = S::NT;
   const TileAddr a = tile_addr<W, N>(axis, blockIdx.x);
+  // forward kinds: the tables are requested before the samples and read from LDS (TabStage)
+  using TS = TabStage<T, N, KIND>;
+  constexpr bool STAGE = (KIND == DCT2 || KIND == DST2 || KIND == DST1) && TS::ON;
+  TS ts;
+  if constexpr (STAGE) ts.request(tb);
+  Tab<T> tl = tb;
   if (axis == 2) {
-    load_tile_z<T, N, NT>(lds, in + a.base);
-    fft_tile<T, N, KIND>(lds, LdsSrc<T, N>{lds}, tb);
+    if constexpr (STAGE) {
+      constexpr int VEC = V16<T>::n, NV = W * N / VEC, PV = (NV + NT - 1) / NT;
+      V16<T> v[PV];
+#pragma unroll
+      for (int u = 0; u < PV; ++u) {
+        const int e = threadIdx.x + u * NT;
+        if (NV % NT == 0 || e < NV) v[u] = reinterpret_cast<const V16<T>*>(in + a.base)[e];
+      }
+      tl = ts.publish(smem, tb);
+#pragma unroll
+      for (int u = 0; u < PV; ++u) {
+        const int e = threadIdx.x + u * NT;
+        if (NV % NT == 0 || e < NV) {
+          const int p = (e * VEC) / N, n = (e * VEC) - p * N;
+#pragma unroll
+          for (int q = 0; q < VEC; ++q) lds[p * (N + 1) + n + q] = v[u].a[q];
+        }
+      }
+      __syncthreads();
+    } else {
+      load_tile_z<T, N, NT>(lds, in + a.base);
+    }
+    fft_tile<T, N, KIND>(lds, LdsSrc<T, N>{lds}, tl);
     V16<T>* o = reinterpret_cast<V16<T>*>(out + a.base);
     constexpr int RV = N / O::VEC;  // vectors per pencil
     V16<T> old[ACC ? 2 * O::PER_Z : 1];
@@ -346,7 +373,7 @@ __global__ __launch_bounds__(tile_nt_max<N>()) __attribute__((amdgpu_waves_per_e
       int j, k0;
       if (O::z(u, j, k0)) {
         V16<T> v0, v1;
-        O::z_values(lds, tb, j, k0, v0, v1);
+        O::z_values(lds, tl, j, k0, v0, v1);
         if constexpr (ACC) {
 #pragma unroll
           for (int q = 0; q < O::VEC; ++q) {
@@ -359,7 +386,16 @@ __global__ __launch_bounds__(tile_nt_max<N>()) __attribute__((amdgpu_waves_per_e
       }
     }
   } else {
-    fft_tile<T, N, KIND>(lds, GlobSrc<T>{in, a.base, a.nstride}, tb);
+    const GlobSrc<T> src{in, a.base, a.nstride};
+    if constexpr (STAGE) {
+      C2<T> z[S::PT1][S::R1];
+      fft_gather<T, N, KIND>([&](int j, int n) { return pre_sample<T, N, KIND>(src, tb, j, n); }, z);
+      tl = ts.publish(smem, tb);
+      __syncthreads();
+      fft_core_from<T, N, KIND>(lds, z, tl);
+    } else {
+      fft_tile<T, N, KIND>(lds, src, tb);
+    }
     C2<T>* o = reinterpret_cast<C2<T>*>(out + a.base);
     const long ns = a.nstride / 2;  // in units of element pairs
     C2<T> old[ACC ? O::PER_XY : 1];
@@ -375,7 +411,7 @@ __global__ __launch_bounds__(tile_nt_max<N>()) __attribute__((amdgpu_waves_per_e
       int j, k;
       if (O::xy(u, j, k)) {
         C2<T> v;
-        post_pair<T, N, KIND>(lds, tb, j, k, v.x, v.y);
+        post_pair<T, N, KIND>(lds, tl, j, k, v.x, v.y);
         if constexpr (ACC) {
           v.x += old[u].x;
           v.y += old[u].y;
@@ -2057,7 +2093,7 @@ static void ensure_lds(K kernel, size_t bytes) {
 template <typename T, int N, int KIND, bool ACC>
 static hipError_t pass_n(int axis, const T* in, T* out, const Tab<T>& tb, hipStream_t s, const Bat& bt) {
   using S = TileCfg<T, N, KIND>;
-  const size_t lds = S::BYTES;
+  const size_t lds = TabStage<T, N, KIND>::BYTES;  // (S::BYTES where the table stage is off)
   const int blocks = N * N / S::W;
   // the inverse kinds read two samples per FFT input, which the staged tile serves from LDS;
   // for the forward kinds the direct gather measured faster
