@@ -825,6 +825,23 @@ __device__ __forceinline__ void store_xy_outputs(const T* lds, const Tab<T>& tb,
 // The forward outputs go to registers, are weighted (and fh read or written), and the tile
 // is restaged in LDS for the inverse.
 // ---------------------------------------------------------------------------------------
+// LDS of the fused x passes of the right-hand side and the back-substitution: the transform
+// work area, then (float32, where the resident blocks per compute unit stay the same) the
+// tables read between the transforms: the twiddles of the two kinds (one table when their
+// lengths agree), mk and the x eigenvalues of the component.
+template <typename T, int N, int KF, int KI>
+struct XfuseLds {
+  using SF = TileCfg<T, N, KF>;
+  using SI = TileCfg<T, N, KI>;
+  static constexpr size_t WORK = SF::BYTES > SI::BYTES ? SF::BYTES : SI::BYTES;
+  static constexpr size_t TAB_OFF = (WORK + 15) / 16 * 16;
+  static constexpr bool SHARE = SF::L == SI::L;
+  static constexpr int NTW = SF::L + (SHARE ? 0 : SI::L);
+  static constexpr size_t TAB_BYTES = TAB_OFF + (size_t)(NTW + N) * sizeof(C2<T>) + (size_t)N * sizeof(T);
+  static constexpr bool ON = sizeof(T) == 4 && 163840 / TAB_BYTES >= 163840 / WORK;
+  static constexpr size_t BYTES = ON ? TAB_BYTES : WORK;
+};
+
 template <typename T, int N, int KF, int KI, bool BACKSUB>
 __global__ __launch_bounds__(tile_nt_max<N>()) __attribute__((amdgpu_waves_per_eu(xfuse_waves<T, N>()))) void k_xfuse(const T* __restrict__ in, T* __restrict__ fh, T* __restrict__ out,
                                               int m, double mu, Tab<T> tb, Bat bt) {
@@ -835,11 +852,64 @@ __global__ __launch_bounds__(tile_nt_max<N>()) __attribute__((amdgpu_waves_per_e
   out = wb(out, bt);
   T* lds = reinterpret_cast<T*>(smem);
   using SF = TileCfg<T, N, KF>;
+  using SI = TileCfg<T, N, KI>;
   using OF = OutItems<T, N, KF>;
-  static_assert(SF::W == TileCfg<T, N, KI>::W, "one tile for both transforms");
-  constexpr int W = SF::W, RS = N + 1;
+  using X = XfuseLds<T, N, KF, KI>;
+  static_assert(SF::W == SI::W, "one tile for both transforms");
+  static_assert(KF == DCT2 || KF == DST2 || KF == DST1, "the forward kind gathers without tables");
+  constexpr int W = SF::W, RS = N + 1, NT = SF::NT;
   const TileAddr a = tile_addr<W, N>(0, blockIdx.x);
-  const int yi = blockIdx.x / (N / W), z0 = (blockIdx.x % (N / W)) * W;
+  const int yi = blockIdx.x / (N / W), z0 = (blockIdx.x % (N / W)) * W, j0 = threadIdx.x % SF::NJ;
+  // sigma_m^2 / Lambda_m parts: y and z eigenvalues of the thread's pencils (z indices z0 + 2 j0,
+  // z0 + 2 j0 + 1, the same for all its outputs), and sigma_m where m is not x; the index along
+  // m is mode k of the DCT-II / DST-I, along the other axes mode k + 1 of the DST-II
+  // (read before the samples where the tables go to LDS, after the transform otherwise, which
+  // keeps them out of the float64 kernels' register peak)
+  const T* gx = (m == 0) ? tb.sg2 : tb.sg2s;
+  T ly, lz[2], sgc[2];
+  auto load_parts = [&]() {
+    ly = (m == 1) ? tb.sg2[yi] : tb.sg2s[yi];
+#pragma unroll
+    for (int w = 0; w < 2; ++w) {
+      const int iz = z0 + 2 * j0 + w;
+      lz[w] = (m == 2) ? tb.sg2[iz] : tb.sg2s[iz];
+      const T sq = (m == 1) ? tb.sg2[yi] : (m == 2) ? tb.sg2[iz] : T(1);
+      if constexpr (sizeof(T) == 4)
+        sgc[w] = __builtin_sqrtf(sq);
+      else
+        sgc[w] = sqrt(sq);
+    }
+  };
+  if constexpr (X::ON) load_parts();
+  // tables requested before the samples (published to LDS once they have arrived)
+  constexpr int PLF = X::ON ? (SF::L + NT - 1) / NT : 1, PLI = (X::ON && !X::SHARE) ? (SI::L + NT - 1) / NT : 1;
+  constexpr int PN = X::ON ? (N + NT - 1) / NT : 1;
+  C2<T> rtf[PLF], rti[PLI], rmk[PN];
+  T rgx[PN];
+  const C2<T>* gtf = (SF::L == N) ? tb.tw : tb.tw2;
+  const C2<T>* gti = (SI::L == N) ? tb.tw : tb.tw2;
+  if constexpr (X::ON) {
+#pragma unroll
+    for (int u = 0; u < PLF; ++u) {
+      const int i = threadIdx.x + u * NT;
+      if (i < SF::L) rtf[u] = gtf[i];
+    }
+    if constexpr (!X::SHARE) {
+#pragma unroll
+      for (int u = 0; u < PLI; ++u) {
+        const int i = threadIdx.x + u * NT;
+        if (i < SI::L) rti[u] = gti[i];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < PN; ++u) {
+      const int i = threadIdx.x + u * NT;
+      if (i < N) {
+        rmk[u] = tb.mk[i];
+        rgx[u] = gx[i];
+      }
+    }
+  }
   C2<T>* fp = reinterpret_cast<C2<T>*>(fh + a.base);
   const long ns = a.nstride / 2;
   C2<T> f[BACKSUB ? OF::PER_XY : 1];
@@ -850,31 +920,63 @@ __global__ __launch_bounds__(tile_nt_max<N>()) __attribute__((amdgpu_waves_per_e
       if (OF::xy(u, j, k)) f[u] = fp[k * ns + j];
     }
   }
-  fft_tile<T, N, KF>(lds, GlobSrc<T>{in, a.base, a.nstride}, tb);
+  const GlobSrc<T> src{in, a.base, a.nstride};
+  Tab<T> tl = tb;
+  const T* lgx = gx;
+  if constexpr (X::ON) {
+    C2<T> z[SF::PT1][SF::R1];
+    fft_gather<T, N, KF>([&](int j, int n) { return pre_sample<T, N, KF>(src, tb, j, n); }, z);
+    C2<T>* ltf = reinterpret_cast<C2<T>*>(smem + X::TAB_OFF);
+    C2<T>* lti = X::SHARE ? ltf : ltf + SF::L;
+    C2<T>* lmk = ltf + X::NTW;
+    T* lg = reinterpret_cast<T*>(lmk + N);
+#pragma unroll
+    for (int u = 0; u < PLF; ++u) {
+      const int i = threadIdx.x + u * NT;
+      if (i < SF::L) ltf[i] = rtf[u];
+    }
+    if constexpr (!X::SHARE) {
+#pragma unroll
+      for (int u = 0; u < PLI; ++u) {
+        const int i = threadIdx.x + u * NT;
+        if (i < SI::L) lti[i] = rti[u];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < PN; ++u) {
+      const int i = threadIdx.x + u * NT;
+      if (i < N) {
+        lmk[i] = rmk[u];
+        lg[i] = rgx[u];
+      }
+    }
+    if (SF::L == N) tl.tw = ltf; else tl.tw2 = ltf;
+    if (SI::L == N) tl.tw = lti; else tl.tw2 = lti;
+    tl.mk = lmk;
+    lgx = lg;
+    __syncthreads();
+    fft_core_from<T, N, KF>(lds, z, tl);
+  } else {
+    fft_tile<T, N, KF>(lds, src, tb);
+    load_parts();
+  }
   C2<T> v[OF::PER_XY];
 #pragma unroll
   for (int u = 0; u < OF::PER_XY; ++u) {
     int j, k;
     if (OF::xy(u, j, k)) {
-      post_pair<T, N, KF>(lds, tb, j, k, v[u].x, v[u].y);
-      // sigma_m and 1 / (mu Lambda_m) of the two pencils (z indices z0 + 2j, z0 + 2j + 1); the
-      // index along m is mode k of the DCT-II / DST-I, along the other axes mode k + 1 of DST-II
+      post_pair<T, N, KF>(lds, tl, j, k, v[u].x, v[u].y);
+      // sigma_m and 1 / (mu Lambda_m) of the two pencils
+      const T lx = lgx[k];
       T sg[2], il[2];
-      const int id[3] = {k, yi, z0 + 2 * j};
 #pragma unroll
       for (int w = 0; w < 2; ++w) {
-        T lam = T(0);
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-          const int i = id[d] + (d == 2 ? w : 0);
-          lam += (d == m) ? tb.sg2[i] : tb.sg2s[i];
-        }
-        const int im = (m == 2) ? id[2] + w : id[m];
+        const T lam = lx + ly + lz[w];
         if constexpr (sizeof(T) == 4) {
-          sg[w] = __builtin_sqrtf(tb.sg2[im]);
+          sg[w] = (m == 0) ? __builtin_sqrtf(lx) : sgc[w];
           il[w] = __builtin_amdgcn_rcpf(T(mu) * lam);  // 1 ulp: the float32 inner solve
         } else {
-          sg[w] = sqrt(tb.sg2[im]);
+          sg[w] = (m == 0) ? sqrt(lx) : sgc[w];
           il[w] = T(1) / (T(mu) * lam);
         }
       }
@@ -898,8 +1000,8 @@ __global__ __launch_bounds__(tile_nt_max<N>()) __attribute__((amdgpu_waves_per_e
     }
   }
   __syncthreads();
-  fft_tile<T, N, KI>(lds, LdsSrc<T, N>{lds}, tb);
-  store_xy_outputs<T, N, KI>(lds, tb, out + a.base, a.nstride);
+  fft_tile<T, N, KI>(lds, LdsSrc<T, N>{lds}, tl);
+  store_xy_outputs<T, N, KI>(lds, tl, out + a.base, a.nstride);
 }
 
 // one tile per block (two tiles per block, with the second tile's samples requested before the
@@ -2211,7 +2313,7 @@ static hipError_t xfuse_n(int m, const T* in, T* fh, T* out, double mu, const De
                           const Bat& bt) {
   using SF = TileCfg<T, N, KF>;
   using SI = TileCfg<T, N, KI>;
-  const size_t lds = SF::BYTES > SI::BYTES ? SF::BYTES : SI::BYTES;
+  const size_t lds = XfuseLds<T, N, KF, KI>::BYTES;
   const int nt = SF::NT > SI::NT ? SF::NT : SI::NT;
   const int blocks = N * N / SF::W;
   ensure_lds(k_xfuse<T, N, KF, KI, BS>, lds);
