@@ -490,6 +490,10 @@ struct MacSolver {
     auto nan_check = [&](double v) {
       if (std::isnan(v)) throw DevErr{"NaN in the Schur CG residual"};
     };
+    // Without a mean projection between the solve and the back-substitution (mean_free false,
+    // c = 0), the pending x += alpha d of a finished right-hand side is left to the first pass
+    // of the back-substitution (its x, d and alpha stay untouched: later iterations skip it).
+    const bool defer_final = !mean_free && c == 0;
     auto finish = [&](int rr) {  // right-hand side rr has converged: its pending update, and out
       done[rr] = 1;
       ++ndone;
@@ -498,8 +502,10 @@ struct MacSolver {
       Bat one = bt;
       one.nb = 1;
       one.act = nullptr;
-      HIPCHK(launch_axpy_scal<T>(M, at(x, rr), at(d, rr), at(scal, rr), 1, s, one));  // x += alpha d
-      bytes += 3.0 * M * sizeof(T);
+      if (!defer_final) {
+        HIPCHK(launch_axpy_scal<T>(M, at(x, rr), at(d, rr), at(scal, rr), 1, s, one));  // x += alpha d
+        bytes += 3.0 * M * sizeof(T);
+      }
       if (NB > 1) HIPCHK(launch_fill<int>(1, act_cg + rr, 0, s));
     };
     while (ndone < NB && it < maxit) {
@@ -560,7 +566,12 @@ struct MacSolver {
     // z and y shared as in the matvec, then per component the fused x pass and the y, z inverses
     // A = DST_z p, B = DCT_z p
     mark(ST_BACKSUB);
-    HIPCHK(launch_zfwd_cg<T>(N, ZF_PLAIN, nullptr, x, nullptr, nullptr, A, B, nullptr, nullptr, tb, s, cur));
+    if (defer_final) {  // x += alpha d, written back, and its transforms
+      HIPCHK(launch_zfwd_cg<T>(N, ZF_FINAL, nullptr, x, d, nullptr, A, B, scal, nullptr, tb, s, cur));
+      count(2);
+    } else {
+      HIPCHK(launch_zfwd_cg<T>(N, ZF_PLAIN, nullptr, x, nullptr, nullptr, A, B, nullptr, nullptr, tb, s, cur));
+    }
     if (sizeof(T) == 4) pass(DST2, 1, B, B3);                         // C_2 along y (order as in the matvec)
     HIPCHK(launch_ypair<T>(N, false, A, A, A1, B2, tb, s, cur));     // C_0, C_1 along y
     count(3 + 3);

@@ -56,7 +56,8 @@ hipError_t launch_xmid(int N, T* A0, T* A1, T* A2, double mu, const DevTables<T>
 //   ZF_FUSED  x += alpha d; r -= alpha (q - mean q); d = r + beta d (scal[1], scal[2], scal[3]);
 //             v = d; rpart[block] = partial r.r of the updated r
 // rpart holds zfwd_blocks(N, sizeof(T)) doubles.
-enum ZfwdMode { ZF_PLAIN = 0, ZF_FIRST = 1, ZF_FUSED = 2 };
+//   ZF_FINAL  r += scal[1] d (written back), v = r
+enum ZfwdMode { ZF_PLAIN = 0, ZF_FIRST = 1, ZF_FUSED = 2, ZF_FINAL = 3 };
 template <typename T>
 hipError_t launch_zfwd_cg(int N, int mode, T* x, T* r, T* d, const T* q, T* A, T* B, const double* scal,
                           double* rpart, const DevTables<T>& tb, hipStream_t s, const Bat& bt = Bat());

@@ -1129,6 +1129,8 @@ __device__ __forceinline__ void store_z_outputs(const T* lds, const Tab<T>& tb, 
 //             d; partial sums of r.r
 //   ZF_FUSED  x += alpha d, r -= alpha (q - mean q), d = r + beta d (alpha, beta, mean q of the
 //             previous iteration in scal[1..3]), then the transforms of d; partial sums of r.r
+//   ZF_FINAL  r += alpha d (the pending update of the CG iterate, r = x), written back, then its
+//             transforms (velocity back-substitution)
 // Every thread streams its vectors once; d stays in registers for the second transform.
 template <typename T, int N, int MODE>
 __global__ __launch_bounds__(tile_nt_max<N>()) void k_zfwd_cg(T* __restrict__ x, T* __restrict__ r, T* __restrict__ d,
@@ -1181,6 +1183,12 @@ __global__ __launch_bounds__(tile_nt_max<N>()) void k_zfwd_cg(T* __restrict__ x,
           v[u].a[c] += beta * dold.a[c];
         }
         dv[e] = v[u];
+      } else if constexpr (MODE == ZF_FINAL) {
+        const T alpha = T(scal[1]);
+        const V16<T> dv = reinterpret_cast<const V16<T>*>(d + a.base)[e];
+#pragma unroll
+        for (int c = 0; c < VEC; ++c) v[u].a[c] += alpha * dv.a[c];
+        reinterpret_cast<V16<T>*>(r + a.base)[e] = v[u];
       } else if constexpr (MODE == ZF_FIRST) {
         const T shift = T(scal[9] * (-1.0 / ((double)N * N * N)));
 #pragma unroll
@@ -1198,7 +1206,7 @@ __global__ __launch_bounds__(tile_nt_max<N>()) void k_zfwd_cg(T* __restrict__ x,
     }
   }
   const Tab<T> tb = ts.publish(smem, tg);  // read after the first stage's barrier
-  if constexpr (MODE != ZF_PLAIN) {
+  if constexpr (MODE == ZF_FIRST || MODE == ZF_FUSED) {
     const double t = block_sum(rr, red);
     if (threadIdx.x == 0) rpart[blockIdx.x] = t;
   }
@@ -2278,6 +2286,8 @@ hipError_t launch_zfwd_cg(int N, int mode, T* x, T* r, T* d, const T* q, T* A, T
       KFBI_ZF(NN, ZF_FUSED)   \
     else if (mode == ZF_FIRST) \
       KFBI_ZF(NN, ZF_FIRST)   \
+    else if (mode == ZF_FINAL) \
+      KFBI_ZF(NN, ZF_FINAL)   \
     else                      \
       KFBI_ZF(NN, ZF_PLAIN)   \
   }
