@@ -321,6 +321,18 @@ struct MacSolver {
     timed(kind == prof_kind && (prof_axis < 0 || axis == prof_axis) && !acc,
           [&] { return launch_pass<T>(N, kind, axis, in, out, acc, tb, s, cur); });
   }
+  // Sparse right-hand side (set by the caller for one solve, else null): component m of Fu is
+  // zero outside the z-pencils flagged with bit m in sp_pmask (sp_xmask: or over y); sp_zread[m],
+  // sp_yread[m]: the shares of the z and y tiles of component m that hold such a pencil
+  const uint8_t* sp_pmask = nullptr;
+  const uint8_t* sp_xmask = nullptr;
+  double sp_zread[3] = {1, 1, 1}, sp_yread[3] = {1, 1, 1};
+  void pass_sparse(int kind, int axis, const T* in, T* out, int m) {
+    const double share = !sp_pmask ? 1.0 : axis == 2 ? sp_zread[m] : sp_yread[m];
+    count(1 + share);  // the tiles read, and every tile written
+    timed(kind == prof_kind && (prof_axis < 0 || axis == prof_axis),
+          [&] { return launch_pass<T>(N, kind, axis, in, out, false, tb, s, cur, sp_pmask, sp_xmask, m); });
+  }
   // algorithmic HBM bytes of one launch of kernel id (one read and one write per field touched)
   double kernel_bytes(int id) const {
     const double f = (double)M * sizeof(T);
@@ -446,8 +458,8 @@ struct MacSolver {
     T* H[3] = {A1, B2, B3};
     mark(ST_RHS);
     for (int m = 0; m < 3; ++m) {
-      pass(m == 2 ? DST1 : DST2, 2, Fu + m * M, Fh[m]);
-      pass(m == 1 ? DST1 : DST2, 1, Fh[m], Fh[m]);
+      pass_sparse(m == 2 ? DST1 : DST2, 2, Fu + m * M, Fh[m], m);
+      pass_sparse(m == 1 ? DST1 : DST2, 1, Fh[m], Fh[m], m);
       HIPCHK(launch_xfuse<T>(N, m, false, Fh[m], Fh[m], H[m], mu, tb, s, cur));
       count(3);
     }
@@ -662,6 +674,8 @@ struct kfbi_ctx {
   // irregular nodes): the refinement passes read F only there
   uint8_t* fmask = nullptr;
   double fmask_frac = 1;  // share of the (pencil, component) pairs flagged
+  uint8_t* fxmask = nullptr;  // the flags or-ed over y, per plane x
+  double fz_share[2][3] = {}, fy_share[3] = {};  // tile shares (float32, float64 z tiles; planes)
   // pinned host scalars written by kernels and read after a later synchronisation (hflag: the
   // tag of the current call's input check if it saw a non-finite value), their device
   // addresses, and the stage clock of a call
@@ -786,6 +800,27 @@ kfbi_status kfbi_create(const kfbi_config* cfg_in, kfbi_ctx** out) {
       for (uint8_t v : fm) bits += __builtin_popcount(v);
       C->fmask_frac = (double)bits / (4.0 * (double)fm.size());
       C->fmask = dupload(fm, o, s);
+      // or over y of each plane x, and the shares of the z tiles (W pencils of one plane) and of
+      // the planes that hold a flagged pencil, per velocity component
+      std::vector<uint8_t> xm((size_t)S.N, 0);
+      for (int x = 0; x < S.N; ++x)
+        for (int y = 0; y < S.N; ++y) xm[x] |= fm[(size_t)x * S.N + y];
+      C->fxmask = dupload(xm, o, s);
+      for (int m = 0; m < 3; ++m) {
+        int64_t planes = 0;
+        for (uint8_t v : xm) planes += (v >> m) & 1;
+        C->fy_share[m] = (double)planes / S.N;
+        for (int wi = 0; wi < 2; ++wi) {
+          const int W = std::min(wi == 0 ? 32 : 16, S.N);  // float32, float64 tile widths
+          int64_t tiles = 0;
+          for (size_t t = 0; t < fm.size() / W; ++t) {
+            unsigned any = 0;
+            for (int p = 0; p < W; ++p) any |= fm[t * W + p];
+            tiles += (any >> m) & 1;
+          }
+          C->fz_share[wi][m] = (double)tiles / (double)(fm.size() / W);
+        }
+      }
     }
     C->irr_ptr = dupload(S.irr_ptr, o, s);
     C->arm_t = dupload(S.arm_t, o, s);
@@ -980,8 +1015,29 @@ int mac_solve(kfbi_ctx* C, const double* F, double* u, double* p, kfbi_info* inf
     for (int v : its) t += v;
     return t;
   };
+  // F zero outside the irregular nodes (the corrections alone): the right-hand-side transforms
+  // skip the tiles without any, and the refinement reads F only in their pencils
+  const bool f_sparse = F == C->F && C->f_clean;
+  auto sparse_rhs = [&](auto& sv, bool on) {
+    const int wi = sizeof(*sv.x) == 4 ? 0 : 1;
+    sv.sp_pmask = on ? C->fmask : nullptr;
+    sv.sp_xmask = on ? C->fxmask : nullptr;
+    for (int m = 0; m < 3; ++m) {
+      sv.sp_zread[m] = on ? C->fz_share[wi][m] : 1.0;
+      sv.sp_yread[m] = on ? C->fy_share[m] : 1.0;
+    }
+  };
+  struct SparseOff {  // no solver keeps the sparse flags past this call, exceptions included
+    kfbi_ctx* C;
+    ~SparseOff() {
+      C->s32.sp_pmask = C->s32.sp_xmask = nullptr;
+      C->s64.sp_pmask = C->s64.sp_xmask = nullptr;
+    }
+  } sparse_off{C};
   if (!C->mixed) {
+    sparse_rhs(C->s64, f_sparse);
     int it = C->s64.solve(F, F + 3 * M, u, p, C->cfg.cg_rtol, C->cfg.cg_maxit, nullptr, &its);
+    sparse_rhs(C->s64, false);
     if (it < 0) throw std::runtime_error("ENOCONV: Schur CG reached cg_maxit");
     if (info) {
       info->cg_iters += NB == 1 ? it : sum_its();
@@ -1023,7 +1079,7 @@ int mac_solve(kfbi_ctx* C, const double* F, double* u, double* p, kfbi_info* inf
   HIPCHK(launch_reduce(C->rpart, NP, 3, C->rscal, R_RESNORM0, stokes, M, s, nullptr, bt, hf0_dev));
   const double* shift = stokes ? C->rscal + 6 : nullptr;  // mean of F_p (Stokes)
   // F zero outside the irregular nodes (the corrections alone): read only in their pencils
-  const uint8_t* fm = (F == C->F && C->f_clean) ? C->fmask : nullptr;
+  const uint8_t* fm = f_sparse ? C->fmask : nullptr;
   const double fbytes = 32.0 * (fm ? C->fmask_frac : 1.0);  // F bytes read per cell
   // the iterate alternates between (u, p) and the spare float64 fields (neighbour values of
   // the old iterate are read while the new one is written); in_ru[r]: where right-hand side r
@@ -1038,8 +1094,10 @@ int mac_solve(kfbi_ctx* C, const double* F, double* u, double* p, kfbi_info* inf
     std::fill(its.begin(), its.end(), 0);
     // Stokes: the pressure correction enters the residual only through its gradient, and the
     // final pressure is projected after the rounds
+    sparse_rhs(C->s32, f_sparse && rounds == 0);  // the first round's right-hand side is F itself
     int it = C->s32.solve(rin, rin + 3 * M, C->x32, C->x32 + 3 * M, C->cfg.inner_rtol, C->cfg.cg_maxit, &live, &its,
                           !stokes);
+    sparse_rhs(C->s32, false);
     if (it < 0) throw std::runtime_error("ENOCONV: inner float32 CG reached cg_maxit");
     total += NB == 1 ? it : sum_its();
     double* nu = (rounds == 0 || cu != u) ? u : C->ru;

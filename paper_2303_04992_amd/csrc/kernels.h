@@ -42,9 +42,13 @@ struct DevTables {
 enum WeightKind { W_SCHUR = 0, W_RHS = 1 };
 
 // ---- transforms
+// pmask / xmask / mbit (optional, forward sparse inputs along axis 2 or 1): the input is zero
+// outside the z-pencils (x, y) with bit mbit of pmask[x N + y] set (xmask[x]: or over y); tiles
+// whose transform is then zero are written as zeros without being read
 template <typename T>
 hipError_t launch_pass(int N, int kind, int axis, const T* in, T* out, bool accumulate, const DevTables<T>& tb,
-                       hipStream_t s, const Bat& bt = Bat());
+                       hipStream_t s, const Bat& bt = Bat(), const uint8_t* pmask = nullptr,
+                       const uint8_t* xmask = nullptr, int mbit = -1);
 // fused x-pass of the Schur operator for the three components (fwd x, weight, inverse x)
 template <typename T>
 hipError_t launch_xmid(int N, T* A0, T* A1, T* A2, double mu, const DevTables<T>& tb, hipStream_t s,

@@ -314,8 +314,15 @@ static int persistent_blocks(K kernel, int threads, size_t lds_bytes, int ntiles
 // generic transform pass: out (+)= transform_KIND(in) along axis
 // ---------------------------------------------------------------------------------------
 // (in may equal out: a block reads its whole tile before it writes any output)
+// pmask (may be null; axes 1 and 2 only): the input is zero outside the z-pencils (x, y) whose
+// byte pmask[x N + y] has bit mbit set (xmask[x]: the same bits or-ed over y).  A tile without
+// such a pencil (axis 2), or of a plane x without one (axis 1: after the z transform a flagged
+// pencil fills its whole plane), has a zero transform: it is written as zeros (or, accumulating,
+// left as it is) without being read.
 template <typename T, int N, int KIND, bool ACC>
-__global__ __launch_bounds__(tile_nt_max<N>()) __attribute__((amdgpu_waves_per_eu(tile_waves<T, N>()))) void k_pass(const T* in, T* out, int axis, Tab<T> tb, Bat bt) {
+__global__ __launch_bounds__(tile_nt_max<N>()) __attribute__((amdgpu_waves_per_eu(tile_waves<T, N>()))) void k_pass(const T* in, T* out, int axis, Tab<T> tb, Bat bt,
+                                                const uint8_t* __restrict__ pmask, const uint8_t* __restrict__ xmask,
+                                                int mbit) {
   extern __shared__ __align__(16) unsigned char smem[];
   if (rhs_skipped(bt)) return;
   in = wb(in, bt);
@@ -325,6 +332,31 @@ __global__ __launch_bounds__(tile_nt_max<N>()) __attribute__((amdgpu_waves_per_e
   using O = OutItems<T, N, KIND>;
   constexpr int W = S::W, NT = S::NT;
   const TileAddr a = tile_addr<W, N>(axis, blockIdx.x);
+  if (pmask && axis != 0) {
+    unsigned any = 0;
+    if (axis == 2) {
+#pragma unroll
+      for (int p = 0; p < W; ++p) any |= pmask[(int64_t)blockIdx.x * W + p];
+    } else {
+      any = xmask[blockIdx.x / (N / W)];
+    }
+    if (!((any >> mbit) & 1u)) {
+      if constexpr (!ACC) {
+        if (axis == 2) {
+          constexpr int NV = W * N / V16<T>::n;
+          V16<T> zero;
+#pragma unroll
+          for (int q = 0; q < V16<T>::n; ++q) zero.a[q] = T(0);
+          for (int e = threadIdx.x; e < NV; e += blockDim.x) reinterpret_cast<V16<T>*>(out + a.base)[e] = zero;
+        } else {
+          C2<T>* o = reinterpret_cast<C2<T>*>(out + a.base);
+          const long ns = a.nstride / 2;
+          for (int e = threadIdx.x; e < N * S::NJ; e += blockDim.x) o[(e / S::NJ) * ns + e % S::NJ] = C2<T>{T(0), T(0)};
+        }
+      }
+      return;
+    }
+  }
   // forward kinds: the tables are requested before the samples and read from LDS (TabStage)
   using TS = TabStage<T, N, KIND>;
   constexpr bool STAGE = (KIND == DCT2 || KIND == DST2 || KIND == DST1) && TS::ON;
@@ -2201,7 +2233,8 @@ static void ensure_lds(K kernel, size_t bytes) {
   }
 
 template <typename T, int N, int KIND, bool ACC>
-static hipError_t pass_n(int axis, const T* in, T* out, const Tab<T>& tb, hipStream_t s, const Bat& bt) {
+static hipError_t pass_n(int axis, const T* in, T* out, const Tab<T>& tb, hipStream_t s, const Bat& bt,
+                         const uint8_t* pmask, const uint8_t* xmask, int mbit) {
   using S = TileCfg<T, N, KIND>;
   const size_t lds = TabStage<T, N, KIND>::BYTES;  // (S::BYTES where the table stage is off)
   const int blocks = N * N / S::W;
@@ -2219,16 +2252,18 @@ static hipError_t pass_n(int axis, const T* in, T* out, const Tab<T>& tb, hipStr
     }
   }
   ensure_lds(k_pass<T, N, KIND, ACC>, lds);
-  hipLaunchKernelGGL((k_pass<T, N, KIND, ACC>), dim3(blocks, 1, bt.nb), dim3(S::NT), lds, s, in, out, axis, tb, bt);
+  hipLaunchKernelGGL((k_pass<T, N, KIND, ACC>), dim3(blocks, 1, bt.nb), dim3(S::NT), lds, s, in, out, axis, tb, bt,
+                     pmask, xmask, mbit);
   return hipGetLastError();
 }
 
 template <typename T, int N>
 static hipError_t pass_kind(int kind, int axis, const T* in, T* out, bool acc, const Tab<T>& tb, hipStream_t s,
-                            const Bat& bt) {
-#define KFBI_K(KD)                                                                            \
-  case KD:                                                                                    \
-    return acc ? pass_n<T, N, KD, true>(axis, in, out, tb, s, bt) : pass_n<T, N, KD, false>(axis, in, out, tb, s, bt);
+                            const Bat& bt, const uint8_t* pm, const uint8_t* xm, int mbit) {
+#define KFBI_K(KD)                                                                                          \
+  case KD:                                                                                                  \
+    return acc ? pass_n<T, N, KD, true>(axis, in, out, tb, s, bt, pm, xm, mbit)                             \
+               : pass_n<T, N, KD, false>(axis, in, out, tb, s, bt, pm, xm, mbit);
   switch (kind) {
     KFBI_K(DCT2)
     KFBI_K(DST2)
@@ -2242,9 +2277,10 @@ static hipError_t pass_kind(int kind, int axis, const T* in, T* out, bool acc, c
 
 template <typename T>
 hipError_t launch_pass(int N, int kind, int axis, const T* in, T* out, bool accumulate, const DevTables<T>& tb,
-                       hipStream_t s, const Bat& bt) {
+                       hipStream_t s, const Bat& bt, const uint8_t* pmask, const uint8_t* xmask, int mbit) {
+  if (pmask && (!xmask || mbit < 0 || mbit > 7)) return hipErrorInvalidValue;
   const Tab<T> t = tab_of(tb);
-#define KFBI_M(NN) return pass_kind<T, NN>(kind, axis, in, out, accumulate, t, s, bt)
+#define KFBI_M(NN) return pass_kind<T, NN>(kind, axis, in, out, accumulate, t, s, bt, pmask, xmask, mbit)
   KFBI_DISPATCH_N(N, KFBI_M)
 #undef KFBI_M
   return hipErrorInvalidValue;
@@ -2555,7 +2591,7 @@ hipError_t launch_check_finite(int64_t n, const double* a, int* flag, int tag, h
 // explicit instantiations
 #define KFBI_INST(T)                                                                                                 \
   template hipError_t launch_pass<T>(int, int, int, const T*, T*, bool, const DevTables<T>&, hipStream_t,          \
-                                     const Bat&);                                                                    \
+                                     const Bat&, const uint8_t*, const uint8_t*, int);                               \
   template hipError_t launch_xmid<T>(int, T*, T*, T*, double, const DevTables<T>&, hipStream_t, const Bat&);         \
   template hipError_t launch_zfwd_cg<T>(int, int, T*, T*, T*, const T*, T*, T*, const double*, double*,               \
                                         const DevTables<T>&, hipStream_t, const Bat&);                               \
