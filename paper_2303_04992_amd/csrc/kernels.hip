@@ -680,7 +680,7 @@ __device__ void xmid_tile_regs(T* lds, T* field, int tile, int mc, double mu, co
   using O = OutItems<T, N, KI>;
   C2<T>* o = reinterpret_cast<C2<T>*>(field + a.base);
   const long ns = a.nstride / 2;
-#pragma unroll 4
+#pragma unroll
   for (int u = 0; u < O::PER_XY; ++u) {
     int jj, k;
     if (O::xy(u, jj, k)) {
@@ -822,7 +822,7 @@ __device__ __forceinline__ void xmid_tile_regs3(T* lds, T* field, int tile, int 
   using O = OutItems<T, N, KI>;
   C2<T>* o = reinterpret_cast<C2<T>*>(field + a.base);
   const long ns = a.nstride / 2;
-#pragma unroll 4
+#pragma unroll
   for (int u = 0; u < O::PER_XY; ++u) {
     int jj, k;
     if (O::xy(u, jj, k)) {
@@ -838,7 +838,9 @@ __device__ __forceinline__ void store_xy_outputs(const T* lds, const Tab<T>& tb,
   using O = OutItems<T, N, KIND>;
   C2<T>* o = reinterpret_cast<C2<T>*>(out);
   const long ns = nstride / 2;
-#pragma unroll 4
+  // all outputs unrolled up to N = 256 (the pipelined forward y pair at 512 would spill)
+  constexpr int UNROLL = N >= 512 ? 4 : O::PER_XY;
+#pragma unroll UNROLL
   for (int u = 0; u < O::PER_XY; ++u) {
     int j, k;
     if (O::xy(u, j, k)) {
